@@ -1,0 +1,187 @@
+#!/usr/bin/env python3
+"""Benchmark of the randomized interpolative decomposition on one MI355X.
+
+A step is one whole ID through the C ABI (rid_decompose): Gaussian sketch
+Y = G A, pivoted QR of Y, P = [I T], and the power-iteration estimate of
+||A - A(:,J) P||_2 with q = 10 steps -- 1 + (2q - 1) = 2q passes over A.
+Workload: A = X W + 1e-12 N, complex128, m = 131072, n = 16384, k = 100,
+l = 108 (34.4 GB), X, W, N i.i.d. complex Gaussian, generated on the GPU
+before the timed region (synthetic stand-in for the Gaussian low-rank test
+matrices of arXiv 1205.3830, Sec. 3.3).
+
+Prints one JSON line: value = GB/s of A streamed (2q passes of A's bytes per
+ID), plus IDs/s, the roofline of the dominant kernel (event-timed inside the
+timed region), and the CPU oracle timed on a bounded column sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
+FP64_PEAK_TFS = 78.6         # MI355X FP64 matrix (dense)
+
+
+def _traffic(kernel_name: str, src_file: str):
+    """HBM bytes per launch from a committed counter summary, if it was
+    taken on the current kernel source (matching sha256); else None."""
+    path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(os.path.join(ROOT, "paper_1205_3830_amd", "csrc", src_file), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("source_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(A_dev, k, l, q, cols):
+    """The oracle, untuned, on columns [0, cols) of the same A."""
+    import numpy as np
+
+    import oracle
+    m = A_dev.shape[0]
+    Ah = A_dev[:, :cols].t().contiguous().cpu().numpy().T   # (m, cols), Fortran order
+    Ah = np.asfortranarray(Ah)
+    t0 = time.perf_counter()
+    r = oracle.decompose(Ah, k, l, seed=0, q=q)
+    dt = time.perf_counter() - t0
+    gbs = 2 * q * 16.0 * m * cols / dt / 1e9
+    return {"value": gbs, "unit": "GB/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "oracle.decompose on columns 0..%d of the same A (%d x %d complex128, "
+                      "%.0f MB), k=%d, l=%d, q=%d; %.1f s; status %d"
+                      % (cols - 1, m, cols, 16.0 * m * cols / 1e6, k, l, q, dt, r["status"]),
+            "seconds": dt}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--m", type=int, default=131072)
+    ap.add_argument("--n", type=int, default=16384)
+    ap.add_argument("--k", type=int, default=100)
+    ap.add_argument("--l", type=int, default=108)
+    ap.add_argument("--q", type=int, default=10)
+    ap.add_argument("--noise", type=float, default=1e-12)
+    ap.add_argument("--cpu-cols", type=int, default=128)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d, WORLD_SIZE %d requested)" % (args.gpus, world), file=sys.stderr)
+        return 2
+
+    import torch
+
+    import paper_1205_3830_amd as rid
+    import synth
+
+    m, n, k, l, q = args.m, args.n, args.k, args.l, args.q
+    torch.cuda.set_device(0)
+    print("generating A %d x %d complex128 on the GPU" % (m, n), file=sys.stderr, flush=True)
+    A = synth.lowrank_device(m, n, k, args.noise, seed=0).t()      # (m, n), stride (1, m)
+    torch.cuda.synchronize()
+    h = rid.rid_create(0)
+    rid.rid_reserve(h, m, n, l, k)
+    J = torch.empty(k, dtype=torch.int64, device="cuda")
+    P = torch.empty((n, k), dtype=torch.complex128, device="cuda").t()
+    sigma = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def step():
+        return rid.rid_decompose(h, A, k, l, seed=0, q=q, J=J, P=P, sigma=sigma)
+
+    for i in range(args.warmup):
+        step()
+        print("warmup %d done" % i, file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    rid.rid_profile(h, True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rid.rid_profile(h, False)
+    ms = (t1 - t0) * 1e3 / args.steps
+    bytes_a = 16.0 * m * n
+    passes = 2 * q
+    gbs = passes * bytes_a / (ms * 1e-3) / 1e9
+
+    kern = {}
+    for kid, name in rid.KERNEL_NAMES.items():
+        tot, cnt = rid.rid_profile_read(h, kid)
+        if cnt:
+            kern[name] = {"total_ms": tot, "launches": cnt, "avg_ms": tot / cnt}
+    rooflines = {}
+    for name, src in (("residual_ax", "residual.hip"), ("residual_ahz", "residual.hip")):
+        if name in kern:
+            avg = kern[name]["avg_ms"] * 1e-3
+            ach = bytes_a / avg / 1e9
+            rooflines[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                               "traffic": _traffic(name, src),
+                               "algorithmic_bytes_per_launch": bytes_a,
+                               "avg_launch_ms": kern[name]["avg_ms"]}
+    if "sketch" in kern:
+        avg = kern["sketch"]["avg_ms"] * 1e-3
+        ach = 8.0 * l * m * n / avg / 1e12
+        rooflines["sketch"] = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFS,
+                               "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFS,
+                               "traffic": _traffic("sketch", "sketch_f64.hip"),
+                               "algorithmic_flops_per_launch": 8.0 * l * m * n,
+                               "avg_launch_ms": kern["sketch"]["avg_ms"]}
+    dominant = max(kern, key=lambda x: kern[x]["total_ms"]) if kern else None
+    roof = dict(rooflines.get(dominant, {}))
+    if roof:
+        roof["kernel"] = dominant
+
+    J_h = J.cpu()
+    ok = bool((P[:, J_h].cpu() == torch.eye(k, dtype=torch.complex128)).all())
+
+    out = {
+        "metric": "A GB/s streamed & IDs/sec at <=1e-10 rel err; p50/p99 latency vs plain FP64",
+        "value": gbs,
+        "unit": "GB/s",
+        "ids_per_s": 1e3 / ms,
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "plain FP64 randomized ID, A = X W + %g N complex128, "
+                               "%d x %d, k=%d, l=%d, q=%d power steps (%d passes over A)"
+                               % (args.noise, m, n, k, l, q, passes),
+                   "m": m, "n": n, "k": k, "l": l, "q": q, "bytes_A": bytes_a},
+        "roofline": roof,
+        "kernels": kern,
+        "rooflines": rooflines,
+        "sigma": float(sigma.cpu()[0]),
+        "identity_on_J": ok,
+    }
+    if not args.no_cpu_baseline and args.cpu_cols > 0:
+        print("timing the CPU oracle on a column sample", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(A, k, l, q, min(args.cpu_cols, n))
+    rid.rid_destroy(h)
+    print(json.dumps(out))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,235 @@
+/*
+ * rid.h -- C ABI of librid, a randomized interpolative decomposition (ID) of
+ * complex matrices on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Lucas, Stalzer & Feo, "Parallel implementation of fast randomized
+ * algorithms for the decomposition of low rank matrices", arXiv 1205.3830.
+ * Given A (m x n, approximate rank k), find k columns B = A(:, J) and a
+ * k x n matrix P with A ~= B P (Sec. 2, problem statement).  The steps are
+ *   1. randomization  Y = G A with an l x m complex Gaussian G, l >= k
+ *      (Sec. 2 randomization step; the paper's own operator is a subsampled
+ *      FFT, and Sec. 2 allows a faster randomization in its place);
+ *   2. a QR factorization of Y with column pivoting, whose first k pivots
+ *      are the skeleton J (Sec. 2, approximate QR and column permutation);
+ *   3. P = [I T] with R2 = R1 T, written in the original column order
+ *      (Sec. 2, interpolation matrix);
+ *   4. the error ||A - A(:, J) P||_2 of Table 5, estimated by power iteration.
+ *
+ * Conventions for every entry point
+ *  - Matrices are column-major with a leading dimension ld >= rows, complex
+ *    stored as interleaved (re, im) pairs: complex128 = two doubles (the
+ *    layout of std::complex<double> and torch.complex128).  Exception: the
+ *    Gaussian operator G is stored by rows (entry (i, p) at G[i * ldg + p]).
+ *  - Indices are 0-based int64.
+ *  - Every data pointer is a DEVICE pointer owned by the caller, unless the
+ *    argument's comment says "host".  The library never frees caller memory
+ *    and never writes A.
+ *  - Calls are asynchronous on `stream` unless their comment says they
+ *    synchronise.  A handle serialises nothing by itself: calls on one handle
+ *    must be ordered by their streams (the handle's workspace is shared).
+ *  - Argument errors are reported synchronously, before anything is
+ *    launched, as RID_ERR_INVALID_ARG.  A failed HIP call is reported as
+ *    RID_ERR_HIP; rid_last_hip_error() returns the hipError_t.
+ *  - Numerical rank failure (rank(Y) < k, Sec. 2) is recorded in a device
+ *    status word of the handle by rid_pivqr; rid_query_status() reads it.
+ *    rid_decompose() reads it itself and redraws G with the next seed, as
+ *    Sec. 2 prescribes for this failure.
+ *  - Arithmetic: `RID_FP64` runs every step in double precision.  The QR,
+ *    the triangular solve and every norm and residual accumulation are
+ *    double (the residual sums are compensated, i.e. double-double) in every
+ *    precision mode; a lower `rid_prec` only changes the sketch product.
+ *  - Determinism: no floating-point atomics; a call repeated with the same
+ *    inputs on the same device gives bit-identical outputs.
+ */
+#ifndef RID_H
+#define RID_H
+
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct rid_ctx *rid_handle;
+
+typedef enum {
+  RID_OK = 0,
+  RID_ERR_INVALID_ARG = 1,
+  RID_ERR_UNSUPPORTED = 2,
+  RID_ERR_NOMEM = 3,
+  RID_ERR_HIP = 4,
+  RID_ERR_RANK = 5 /* rank(Y) < k at the QR step (Sec. 2 failure case) */
+} rid_status;
+
+/* Storage type of A. */
+typedef enum { RID_C128 = 0, RID_C64 = 1 } rid_dtype;
+
+/* Arithmetic of the sketch product Y = G A (Y itself is always complex128).
+ *   RID_FP64   double FMA (A must be RID_C128);
+ *   RID_FP32   single-precision products, single accumulation;
+ *   RID_BF16X3 each operand split into three bfloat16 terms, six bf16
+ *              products per real product, single accumulation.         */
+typedef enum { RID_FP64 = 0, RID_FP32 = 1, RID_BF16X3 = 2 } rid_prec;
+
+/* ---------------------------------------------------------------- handle */
+
+/* Create a handle bound to HIP device `device` (host out-pointer `h`).
+ * Allocates a small device status word; workspace is allocated on first use
+ * or by rid_reserve().  Errors: INVALID_ARG (null h, bad device), HIP.    */
+rid_status rid_create(rid_handle *h, int device);
+
+/* Free the handle and its workspace.  The caller must make sure no work
+ * that uses the handle is still running.  A null handle is a no-op.      */
+rid_status rid_destroy(rid_handle h);
+
+/* Static string naming a status code (never null). */
+const char *rid_status_string(int status);
+
+/* hipError_t of the last failed HIP call on this handle (0 if none). */
+int rid_last_hip_error(rid_handle h);
+
+/* Pre-size the workspace for every call with m <= max_m, n <= max_n,
+ * l <= max_l, k <= max_k, so that later calls allocate nothing (needed
+ * before capturing calls into a HIP graph).  Synchronises the device.
+ * Errors: INVALID_ARG (negative sizes), NOMEM.                            */
+rid_status rid_reserve(rid_handle h, int64_t max_m, int64_t max_n, int64_t max_l,
+                       int64_t max_k);
+
+/* ---------------------------------------------------------------- step 1 */
+
+/* The Gaussian sketch operator of the randomization step (Sec. 2), or any
+ * block of the project's Gaussian stream: out (rows x cols complex128,
+ * row-major, entry (i, j) at out[i * ld + j], ld >= cols) receives
+ *   g(i, j) = sqrt(-ln u1) * exp(2 pi i u2),   Re, Im ~ N(0, 1/2),
+ * where (u1, u2) are two 52-bit uniforms in (0, 1), u = (2x + 1) 2^-53 with x
+ * the top 52 bits of a 64-bit word pair, taken from the Philox4x32-10 block
+ * (Salmon et al., SC'11) with counter (j mod 2^32, j >> 32, i, stream_id) and
+ * key (seed mod 2^32, seed >> 32): words (w0, w1) give u1 and (w2, w3) u2.
+ * stream_id 0 is the sketch operator G (l x m), stream_id 1 the power-
+ * iteration start vector (1 x n).
+ * Errors: INVALID_ARG (rows or cols < 0, ld < cols, null out), HIP.      */
+rid_status rid_gaussian(rid_handle h, hipStream_t stream, int64_t rows, int64_t cols,
+                        uint64_t seed, uint32_t stream_id, void *out, int64_t ld);
+
+/* Randomization step (Sec. 2) with the Gaussian operator of `seed`:
+ *   Y (l x n complex128, ldy >= l) = G(seed) (l x m) * A (m x n, lda >= m).
+ * A is complex128 or complex64 per `dtype`; `prec` selects the product
+ * arithmetic.  G is drawn into the handle's workspace (16 l m bytes).
+ * Requires 1 <= l, 0 <= m, 0 <= n; A 16-byte aligned for RID_C128 (8 for
+ * RID_C64), Y 16-byte aligned.  Errors: INVALID_ARG, UNSUPPORTED (dtype/prec
+ * pair not built), NOMEM, HIP.                                            */
+rid_status rid_sketch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                      int64_t m, int64_t n, int64_t l, const void *A, int64_t lda,
+                      uint64_t seed, void *Y, int64_t ldy);
+
+/* As rid_sketch, with a caller-supplied operator G (l x m complex128,
+ * row-major, entry (i, p) at G[i * ldg + p], ldg >= m).                  */
+rid_status rid_sketch_explicit(rid_handle h, hipStream_t stream, rid_dtype dtype,
+                               rid_prec prec, int64_t m, int64_t n, int64_t l, const void *A,
+                               int64_t lda, const void *G, int64_t ldg, void *Y, int64_t ldy);
+
+/* ---------------------------------------------------------------- step 2 */
+
+/* Column-pivoted QR of Y (Sec. 2 approximate QR with the column
+ * permutation), k steps of Householder reflections with exact pivoting:
+ * step t picks, among the columns not yet picked, the one whose rows t..l-1
+ * (after the t earlier reflections) have the largest 2-norm, the lowest
+ * column index winning an exact tie; those trailing norms are recomputed at
+ * every step.  On return
+ *   Y(0:k, :)  holds R = [R1 R2] in ORIGINAL column order: R(:, perm[t]) is
+ *              column t of the upper-triangular R1 (zero below row t), the
+ *              other columns are R2; rows k..l-1 of Y are left undefined;
+ *   perm[0:k]  is the skeleton J in pivot order, perm[k:n] the remaining
+ *              columns in increasing order;
+ *   gaps[t]    (if gaps is not null) = (best - second best) / best trailing
+ *              norm at step t (1 when one candidate is left).
+ * If at some step the best trailing norm is <= rank_tol * (the best norm of
+ * step 0), the handle's status word is set to RID_ERR_RANK and the outputs
+ * are undefined (Sec. 2: rank(Y) < k).  Requires 1 <= k <= min(l, n),
+ * ldy >= l.  Errors: INVALID_ARG, NOMEM, HIP.                             */
+rid_status rid_pivqr(rid_handle h, hipStream_t stream, int64_t l, int64_t n, int64_t k,
+                     void *Y, int64_t ldy, int64_t *perm, double *gaps, double rank_tol);
+
+/* ---------------------------------------------------------------- step 3 */
+
+/* Interpolation matrix (Sec. 2): with R1 = R(:, J) upper triangular and R2
+ * the other columns of R (k x n complex128, ORIGINAL column order, ldr >= k,
+ * as left by rid_pivqr), solve R1 T = R2 column by column by back
+ * substitution and write P (k x n complex128, ldp >= k) in original column
+ * order: P(:, J[t]) = e_t exactly, P(:, j) = R1^{-1} R(:, j) otherwise.
+ * J: k distinct indices in [0, n) (device).  Requires 1 <= k <= n.
+ * Errors: INVALID_ARG, HIP.                                               */
+rid_status rid_interp(rid_handle h, hipStream_t stream, int64_t n, int64_t k, const void *R,
+                      int64_t ldr, const int64_t *J, void *P, int64_t ldp);
+
+/* ---------------------------------------------------------------- step 4 */
+
+/* Power-iteration estimate of ||E||_2, E = A - A(:, J) P (the error of
+ * Table 5), without forming E: E x = A x~ with x~ = x - S_J (P x), and
+ * E^H z = u - P^H u_J with u = A^H z.  Start vector x0 = rid_gaussian(seed,
+ * stream_id 1) (1 x n), normalised.  Step t = 1..q: z = E x,
+ * sigma_t = ||z||_2, and for t < q, x = E^H z / ||E^H z||; if E^H z = 0 the
+ * iteration stops and later sigma_t repeat the last value.  All sums over A
+ * are compensated (double-double).  Outputs: *sigma (device double) =
+ * sigma_q; hist (device, q doubles, or null) = sigma_1..sigma_q.
+ * A: m x n (lda >= m) of type `dtype`; P: k x n complex128 (ldp >= k);
+ * J: k device indices.  `prec` must be RID_FP64 (the residual is always
+ * accumulated in double).  Requires 0 <= k <= n, q >= 1.
+ * Errors: INVALID_ARG, UNSUPPORTED, NOMEM, HIP.                           */
+rid_status rid_residual(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                        int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
+                        const int64_t *J, const void *P, int64_t ldp, int q, uint64_t seed,
+                        double *sigma, double *hist);
+
+/* ---------------------------------------------------------------- all steps */
+
+/* The whole ID (Sec. 2): sketch with G(seed), pivoted QR, interpolation,
+ * residual (q power steps, start vector of the same seed).  If the QR finds
+ * rank(Y) < k, the draw is repeated with seed + 1, up to max_retries more
+ * times (Sec. 2 failure remedy).  Outputs: J (k device int64, pivot order),
+ * P (k x n complex128, ldp >= k), *sigma (device double), *seed_used (host,
+ * may be null) = the seed of the successful draw.  Requires
+ * 1 <= k <= min(l, n), l <= m, q >= 1, max_retries >= 0.  SYNCHRONISES the
+ * stream (to read the rank status).  Errors: INVALID_ARG, UNSUPPORTED,
+ * NOMEM, HIP, RANK (every draw failed).                                   */
+rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                         int64_t m, int64_t n, int64_t k, int64_t l, const void *A,
+                         int64_t lda, uint64_t seed, int q, int max_retries, double rank_tol,
+                         int64_t *J, void *P, int64_t ldp, double *sigma,
+                         uint64_t *seed_used);
+
+/* ---------------------------------------------------------------- profiling */
+
+/* Kernel families timed by the profiling hook. */
+typedef enum {
+  RID_KERNEL_SKETCH = 0,  /* Y = G A product kernel (one launch per sketch)   */
+  RID_KERNEL_AX = 1,      /* z = A x~ pass of the residual (one per step)      */
+  RID_KERNEL_AHZ = 2,     /* u = A^H z pass of the residual (one per step < q) */
+  RID_KERNEL_PIVQR = 3,   /* all launches of one pivoted QR, as one interval   */
+  RID_KERNEL_INTERP = 4,  /* the back-substitution kernel                      */
+  RID_KERNEL_COUNT = 5
+} rid_kernel;
+
+/* enable = 1: forget earlier records and, from now on, record a HIP event
+ * pair on the launch stream around every launch of the kernel families
+ * above; enable = 0: stop recording (records are kept).  Recording adds two
+ * event records per launch and nothing else.  Errors: INVALID_ARG.        */
+rid_status rid_profile(rid_handle h, int enable);
+
+/* Total elapsed milliseconds and number of recorded launches of one kernel
+ * family since rid_profile(h, 1) (host out-pointers; either may be null).
+ * Synchronises on the recorded events.  Errors: INVALID_ARG, HIP.        */
+rid_status rid_profile_read(rid_handle h, int kernel, double *total_ms, int64_t *launches);
+
+/* Synchronise `stream` and return the handle's status word: RID_OK, or
+ * RID_ERR_RANK if the last rid_pivqr on this handle met rank(Y) < k.
+ * Errors: HIP.                                                            */
+rid_status rid_query_status(rid_handle h, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RID_H */

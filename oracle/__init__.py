@@ -57,6 +57,7 @@ def _load():
         lib = ctypes.CDLL(_LIB)
         P = ctypes.c_void_p
         I64 = ctypes.c_int64
+        lib.orc_num_threads.restype = ctypes.c_int
         lib.orc_philox4x32_10.argtypes = [P, P, P]
         lib.orc_gauss_entry.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
                                         ctypes.c_uint64, P]
@@ -71,6 +72,11 @@ def _load():
         lib.orc_residual.restype = ctypes.c_int
         _lib = lib
     return _lib
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's loops run on."""
+    return int(_load().orc_num_threads())
 
 
 def _ptr(a: np.ndarray):

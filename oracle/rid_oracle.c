@@ -35,6 +35,7 @@
  * here is pinned by a CPU test except where a comment says otherwise.
  */
 #include <math.h>
+#include <omp.h>
 #include <quadmath.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -43,6 +44,9 @@
 #define ORC_OK 0
 #define ORC_ERR_ARG 1
 #define ORC_ERR_RANK 5
+
+/* Threads the OpenMP loops of the oracle use. */
+int orc_num_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as   */

@@ -1,0 +1,316 @@
+"""Python binding of librid (randomized interpolative decomposition on MI355X).
+
+Thin ctypes marshalling over the C ABI in include/rid.h: the functions here
+have the C names, take torch tensors that live on the GPU, pass their device
+pointers, leading dimensions and the current HIP stream, and raise RidError
+on a non-OK status.  Every step of the computation runs in librid's HIP
+kernels; nothing here computes.  There is no CPU fallback: importing this
+package works, but every call raises ImportError until librid.so is built.
+
+Layouts (as in rid.h): A, Y, R, P are column-major, i.e. tensors of shape
+(rows, cols) with stride (1, ld); ``colmajor()`` makes such a copy.  G is
+row-major (an ordinary contiguous (l, m) tensor).  Indices are int64.
+
+Method: Lucas, Stalzer & Feo, arXiv 1205.3830, Sec. 2 (sketch, pivoted QR,
+R2 = R1 T, P = [I T]) and Table 5 (the error ||A - BP||_2).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librid.so")
+
+RID_OK = 0
+RID_ERR_INVALID_ARG = 1
+RID_ERR_UNSUPPORTED = 2
+RID_ERR_NOMEM = 3
+RID_ERR_HIP = 4
+RID_ERR_RANK = 5
+
+RID_C128 = 0
+RID_C64 = 1
+RID_FP64 = 0
+RID_FP32 = 1
+RID_BF16X3 = 2
+
+EXPORTED = ["rid_create", "rid_destroy", "rid_status_string", "rid_last_hip_error",
+            "rid_reserve", "rid_gaussian", "rid_sketch", "rid_sketch_explicit", "rid_pivqr",
+            "rid_interp", "rid_residual", "rid_decompose", "rid_query_status", "rid_profile",
+            "rid_profile_read"]
+
+RID_KERNEL_SKETCH = 0
+RID_KERNEL_AX = 1
+RID_KERNEL_AHZ = 2
+RID_KERNEL_PIVQR = 3
+RID_KERNEL_INTERP = 4
+KERNEL_NAMES = {RID_KERNEL_SKETCH: "sketch", RID_KERNEL_AX: "residual_ax",
+                RID_KERNEL_AHZ: "residual_ahz", RID_KERNEL_PIVQR: "pivqr",
+                RID_KERNEL_INTERP: "interp"}
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_U64 = ctypes.c_uint64
+_I = ctypes.c_int
+_D = ctypes.c_double
+
+_lib = None
+
+_sig = {
+    "rid_create": ([ctypes.POINTER(_P), _I], _I),
+    "rid_destroy": ([_P], _I),
+    "rid_status_string": ([_I], ctypes.c_char_p),
+    "rid_last_hip_error": ([_P], _I),
+    "rid_reserve": ([_P, _I64, _I64, _I64, _I64], _I),
+    "rid_gaussian": ([_P, _P, _I64, _I64, _U64, ctypes.c_uint32, _P, _I64], _I),
+    "rid_sketch": ([_P, _P, _I, _I, _I64, _I64, _I64, _P, _I64, _U64, _P, _I64], _I),
+    "rid_sketch_explicit": ([_P, _P, _I, _I, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64],
+                            _I),
+    "rid_pivqr": ([_P, _P, _I64, _I64, _I64, _P, _I64, _P, _P, _D], _I),
+    "rid_interp": ([_P, _P, _I64, _I64, _P, _I64, _P, _P, _I64], _I),
+    "rid_residual": ([_P, _P, _I, _I, _I64, _I64, _I64, _P, _I64, _P, _P, _I64, _I, _U64, _P,
+                      _P], _I),
+    "rid_decompose": ([_P, _P, _I, _I, _I64, _I64, _I64, _I64, _P, _I64, _U64, _I, _I, _D, _P,
+                       _P, _I64, _P, ctypes.POINTER(_U64)], _I),
+    "rid_query_status": ([_P, _P], _I),
+    "rid_profile": ([_P, _I], _I),
+    "rid_profile_read": ([_P, _I, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I),
+}
+
+
+class _Lib:
+    """librid.so, loaded on first use; raises if it has not been built."""
+
+    def __getattr__(self, name):
+        global _lib
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError("librid.so is not built (run __graft_entry__.build() or "
+                                  "python -m paper_1205_3830_amd.build); there is no "
+                                  "fallback")
+            lib = ctypes.CDLL(LIB_PATH)
+            for fname, (args, res) in _sig.items():
+                f = getattr(lib, fname)
+                f.argtypes = args
+                f.restype = res
+            _lib = lib
+        return getattr(_lib, name)
+
+
+_L = _Lib()
+
+
+def load():
+    """Load librid.so now (ImportError if it is missing); returns the CDLL."""
+    _L.rid_status_string
+    return _lib
+
+
+class RidError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _L.rid_status_string(status).decode()
+        super().__init__("%s failed: %s" % (where, msg))
+
+
+def _check(st: int, where: str) -> None:
+    if st != RID_OK:
+        raise RidError(st, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    if stream is None:
+        return _P(_torch().cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return _P(stream)
+    return _P(stream.cuda_stream)
+
+
+def _ptr(t):
+    return _P(t.data_ptr()) if t is not None else _P(0)
+
+
+def colmajor(t):
+    """A column-major (stride (1, rows)) copy of a 2-D tensor."""
+    return t.t().contiguous().t()
+
+
+def _ld_colmajor(t, name):
+    if t.dim() != 2 or (t.stride(0) != 1 and t.shape[0] > 1) or not t.is_cuda:
+        raise ValueError("%s must be a 2-D column-major CUDA tensor" % name)
+    return max(t.stride(1), t.shape[0], 1)
+
+
+def _dtype_code(t):
+    torch = _torch()
+    if t.dtype == torch.complex128:
+        return RID_C128
+    if t.dtype == torch.complex64:
+        return RID_C64
+    raise ValueError("A must be complex128 or complex64")
+
+
+# --------------------------------------------------------------------- handle
+def rid_create(device: int = 0):
+    h = _P()
+    _check(_L.rid_create(ctypes.byref(h), device), "rid_create")
+    return h
+
+
+def rid_destroy(h) -> None:
+    _check(_L.rid_destroy(h), "rid_destroy")
+
+
+def rid_status_string(status: int) -> str:
+    return _L.rid_status_string(status).decode()
+
+
+def rid_last_hip_error(h) -> int:
+    return _L.rid_last_hip_error(h)
+
+
+def rid_reserve(h, max_m: int, max_n: int, max_l: int, max_k: int) -> None:
+    _check(_L.rid_reserve(h, max_m, max_n, max_l, max_k), "rid_reserve")
+
+
+# --------------------------------------------------------------------- steps
+def rid_gaussian(h, rows: int, cols: int, seed: int, stream_id: int, out=None, stream=None):
+    """rows x cols block of the Gaussian stream (row-major complex128)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((rows, cols), dtype=torch.complex128, device="cuda")
+    ld = out.stride(0) if rows > 1 else max(cols, 1)
+    _check(_L.rid_gaussian(h, _stream(stream), rows, cols, seed, stream_id, _ptr(out), ld),
+           "rid_gaussian")
+    return out
+
+
+def _new_colmajor(rows, cols, dtype):
+    torch = _torch()
+    return torch.empty((cols, rows), dtype=dtype, device="cuda").t()
+
+
+def rid_sketch(h, A, l: int, seed: int, Y=None, prec: int = RID_FP64, stream=None):
+    """Y = G(seed) A (l x n complex128, column-major)."""
+    torch = _torch()
+    m, n = A.shape
+    lda = _ld_colmajor(A, "A")
+    if Y is None:
+        Y = _new_colmajor(l, n, torch.complex128)
+    ldy = _ld_colmajor(Y, "Y")
+    _check(_L.rid_sketch(h, _stream(stream), _dtype_code(A), prec, m, n, l, _ptr(A), lda,
+                           seed, _ptr(Y), ldy), "rid_sketch")
+    return Y
+
+
+def rid_sketch_explicit(h, A, G, Y=None, prec: int = RID_FP64, stream=None):
+    """Y = G A with a caller-supplied row-major G (l x m complex128)."""
+    torch = _torch()
+    m, n = A.shape
+    l = G.shape[0]
+    lda = _ld_colmajor(A, "A")
+    if G.dim() != 2 or G.shape[1] != m or (G.stride(1) != 1 and m > 1):
+        raise ValueError("G must be a row-major (l, m) tensor")
+    ldg = max(G.stride(0), m, 1)
+    if Y is None:
+        Y = _new_colmajor(l, n, torch.complex128)
+    ldy = _ld_colmajor(Y, "Y")
+    _check(_L.rid_sketch_explicit(h, _stream(stream), _dtype_code(A), prec, m, n, l,
+                                    _ptr(A), lda, _ptr(G), ldg, _ptr(Y), ldy),
+           "rid_sketch_explicit")
+    return Y
+
+
+def rid_pivqr(h, Y, k: int, perm=None, gaps=None, rank_tol: float = 1e-12, stream=None):
+    """Pivoted QR of Y in place; returns (perm, gaps)."""
+    torch = _torch()
+    l, n = Y.shape
+    ldy = _ld_colmajor(Y, "Y")
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int64, device="cuda")
+    if gaps is None:
+        gaps = torch.empty(k, dtype=torch.float64, device="cuda")
+    _check(_L.rid_pivqr(h, _stream(stream), l, n, k, _ptr(Y), ldy, _ptr(perm), _ptr(gaps),
+                          rank_tol), "rid_pivqr")
+    return perm, gaps
+
+
+def rid_interp(h, R, J, P=None, stream=None):
+    """P = [I T] with R1 T = R2 (k x n complex128, original column order)."""
+    torch = _torch()
+    k = J.shape[0]
+    n = R.shape[1]
+    ldr = _ld_colmajor(R, "R")
+    if P is None:
+        P = _new_colmajor(k, n, torch.complex128)
+    ldp = _ld_colmajor(P, "P")
+    _check(_L.rid_interp(h, _stream(stream), n, k, _ptr(R), ldr, _ptr(J), _ptr(P), ldp),
+           "rid_interp")
+    return P
+
+
+def rid_residual(h, A, J, P, q: int, seed: int, sigma=None, hist=None, prec: int = RID_FP64,
+                 stream=None):
+    """Power-iteration estimate of ||A - A(:,J) P||_2; returns (sigma, hist)."""
+    torch = _torch()
+    m, n = A.shape
+    k = J.shape[0] if J is not None else 0
+    lda = _ld_colmajor(A, "A")
+    ldp = _ld_colmajor(P, "P") if k > 0 else 1
+    if sigma is None:
+        sigma = torch.zeros(1, dtype=torch.float64, device="cuda")
+    if hist is None:
+        hist = torch.zeros(q, dtype=torch.float64, device="cuda")
+    _check(_L.rid_residual(h, _stream(stream), _dtype_code(A), prec, m, n, k, _ptr(A), lda,
+                             _ptr(J) if k else _P(0), _ptr(P) if k else _P(0), ldp, q, seed,
+                             _ptr(sigma), _ptr(hist)), "rid_residual")
+    return sigma, hist
+
+
+def rid_decompose(h, A, k: int, l: int, seed: int = 0, q: int = 10, max_retries: int = 3,
+                  rank_tol: float = 1e-12, J=None, P=None, sigma=None, prec: int = RID_FP64,
+                  stream=None):
+    """The whole ID; returns (J, P, sigma, seed_used).  Synchronises."""
+    torch = _torch()
+    m, n = A.shape
+    lda = _ld_colmajor(A, "A")
+    if J is None:
+        J = torch.empty(k, dtype=torch.int64, device="cuda")
+    if P is None:
+        P = _new_colmajor(k, n, torch.complex128)
+    ldp = _ld_colmajor(P, "P")
+    if sigma is None:
+        sigma = torch.zeros(1, dtype=torch.float64, device="cuda")
+    used = _U64(0)
+    _check(_L.rid_decompose(h, _stream(stream), _dtype_code(A), prec, m, n, k, l, _ptr(A),
+                              lda, seed, q, max_retries, rank_tol, _ptr(J), _ptr(P), ldp,
+                              _ptr(sigma), ctypes.byref(used)), "rid_decompose")
+    return J, P, sigma, int(used.value)
+
+
+def rid_query_status(h, stream=None) -> int:
+    """Synchronise and read the handle's status word (RID_OK or RID_ERR_RANK)."""
+    st = _L.rid_query_status(h, _stream(stream))
+    if st not in (RID_OK, RID_ERR_RANK):
+        raise RidError(st, "rid_query_status")
+    return st
+
+
+def rid_profile(h, enable: bool) -> None:
+    """Start (and clear) or stop event timing of the hot kernels."""
+    _check(_L.rid_profile(h, 1 if enable else 0), "rid_profile")
+
+
+def rid_profile_read(h, kernel: int):
+    """(total milliseconds, launches) recorded for one kernel family."""
+    ms = _D(0.0)
+    cnt = _I64(0)
+    _check(_L.rid_profile_read(h, kernel, ctypes.byref(ms), ctypes.byref(cnt)),
+           "rid_profile_read")
+    return ms.value, cnt.value

@@ -1,0 +1,147 @@
+// interp.hip -- the interpolation matrix of Sec. 2: solve R2 = R1 T by back
+// substitution, each column on its own (the column-parallel "factorization
+// of R" of Sec. 3.2), and write P = [I T] in the original column order.
+//
+// One wave per column of P.  The k right-hand-side entries of column j sit
+// in the lanes (RR per lane, k <= 64 RR); step t divides entry t by the
+// diagonal R1(t, t), broadcasts the quotient and updates the entries above
+// it with column t of R1 (= column J[t] of R, a coalesced read that all
+// columns share through the L2).  The read for step t-1 is issued before
+// the arithmetic of step t.
+#include "rid_internal.hpp"
+
+namespace {
+
+__global__ void interp_mark_clear_kernel(int64_t n, int *mark) {
+  const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (j < n) mark[j] = -1;
+}
+
+__global__ void interp_mark_set_kernel(int64_t n, int64_t k, const int64_t *J, int *mark) {
+  const int64_t t = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (t < k) {
+    const int64_t j = J[t];
+    if (j >= 0 && j < n) mark[j] = static_cast<int>(t);
+  }
+}
+
+template <int RR>
+__global__ __launch_bounds__(256) void interp_kernel(int64_t n, int64_t k,
+                                                     const double2 *__restrict__ R,
+                                                     int64_t ldr, const int64_t *__restrict__ J,
+                                                     double2 *__restrict__ P, int64_t ldp,
+                                                     const int *__restrict__ mark) {
+  __shared__ int64_t Js[64 * RR];
+  for (int t = threadIdx.x; t < 64 * RR; t += blockDim.x) {
+    int64_t jt = (t < k) ? J[t] : 0;
+    if (jt < 0 || jt >= n) jt = 0;  // keeps every read inside R; such a P is meaningless
+    Js[t] = jt;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int64_t j = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  if (j >= n) return;
+  double2 *pc = P + j * ldp;
+  const int t0 = mark[j];
+  if (t0 >= 0) {
+#pragma unroll
+    for (int h = 0; h < RR; ++h) {
+      const int64_t s = lane + 64 * h;
+      if (s < k) pc[s] = make_double2(s == t0 ? 1.0 : 0.0, 0.0);
+    }
+    return;
+  }
+  double2 r[RR];
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const int64_t s = lane + 64 * h;
+    r[h] = (s < k) ? R[s + j * ldr] : make_double2(0.0, 0.0);
+  }
+  // column of R1 for the current step, prefetched one step ahead
+  double2 rc[RR];
+  {
+    const double2 *cj = R + Js[k - 1] * ldr;
+#pragma unroll
+    for (int h = 0; h < RR; ++h) {
+      const int64_t s = lane + 64 * h;
+      rc[h] = (s < k) ? cj[s] : make_double2(0.0, 0.0);
+    }
+  }
+  for (int64_t t = k - 1; t >= 0; --t) {
+    double2 nx[RR];
+    if (t > 0) {
+      const double2 *cj = R + Js[t - 1] * ldr;
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int64_t s = lane + 64 * h;
+        nx[h] = (s < t) ? cj[s] : make_double2(0.0, 0.0);
+      }
+    }
+    const int ht = static_cast<int>(t >> 6);
+    const int lt = static_cast<int>(t & 63);
+    double2 own = r[0];
+    double2 dg = rc[0];
+#pragma unroll
+    for (int h = 1; h < RR; ++h)
+      if (h == ht) {
+        own = r[h];
+        dg = rc[h];
+      }
+    const double ox = __shfl(own.x, lt, 64), oy = __shfl(own.y, lt, 64);
+    const double dx = __shfl(dg.x, lt, 64), dy = __shfl(dg.y, lt, 64);
+    const double den = dx * dx + dy * dy;
+    const double tx = (ox * dx + oy * dy) / den;
+    const double ty = (oy * dx - ox * dy) / den;
+#pragma unroll
+    for (int h = 0; h < RR; ++h) {
+      const int64_t s = lane + 64 * h;
+      if (s == t) {
+        r[h] = make_double2(tx, ty);
+      } else if (s < t) {
+        r[h].x -= rc[h].x * tx - rc[h].y * ty;
+        r[h].y -= rc[h].x * ty + rc[h].y * tx;
+      }
+    }
+    if (t > 0) {
+#pragma unroll
+      for (int h = 0; h < RR; ++h) rc[h] = nx[h];
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const int64_t s = lane + 64 * h;
+    if (s < k) pc[s] = r[h];
+  }
+}
+
+}  // namespace
+
+bool interp_supported(int64_t k) { return k >= 1 && k <= 256; }
+
+size_t interp_ws_bytes(int64_t n) { return size_t(n) * sizeof(int) + 256; }
+
+hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R, int64_t ldr,
+                         const int64_t *J, double2 *P, int64_t ldp, void *ws,
+                         RidProf *prof) {
+  int *mark = static_cast<int *>(ws);
+  const unsigned nbn = static_cast<unsigned>((n + 255) / 256);
+  hipLaunchKernelGGL(interp_mark_clear_kernel, dim3(nbn), dim3(256), 0, st, n, mark);
+  hipLaunchKernelGGL(interp_mark_set_kernel, dim3(static_cast<unsigned>((k + 255) / 256)),
+                     dim3(256), 0, st, n, k, J, mark);
+  const unsigned nb = static_cast<unsigned>((n + 3) / 4);
+  ProfScope ps(prof, st, RID_KERNEL_INTERP);
+  if (k <= 64)
+    hipLaunchKernelGGL(interp_kernel<1>, dim3(nb), dim3(256), 0, st, n, k, R, ldr, J, P, ldp,
+                       mark);
+  else if (k <= 128)
+    hipLaunchKernelGGL(interp_kernel<2>, dim3(nb), dim3(256), 0, st, n, k, R, ldr, J, P, ldp,
+                       mark);
+  else if (k <= 192)
+    hipLaunchKernelGGL(interp_kernel<3>, dim3(nb), dim3(256), 0, st, n, k, R, ldr, J, P, ldp,
+                       mark);
+  else
+    hipLaunchKernelGGL(interp_kernel<4>, dim3(nb), dim3(256), 0, st, n, k, R, ldr, J, P, ldp,
+                       mark);
+  ps.stop();
+  return hipGetLastError();
+}

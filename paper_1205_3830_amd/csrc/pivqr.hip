@@ -1,0 +1,333 @@
+// pivqr.hip -- column-pivoted Householder QR of the l x n sketch Y, the
+// approximate QR with column permutation of Sec. 2.  Only the first k steps
+// are taken; the pivots are the skeleton J.
+//
+// One kernel per step.  Workgroup b (4 waves) owns columns [64b, 64b + 64),
+// each wave 16 of them, one column at a time with the rows spread over the
+// 64 lanes (RR rows per lane, l <= 64 RR).  Kernel t
+//   1. merges the per-workgroup candidates of step t-1 into the pivot j* of
+//      step t-1 (max trailing norm, lowest index on exact ties) -- every
+//      workgroup does the same merge in the same order, so all agree;
+//   2. rebuilds the Householder reflector of step t-1 from the candidate
+//      copy of column j* (LAPACK zlarfg convention, real diagonal beta) and
+//      applies its adjoint to the rows t-1.. of its own unpicked columns;
+//      the owner of j* writes beta and zeros into that column;
+//   3. recomputes the exact trailing norm (rows t..l-1) of each unpicked
+//      column and publishes its best column (norm, index, a copy of the
+//      trailing rows) and second-best norm for step t.
+// Columns stay in place: after the last kernel, Y(0:k, :) is R in original
+// column order.  No floating-point atomics; every reduction has a fixed order.
+#include <climits>
+
+#include "rid_internal.hpp"
+
+namespace {
+
+constexpr int PQ_COLS = 64;
+
+struct PivWs {
+  double *cnorm;   // [nb] best trailing norm of the block (-1: none)
+  double *cnorm2;  // [nb] its second-best norm (-1: none)
+  int64_t *cidx;   // [nb] column index of the best
+  double2 *ccol;   // [nb][l] copy of the best column (rows t..l-1 valid)
+  int *pstep;      // [n] step at which the column was picked, -1 if not
+  double *nu0;     // best norm of step 0
+};
+
+PivWs carve_piv(void *ws, int64_t l, int64_t n) {
+  WsCarve c(ws);
+  const int64_t nb = (n + PQ_COLS - 1) / PQ_COLS;
+  PivWs w;
+  w.cnorm = c.take<double>(nb);
+  w.cnorm2 = c.take<double>(nb);
+  w.cidx = c.take<int64_t>(nb);
+  w.ccol = c.take<double2>(size_t(nb) * size_t(l));
+  w.pstep = c.take<int>(n);
+  w.nu0 = c.take<double>(1);
+  return w;
+}
+
+size_t piv_bytes(int64_t l, int64_t n) {
+  WsCarve c(nullptr);
+  const int64_t nb = (n + PQ_COLS - 1) / PQ_COLS;
+  c.take<double>(nb);
+  c.take<double>(nb);
+  c.take<int64_t>(nb);
+  c.take<double2>(size_t(nb) * size_t(l));
+  c.take<int>(n);
+  c.take<double>(1);
+  return c.off + 256;
+}
+
+// (best value, its column, second-best value); larger value wins, lower
+// column index wins an exact tie.
+struct Cand {
+  double v1;
+  int64_t i1;
+  double v2;
+  int src;  // wave that holds the best (block-level merge only)
+};
+
+RID_DEV Cand cand_empty() { return Cand{-1.0, LLONG_MAX, -1.0, -1}; }
+
+RID_DEV Cand cand_merge(Cand a, Cand b) {
+  const bool bwins = (b.v1 > a.v1) || (b.v1 == a.v1 && b.i1 < a.i1);
+  Cand w = bwins ? b : a;
+  const Cand o = bwins ? a : b;
+  w.v2 = fmax(w.v2, o.v1);
+  return w;
+}
+
+__global__ void pivqr_init_kernel(int64_t n, int *pstep, int *status) {
+  const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
+  if (j < n) pstep[j] = -1;
+  if (j == 0) *status = RID_OK;
+}
+
+template <int RR>
+__global__ __launch_bounds__(256) void pivqr_step_kernel(int t, int64_t l, int64_t n,
+                                                         int64_t k, double2 *Y, int64_t ldy,
+                                                         int64_t *perm, double *gaps,
+                                                         double rank_tol, PivWs w,
+                                                         int *status) {
+  __shared__ double2 v_s[64 * RR];
+  __shared__ double2 best_col[4][64 * RR];
+  __shared__ Cand red[256];
+  __shared__ double2 tau_s;
+  __shared__ double beta_s;
+
+  if (*status != RID_OK) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int nb = gridDim.x;
+  const int64_t cbeg = int64_t(blockIdx.x) * PQ_COLS;
+  int64_t jstar = -1;
+  const int64_t r0 = (t > 0) ? t - 1 : 0;  // first row touched by this kernel
+
+  if (t > 0) {
+    // ---- 1. pivot of step t-1
+    Cand cd = cand_empty();
+    for (int b = tid; b < nb; b += 256) {
+      Cand x{w.cnorm[b], w.cidx[b], w.cnorm2[b], 0};
+      if (x.v1 < 0.0) x = cand_empty();
+      cd = cand_merge(cd, x);
+    }
+    red[tid] = cd;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+      if (tid < s) red[tid] = cand_merge(red[tid], red[tid + s]);
+      __syncthreads();
+    }
+    const Cand best = red[0];
+    const double nu1 = best.v1;
+    const double nu0 = (t == 1) ? nu1 : *w.nu0;
+    const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
+    if (blockIdx.x == 0 && tid == 0) {
+      perm[t - 1] = best.i1;
+      if (gaps) gaps[t - 1] = (best.v2 < 0.0) ? 1.0 : (nu1 - best.v2) / nu1;
+      if (t == 1) *w.nu0 = nu1;
+      if (fail) *status = RID_ERR_RANK;
+    }
+    if (fail) return;
+    jstar = best.i1;
+    const int64_t bstar = jstar / PQ_COLS;
+
+    // ---- 2. reflector of step t-1 from the candidate copy (wave 0)
+    if (wave == 0) {
+      const double2 *x = w.ccol + bstar * l;
+      double2 xv[RR];
+      double ss = 0.0;
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int64_t row = r0 + lane + 64 * h;
+        xv[h] = (row < l) ? x[row] : make_double2(0.0, 0.0);
+        if (lane + 64 * h >= 1) ss += xv[h].x * xv[h].x + xv[h].y * xv[h].y;
+      }
+      const double xnorm2 = wave_sum(ss);
+      const double ar = __shfl(xv[0].x, 0, 64);
+      const double ai = __shfl(xv[0].y, 0, 64);
+      double2 tau;
+      double beta;
+      double2 scale;
+      if (xnorm2 == 0.0 && ai == 0.0) {
+        tau = make_double2(0.0, 0.0);
+        beta = ar;
+        scale = make_double2(0.0, 0.0);
+      } else {
+        const double mag = sqrt(ar * ar + ai * ai + xnorm2);
+        beta = (ar >= 0.0) ? -mag : mag;
+        tau = make_double2((beta - ar) / beta, -ai / beta);
+        // scale = 1 / (alpha - beta)
+        const double dr = ar - beta, di = ai;
+        const double den = dr * dr + di * di;
+        scale = make_double2(dr / den, -di / den);
+      }
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int idx = lane + 64 * h;
+        double2 v;
+        if (idx == 0) {
+          v = make_double2(1.0, 0.0);
+        } else {
+          v = make_double2(xv[h].x * scale.x - xv[h].y * scale.y,
+                           xv[h].x * scale.y + xv[h].y * scale.x);
+        }
+        v_s[idx] = (r0 + idx < l) ? v : make_double2(0.0, 0.0);
+      }
+      if (lane == 0) {
+        tau_s = tau;
+        beta_s = beta;
+      }
+    }
+    __syncthreads();
+  }
+
+  // ---- 2b/3. apply the reflector, then the trailing norms of step t
+  const double2 tau = (t > 0) ? tau_s : make_double2(0.0, 0.0);
+  const double beta = (t > 0) ? beta_s : 0.0;
+  Cand wc = cand_empty();
+  for (int cc = 0; cc < 16; ++cc) {
+    const int64_t j = cbeg + wave * 16 + cc;
+    if (j >= n) break;
+    double2 *col = Y + j * ldy;
+    if (j == jstar) {
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int64_t row = r0 + lane + 64 * h;
+        if (row < l) col[row] = (row == r0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
+      }
+      if (lane == 0) w.pstep[j] = t - 1;
+      continue;
+    }
+    if (w.pstep[j] >= 0) continue;
+    double2 y[RR];
+#pragma unroll
+    for (int h = 0; h < RR; ++h) {
+      const int64_t row = r0 + lane + 64 * h;
+      y[h] = (row < l) ? col[row] : make_double2(0.0, 0.0);
+    }
+    if (t > 0) {
+      // d = v^H y
+      double dr = 0.0, di = 0.0;
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const double2 v = v_s[lane + 64 * h];
+        dr += v.x * y[h].x + v.y * y[h].y;
+        di += v.x * y[h].y - v.y * y[h].x;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      // y -= conj(tau) d v
+      const double cr = tau.x * dr + tau.y * di;
+      const double ci = tau.x * di - tau.y * dr;
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const double2 v = v_s[lane + 64 * h];
+        y[h].x -= v.x * cr - v.y * ci;
+        y[h].y -= v.x * ci + v.y * cr;
+        const int64_t row = r0 + lane + 64 * h;
+        if (row < l) col[row] = y[h];
+      }
+    }
+    if (t < k) {
+      double ss = 0.0;
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int64_t row = r0 + lane + 64 * h;
+        if (row >= t && row < l) ss += y[h].x * y[h].x + y[h].y * y[h].y;
+      }
+      const double nrm = sqrt(wave_sum(ss));
+      const Cand x{nrm, j, -1.0, wave};
+      const bool better = (nrm > wc.v1) || (nrm == wc.v1 && j < wc.i1);
+      wc = cand_merge(wc, x);
+      if (better) {
+#pragma unroll
+        for (int h = 0; h < RR; ++h) best_col[wave][lane + 64 * h] = y[h];
+      }
+    }
+  }
+  if (t >= k) return;
+
+  // ---- block-level candidate, merged in wave order
+  if (lane == 0) red[wave] = wc;
+  __syncthreads();
+  Cand bc = cand_empty();
+  for (int wv = 0; wv < 4; ++wv) bc = cand_merge(bc, red[wv]);
+  if (tid == 0) {
+    w.cnorm[blockIdx.x] = bc.v1;
+    w.cnorm2[blockIdx.x] = bc.v2;
+    w.cidx[blockIdx.x] = bc.i1;
+  }
+  if (bc.src >= 0) {
+    double2 *dst = w.ccol + int64_t(blockIdx.x) * l;
+    for (int idx = tid; idx < 64 * RR; idx += 256) {
+      const int64_t row = r0 + idx;
+      if (row >= t && row < l) dst[row] = best_col[bc.src][idx];
+    }
+  }
+}
+
+// perm[k + r] = r-th unpicked column in increasing order (one workgroup).
+__global__ __launch_bounds__(1024) void pivqr_tail_kernel(int64_t n, int64_t k,
+                                                          const int *pstep, int64_t *perm,
+                                                          const int *status) {
+  __shared__ int wcount[16];
+  if (*status != RID_OK) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  int64_t base = k;
+  for (int64_t c0 = 0; c0 < n; c0 += 1024) {
+    const int64_t j = c0 + tid;
+    const bool flag = (j < n) && pstep[j] < 0;
+    const uint64_t mask = __ballot(flag);
+    const int before = __popcll(mask & ((lane == 0) ? 0ull : (~0ull >> (64 - lane))));
+    if (lane == 0) wcount[wave] = __popcll(mask);
+    __syncthreads();
+    int off = 0, total = 0;
+    for (int wv = 0; wv < 16; ++wv) {
+      if (wv < wave) off += wcount[wv];
+      total += wcount[wv];
+    }
+    if (flag) perm[base + off + before] = j;
+    base += total;
+    __syncthreads();
+  }
+}
+
+template <int RR>
+void launch_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y, int64_t ldy,
+                  int64_t *perm, double *gaps, double rank_tol, const PivWs &w, int *status) {
+  const unsigned nb = static_cast<unsigned>((n + PQ_COLS - 1) / PQ_COLS);
+  for (int t = 0; t <= k; ++t)
+    hipLaunchKernelGGL(pivqr_step_kernel<RR>, dim3(nb), dim3(256), 0, st, t, l, n, k, Y, ldy,
+                       perm, gaps, rank_tol, w, status);
+}
+
+}  // namespace
+
+bool pivqr_supported(int64_t l) { return l >= 1 && l <= 256; }
+
+size_t pivqr_ws_bytes(int64_t l, int64_t n) { return piv_bytes(l, n); }
+
+hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y,
+                        int64_t ldy, int64_t *perm, double *gaps, double rank_tol, void *ws,
+                        int *d_status, RidProf *prof) {
+  const PivWs w = carve_piv(ws, l, n);
+  ProfScope ps(prof, st, RID_KERNEL_PIVQR);
+  hipLaunchKernelGGL(pivqr_init_kernel, dim3(static_cast<unsigned>((n + 255) / 256)),
+                     dim3(256), 0, st, n, w.pstep, d_status);
+  if (l <= 64)
+    launch_steps<1>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
+  else if (l <= 128)
+    launch_steps<2>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
+  else if (l <= 192)
+    launch_steps<3>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
+  else
+    launch_steps<4>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
+  hipLaunchKernelGGL(pivqr_tail_kernel, dim3(1), dim3(1024), 0, st, n, k, w.pstep, perm,
+                     d_status);
+  ps.stop();
+  return hipGetLastError();
+}

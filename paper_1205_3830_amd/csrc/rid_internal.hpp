@@ -1,0 +1,214 @@
+// rid_internal.hpp -- declarations shared by the librid translation units:
+// the handle, workspace carving, device helpers (Philox draws, compensated
+// double-double arithmetic, wave64 reductions) and the host-side launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <cstddef>
+#include <vector>
+
+#include "rid.h"
+
+// ------------------------------------------------------------------ profiling
+// Event pairs recorded around launches of the hot kernels (rid_profile).
+struct RidProf {
+  bool on = false;
+  std::vector<hipEvent_t> pool;              // created events, reused
+  size_t used = 0;                           // events handed out since enable
+  std::vector<std::pair<int, size_t>> recs;  // (kernel family, index of start event)
+  hipEvent_t next() {
+    if (used == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[used++];
+  }
+};
+
+// Records the start event in the constructor and the stop event in stop();
+// a no-op when profiling is off or prof is null.
+struct ProfScope {
+  RidProf *p;
+  hipStream_t st;
+  size_t idx = 0;
+  bool active = false;
+  ProfScope(RidProf *prof, hipStream_t s, int kernel) : p(prof), st(s) {
+    if (p && p->on) {
+      idx = p->used;
+      hipEvent_t a = p->next();
+      hipEvent_t b = p->next();
+      if (a && b && hipEventRecord(a, st) == hipSuccess) {
+        p->recs.emplace_back(kernel, idx);
+        active = true;
+      }
+    }
+  }
+  void stop() {
+    if (active) {
+      (void)hipEventRecord(p->pool[idx + 1], st);
+      active = false;
+    }
+  }
+  ~ProfScope() { stop(); }
+};
+
+// ------------------------------------------------------------------ handle
+struct rid_ctx {
+  int device = 0;
+  int last_hip_error = 0;
+  int *d_status = nullptr;  // device status word (RID_OK / RID_ERR_RANK)
+  void *ws = nullptr;       // grow-only workspace
+  size_t ws_bytes = 0;
+  RidProf prof;
+};
+
+// Bump allocator over the handle workspace (256-byte aligned pieces).
+struct WsCarve {
+  char *base;
+  size_t off = 0;
+  explicit WsCarve(void *b) : base(static_cast<char *>(b)) {}
+  template <class T>
+  T *take(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+// ------------------------------------------------------------------ device helpers
+#define RID_DEV __device__ __forceinline__
+
+// Philox4x32-10 block (Salmon et al., SC'11).
+RID_DEV void rid_philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c[0];
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]);
+    const uint32_t lo1 = 0xCD9E8D57u * c[2];
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint32_t n0 = hi1 ^ c[1] ^ k0;
+    const uint32_t n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+RID_DEV double rid_u52(uint32_t lo, uint32_t hi) {
+  const uint64_t x = ((static_cast<uint64_t>(hi) << 32) | lo) >> 12;
+  return static_cast<double>(2 * x + 1) * 0x1p-53;
+}
+
+// One complex Gaussian (Re, Im ~ N(0, 1/2)) of the project's stream:
+// counter (col lo, col hi, row, stream), key (seed lo, seed hi), polar
+// Box-Muller g = sqrt(-ln u1) e^{2 pi i u2}.
+RID_DEV double2 rid_gauss(uint64_t seed, uint32_t stream, uint32_t row, uint64_t col) {
+  uint32_t c[4] = {static_cast<uint32_t>(col), static_cast<uint32_t>(col >> 32), row, stream};
+  rid_philox10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+  const double u1 = rid_u52(c[0], c[1]);
+  const double u2 = rid_u52(c[2], c[3]);
+  const double rad = sqrt(-log(u1));
+  const double ang = 6.283185307179586476925286766559 * u2;
+  return make_double2(rad * cos(ang), rad * sin(ang));
+}
+
+// Error-free transformations (Knuth TwoSum; TwoProd through FMA).  Each
+// helper turns off FMA contraction: fusing the product a*b into a following
+// sum would make the rounded product and its error term disagree.
+RID_DEV void two_sum(double a, double b, double &s, double &e) {
+#pragma clang fp contract(off)
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+// s + c += a * b, compensated (one step of Ogita-Rump-Oishi Dot2).
+RID_DEV void dot2_acc(double &s, double &c, double a, double b) {
+#pragma clang fp contract(off)
+  const double p = a * b;
+  const double pe = fma(a, b, -p);
+  double t, se;
+  two_sum(s, p, t, se);
+  s = t;
+  c += se + pe;
+}
+
+// (s1, c1) += (s2, c2) for unnormalised double-double pairs.
+RID_DEV void dd_add(double &s1, double &c1, double s2, double c2) {
+#pragma clang fp contract(off)
+  double t, e;
+  two_sum(s1, s2, t, e);
+  s1 = t;
+  c1 = c1 + c2 + e;
+}
+
+// Normalise (s, c) to hi + lo with |lo| <= ulp(hi)/2.
+RID_DEV void dd_norm(double s, double c, double &hi, double &lo) {
+#pragma clang fp contract(off)
+  hi = s + c;
+  lo = c - (hi - s);
+}
+
+RID_DEV double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Double-double wave sum; the result is valid in every lane.
+RID_DEV void wave_sum_dd(double &s, double &c) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double s2 = __shfl_xor(s, off, 64);
+    const double c2 = __shfl_xor(c, off, 64);
+    dd_add(s, c, s2, c2);
+  }
+  // lanes may differ in the last bits after xor-butterflies; take lane 0's
+  s = __shfl(s, 0, 64);
+  c = __shfl(c, 0, 64);
+}
+
+// ------------------------------------------------------------------ launchers
+// Each returns hipSuccess or the launch error.  Sizes are validated by the
+// caller (api.hip); the kernels bound-check every access themselves.
+
+// rows x cols complex128 block (column-major, ld) set to zero.
+hipError_t launch_zero(hipStream_t st, int64_t rows, int64_t cols, double2 *out, int64_t ld);
+
+hipError_t launch_gaussian(hipStream_t st, int64_t rows, int64_t cols, uint64_t seed,
+                           uint32_t stream_id, double2 *out, int64_t ld);
+
+// Y = G A in double, G row-major (l x m, ldg), A column-major (m x n, lda).
+// part: workspace of sketch_f64_ws_doubles(m, n, l) doubles.
+size_t sketch_f64_ws_doubles(int64_t m, int64_t n, int64_t l);
+hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l,
+                             const double2 *A, int64_t lda, const double2 *G, int64_t ldg,
+                             double2 *Y, int64_t ldy, double *part, RidProf *prof);
+
+// Pivoted QR workspace and launch.
+size_t pivqr_ws_bytes(int64_t l, int64_t n);
+bool pivqr_supported(int64_t l);
+hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y,
+                        int64_t ldy, int64_t *perm, double *gaps, double rank_tol,
+                        void *ws, int *d_status, RidProf *prof);
+
+size_t interp_ws_bytes(int64_t n);
+bool interp_supported(int64_t k);
+hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R, int64_t ldr,
+                         const int64_t *J, double2 *P, int64_t ldp, void *ws,
+                         RidProf *prof);
+
+size_t residual_ws_bytes(int64_t m, int64_t n, int64_t k, int q);
+hipError_t launch_residual(hipStream_t st, int64_t m, int64_t n, int64_t k,
+                           const double2 *A, int64_t lda, const int64_t *J,
+                           const double2 *P, int64_t ldp, int q, uint64_t seed,
+                           double *sigma, double *hist, void *ws, RidProf *prof);

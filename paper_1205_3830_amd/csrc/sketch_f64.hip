@@ -1,0 +1,207 @@
+// sketch_f64.hip -- randomization step Y = G A (Sec. 2) in double precision
+// on the FP64 matrix cores (v_mfma_f64_16x16x4f64).
+//
+// The complex product is one real GEMM in the real embedding:
+//   Yr (2l x n) = Ge (2l x 2m) * Ar (2m x n),
+// where Ar is A's memory read as doubles (row 2p = Re A(p,:), row 2p+1 =
+// Im A(p,:)), Yr is Y's memory likewise, and the 2x2 block of Ge at (i, p)
+// is [[Re g, -Im g], [Im g, Re g]] with g = G(i, p).  Ge is never stored:
+// each lane builds its matrix-core operand from the complex G entry.
+//
+// Tiling (wave64): a workgroup of 4 waves owns 64 columns of A; each wave
+// owns 16 columns and MT 16-row tiles of Yr (all of Yr when 2l <= 16 MT).
+// One K step covers 16 complex rows of A: lane (r16 = lane % 16, q = lane/16)
+// loads A(p0+4q .. p0+4q+3, col r16) -- 64 contiguous bytes -- and the
+// matching 4 entries of row i of G.  The matrix-core k-slot q of MFMA number
+// s (s = 0..7) stands for real row 8q + s of the step, so the 8 MFMAs of a
+// tile consume the 64-byte vectors lane by lane without any shuffle.
+// Split-K over m is reduced in a fixed order by a second kernel, so the
+// result is deterministic.
+#include "rid_internal.hpp"
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+template <int MT>
+__global__ __launch_bounds__(256) void sketch_f64_kernel(
+    int64_t m, int64_t n, int64_t l, const double2 *__restrict__ A, int64_t lda,
+    const double2 *__restrict__ G, int64_t ldg, double *__restrict__ out, int64_t ldo,
+    int64_t split_stride, int64_t pchunk) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int q = lane >> 4;
+  const int r16 = lane & 15;
+  const int c = lane & 1;
+  const int64_t jcol = int64_t(blockIdx.x) * 64 + wave * 16 + r16;
+  const bool colok = jcol < n;
+  const int64_t pbeg = int64_t(blockIdx.y) * pchunk;
+  const int64_t pend = min(m, pbeg + pchunk);
+  const int mt0 = blockIdx.z * MT;
+
+  d4 acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const double2 *Acol = A + (colok ? jcol : 0) * lda;
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
+    const int64_t pb = p0 + 4 * q;
+    double2 a4[4];
+    if (colok && pb + 4 <= pend) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] = Acol[pb + u];
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        a4[u] = (colok && pb + u < pend) ? Acol[pb + u] : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const int64_t i = int64_t(mt0 + t) * 8 + (r16 >> 1);
+      double2 g4[4];
+      if (i < l && pb + 4 <= pend) {
+        const double2 *Gr = G + i * ldg + pb;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) g4[u] = Gr[u];
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          g4[u] = (i < l && pb + u < pend) ? G[i * ldg + pb + u] : make_double2(0.0, 0.0);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        // row 2i (c = 0): [Re g, -Im g];  row 2i+1 (c = 1): [Im g, Re g]
+        const double o0 = c ? g4[u].y : g4[u].x;
+        const double o1 = c ? g4[u].x : -g4[u].y;
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(o0, a4[u].x, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(o1, a4[u].y, acc[t], 0, 0, 0);
+      }
+    }
+  }
+  if (!colok) return;
+  // D layout of the f64 16x16x4 MFMA: lane, register r -> row 4r + lane/16,
+  // column lane % 16.
+  double *o = out + int64_t(blockIdx.y) * split_stride + jcol * ldo;
+  const int64_t rows = 2 * l;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t mu = int64_t(mt0 + t) * 16 + 4 * r + q;
+      if (mu < rows) o[mu] = acc[t][r];
+    }
+}
+
+// Y(mu, j) = sum over splits s = 0..S-1 (in order) of part[s](mu, j).
+__global__ __launch_bounds__(256) void sketch_reduce_kernel(int64_t rows, int64_t n, int S,
+                                                            const double *__restrict__ part,
+                                                            double *__restrict__ Y,
+                                                            int64_t ldy2) {
+  const int64_t total = rows * n;
+  const int64_t stride = rows * n;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = e / rows;
+    const int64_t mu = e - j * rows;
+    double s = 0.0;
+    for (int sp = 0; sp < S; ++sp) s += part[sp * stride + e];
+    Y[j * ldy2 + mu] = s;
+  }
+}
+
+struct SketchPlan {
+  int MT;       // 16-row tiles per block
+  int nbz;      // blocks along the Yr rows
+  int64_t nbx;  // blocks along columns (64 each)
+  int S;        // K splits
+  int64_t pchunk;
+};
+
+int pick_mt(int64_t tiles) {
+  static const int options[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16,
+                                18, 20, 22, 24, 26, 28};
+  for (int o : options)
+    if (o >= tiles) return o;
+  return 16;  // more than 28 tiles: several blocks along z, 16 tiles each
+}
+
+SketchPlan plan_sketch(int64_t m, int64_t n, int64_t l) {
+  SketchPlan p;
+  const int64_t tiles = (2 * l + 15) / 16;
+  p.MT = pick_mt(tiles);
+  p.nbz = static_cast<int>((tiles + p.MT - 1) / p.MT);
+  p.nbx = (n + 63) / 64;
+  const int64_t base = p.nbx * p.nbz;
+  int64_t S = (2048 + base - 1) / base;
+  const int64_t maxS = (m + 255) / 256;
+  if (S > maxS) S = maxS;
+  if (S < 1) S = 1;
+  int64_t pchunk = (m + S - 1) / S;
+  pchunk = (pchunk + 15) / 16 * 16;
+  if (pchunk < 16) pchunk = 16;
+  S = (m + pchunk - 1) / pchunk;
+  if (S < 1) S = 1;
+  p.S = static_cast<int>(S);
+  p.pchunk = pchunk;
+  return p;
+}
+
+template <int MT>
+void launch_mt(hipStream_t st, const SketchPlan &p, int64_t m, int64_t n, int64_t l,
+               const double2 *A, int64_t lda, const double2 *G, int64_t ldg, double *out,
+               int64_t ldo, int64_t split_stride) {
+  dim3 grid(static_cast<unsigned>(p.nbx), static_cast<unsigned>(p.S),
+            static_cast<unsigned>(p.nbz));
+  hipLaunchKernelGGL(sketch_f64_kernel<MT>, grid, dim3(256), 0, st, m, n, l, A, lda, G, ldg,
+                     out, ldo, split_stride, p.pchunk);
+}
+
+}  // namespace
+
+size_t sketch_f64_ws_doubles(int64_t m, int64_t n, int64_t l) {
+  const SketchPlan p = plan_sketch(m, n, l);
+  if (p.S <= 1) return 0;
+  return size_t(p.S) * size_t(2 * l) * size_t(n);
+}
+
+hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l,
+                             const double2 *A, int64_t lda, const double2 *G, int64_t ldg,
+                             double2 *Y, int64_t ldy, double *part, RidProf *prof) {
+  if (n == 0 || l == 0) return hipSuccess;
+  const SketchPlan p = plan_sketch(m, n, l);
+  double *out;
+  int64_t ldo, split_stride;
+  if (p.S <= 1) {
+    out = reinterpret_cast<double *>(Y);
+    ldo = 2 * ldy;
+    split_stride = 0;
+  } else {
+    out = part;
+    ldo = 2 * l;
+    split_stride = 2 * l * n;
+  }
+  ProfScope ps(prof, st, RID_KERNEL_SKETCH);
+  switch (p.MT) {
+#define RID_MT_CASE(X) \
+  case X:              \
+    launch_mt<X>(st, p, m, n, l, A, lda, G, ldg, out, ldo, split_stride); \
+    break;
+    RID_MT_CASE(1) RID_MT_CASE(2) RID_MT_CASE(3) RID_MT_CASE(4) RID_MT_CASE(5)
+    RID_MT_CASE(6) RID_MT_CASE(7) RID_MT_CASE(8) RID_MT_CASE(9) RID_MT_CASE(10)
+    RID_MT_CASE(11) RID_MT_CASE(12) RID_MT_CASE(13) RID_MT_CASE(14) RID_MT_CASE(15)
+    RID_MT_CASE(16) RID_MT_CASE(18) RID_MT_CASE(20) RID_MT_CASE(22) RID_MT_CASE(24)
+    RID_MT_CASE(26) RID_MT_CASE(28)
+#undef RID_MT_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  ps.stop();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p.S <= 1) return e;
+  const int64_t total = 2 * l * n;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(sketch_reduce_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                     st, 2 * l, n, p.S, part, reinterpret_cast<double *>(Y), 2 * ldy);
+  return hipGetLastError();
+}

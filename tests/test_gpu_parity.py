@@ -1,0 +1,263 @@
+"""GPU parity: every step of the HIP path against the CPU oracle, through the
+C ABI, on seeded synthetic inputs (arXiv 1205.3830, Sec. 3.3 recipe: products
+of complex Gaussian factors plus a small Gaussian noise).
+
+Tolerances (double precision):
+  G      : <= 1e-14 relative per entry (log/sin/cos of two math libraries).
+  Y      : ||dY||_F <= 1e-12 ||Y||_F (summation order; ~u sqrt(m) expected).
+  J      : bit-exact wherever the pivot gap exceeds 1e-10.
+  P      : max|dP| <= 1e-10 max(1, max|P|)  (1e-12 with identical R).
+  sigma  : call-for-call (same A, J, P, seed, q): |d sigma| <= 1e-10 sigma,
+           possible because both sides accumulate the cancelling sums in
+           better than double; end to end (each side its own P):
+           |d sigma| <= 1e-10 sigma + 2 ||A(:,J)||_F ||dP||_F, since
+           | ||E1|| - ||E2|| | <= ||A(:,J)(P1 - P2)||.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+rid = pytest.importorskip("paper_1205_3830_amd")
+
+TAU_J = 1e-10
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = rid.rid_create(0)
+    yield hd
+    rid.rid_destroy(hd)
+
+
+def dev(A):
+    """host complex array (m, n) -> column-major device tensor."""
+    A = np.asarray(A)
+    return torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda").t()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def _lowrank(m, n, k, noise, seed):
+    return synth.lowrank(m, n, k, noise, seed=seed)
+
+
+# ------------------------------------------------------------------ a1: G
+@pytest.mark.parametrize("rows,cols,seed,sid", [(7, 1000, 0, 0), (1, 513, 5, 1),
+                                                (108, 300, 2**40 + 3, 0)])
+def test_gaussian_matches_oracle(h, rows, cols, seed, sid):
+    g = host(rid.rid_gaussian(h, rows, cols, seed, sid))
+    ref = oracle.gaussian(rows, cols, seed, sid)
+    assert np.max(np.abs(g - ref) / np.maximum(np.abs(ref), 1e-300)) <= 1e-14
+
+
+# ------------------------------------------------------------------ a2: Y = G A
+SKETCH_CASES = [
+    (1000, 500, 30),   # 1000 x 500 parity workload, l = k + 10
+    (1037, 131, 30),   # ragged m, n
+    (257, 70, 108),    # l of the large workload (14 row tiles)
+    (64, 64, 1),
+    (5, 3, 2),
+    (1, 1, 1),
+    (600, 97, 208),    # l of the square workload (26 -> 28 tiles)
+    (300, 65, 250),    # 32 tiles: split along the rows of Y
+    (4096, 40, 16),    # several K splits
+]
+
+
+@pytest.mark.parametrize("m,n,l", SKETCH_CASES)
+def test_sketch_explicit_matches_oracle(h, m, n, l):
+    A = _lowrank(m, n, min(8, m, n), 1e-6, seed=m + n)
+    G = oracle.sketch_operator(l, m, seed=1)
+    Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda()))
+    ref = oracle.sketch(A, G)
+    assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("m,n,l,seed", [(1000, 500, 30, 0), (333, 77, 20, 9)])
+def test_sketch_seeded_matches_oracle(h, m, n, l, seed):
+    A = _lowrank(m, n, 10, 1e-8, seed=3)
+    Y = host(rid.rid_sketch(h, dev(A), l, seed))
+    ref = oracle.sketch(A, oracle.sketch_operator(l, m, seed))
+    assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_sketch_leading_dimensions(h):
+    m, n, l = 300, 40, 12
+    A = _lowrank(m, n, 5, 1e-6, seed=4)
+    big = torch.zeros((n, m + 13), dtype=torch.complex128, device="cuda")
+    big[:, :m] = torch.from_numpy(np.ascontiguousarray(A.T)).cuda()
+    Ad = big.t()[:m]                      # lda = m + 13
+    Yb = torch.full((n, l + 5), 7.0, dtype=torch.complex128, device="cuda")
+    Yd = Yb.t()[:l]                        # ldy = l + 5
+    G = oracle.sketch_operator(l, m, seed=2)
+    rid.rid_sketch_explicit(h, Ad, torch.from_numpy(G).cuda(), Y=Yd)
+    ref = oracle.sketch(A, G)
+    Yh = host(Yb).T
+    assert np.linalg.norm(Yh[:l] - ref) <= 1e-12 * np.linalg.norm(ref)
+    assert np.all(Yh[l:] == 7.0)           # padding rows untouched
+
+
+# ------------------------------------------------------------------ a3: pivoted QR
+def _compare_J(Jg, Jo, gaps):
+    """J bit-exact up to the first near-tie; from there only validity."""
+    k = len(Jo)
+    for t in range(k):
+        if gaps[t] <= TAU_J:
+            return t
+        assert Jg[t] == Jo[t], (t, Jg[:t + 1], Jo[:t + 1])
+    return k
+
+
+PIVQR_CASES = [(30, 500, 20), (108, 2000, 100), (12, 12, 12), (40, 9, 9), (8, 300, 1),
+               (200, 700, 150), (65, 100, 64)]
+
+
+@pytest.mark.parametrize("l,n,k", PIVQR_CASES)
+def test_pivqr_and_interp_match_oracle(h, l, n, k):
+    A = _lowrank(max(l, 400), n, k, 1e-9, seed=l * 7 + n)
+    Y = oracle.sketch(A, oracle.sketch_operator(l, A.shape[0], seed=1))
+    st, Jo, Ro, gaps_o = oracle.select(Y, k)
+    assert st == oracle.OK
+    Po = oracle.interp(Ro, Jo)
+    Yd = dev(Y)
+    perm, gaps = rid.rid_pivqr(h, Yd, k)
+    assert rid.rid_query_status(h) == rid.RID_OK
+    perm = host(perm)
+    assert _compare_J(perm[:k], Jo, gaps_o) == k
+    rest = np.setdiff1d(np.arange(n), perm[:k])
+    assert np.array_equal(perm[k:], rest)
+    assert np.allclose(host(gaps), gaps_o, rtol=1e-6, atol=1e-12)
+    R = host(Yd)[:k]
+    # |diag R1| is the step's trailing norm: independent of the reflector convention
+    assert np.allclose(np.abs(R[np.arange(k), perm[:k]]), np.abs(Ro[np.arange(k), Jo]),
+                       rtol=1e-11)
+    # R1 upper triangular in pivot order
+    R1 = R[:, perm[:k]]
+    assert np.all(np.tril(R1, -1) == 0)
+    P = host(rid.rid_interp(h, Yd[:k], torch.from_numpy(perm[:k]).cuda()))
+    assert np.array_equal(P[:, Jo], np.eye(k))
+    assert np.abs(P - Po).max() <= 1e-10 * max(1.0, np.abs(Po).max())
+
+
+@pytest.mark.parametrize("l,n,k", [(30, 500, 20), (108, 1000, 100), (250, 300, 250)])
+def test_interp_same_R_matches_oracle(h, l, n, k):
+    A = _lowrank(max(l, 300), n, k, 1e-8, seed=n)
+    Y = oracle.sketch(A, oracle.sketch_operator(l, A.shape[0], seed=4))
+    st, Jo, Ro, _ = oracle.select(Y, k)
+    Po = oracle.interp(Ro, Jo)
+    P = host(rid.rid_interp(h, dev(Ro), torch.from_numpy(Jo).cuda()))
+    assert np.array_equal(P[:, Jo], np.eye(k))
+    assert np.abs(P - Po).max() <= 1e-12 * max(1.0, np.abs(Po).max())
+
+
+def test_pivqr_rank_failure_sets_status(h):
+    A = _lowrank(200, 80, 5, 0.0, seed=11)          # rank 5 < k = 6
+    Y = oracle.sketch(A, oracle.sketch_operator(10, 200, seed=0))
+    rid.rid_pivqr(h, dev(Y), 6)
+    assert rid.rid_query_status(h) == rid.RID_ERR_RANK
+    rid.rid_pivqr(h, dev(Y), 5)
+    assert rid.rid_query_status(h) == rid.RID_OK
+
+
+def test_pivqr_exact_tie_goes_to_lowest_index(h):
+    Y = synth.hand_example()
+    perm, gaps = rid.rid_pivqr(h, dev(Y), 2)
+    assert list(host(perm)) == [0, 1, 2]
+    assert host(gaps)[1] == 0.0
+
+
+# ------------------------------------------------------------------ a5: residual
+@pytest.mark.parametrize("m,n,k,l,noise,q", [(1000, 500, 20, 30, 1e-10, 10),
+                                             (777, 333, 9, 17, 1e-7, 6),
+                                             (300, 1100, 40, 48, 1e-9, 4),
+                                             (64, 50, 50, 50, 0.0, 3)])
+def test_residual_call_for_call(h, m, n, k, l, noise, q):
+    A = _lowrank(m, n, k, noise, seed=m)
+    r = oracle.decompose(A, k, l, seed=3, q=q)
+    assert r["status"] == oracle.OK
+    sigma, hist = rid.rid_residual(h, dev(A), torch.from_numpy(r["J"]).cuda(),
+                                   dev(r["P"]), q, 3)
+    s, hi = float(host(sigma)[0]), host(hist)
+    if r["sigma"] == 0.0 or noise == 0.0:
+        # k = n: E = 0 up to rounding of P's identity columns
+        assert s <= 1e-12 * np.linalg.norm(A, 2)
+    else:
+        assert abs(s - r["sigma"]) <= 1e-10 * r["sigma"]
+        assert np.all(np.abs(hi - r["hist"]) <= 1e-10 * r["hist"])
+
+
+def test_residual_zero_matrix_stops_early(h):
+    A = np.zeros((20, 6), dtype=np.complex128)
+    J = torch.tensor([0, 1], dtype=torch.int64, device="cuda")
+    P = dev(np.eye(2, 6, dtype=np.complex128))
+    sigma, hist = rid.rid_residual(h, dev(A), J, P, 4, 0)
+    assert float(host(sigma)[0]) == 0.0 and np.all(host(hist) == 0.0)
+
+
+# ------------------------------------------------------------------ end to end
+DECOMP_CASES = [
+    (1000, 500, 20, 30, 1e-10, 10),   # the 1000 x 500 parity workload, seed 0
+    (1000, 500, 20, 30, 0.0, 10),     # exactly rank k
+    (513, 257, 1, 1, 1e-10, 5),       # k = 1, l = k
+    (300, 40, 40, 40, 1e-10, 4),      # k = n: no T at all
+    (2048, 700, 100, 108, 1e-12, 6),  # l, k of the large workload
+]
+
+
+@pytest.mark.parametrize("m,n,k,l,noise,q", DECOMP_CASES)
+def test_decompose_matches_oracle(h, m, n, k, l, noise, q):
+    A = _lowrank(m, n, k, noise, seed=0)
+    r = oracle.decompose(A, k, l, seed=0, q=q)
+    assert r["status"] == oracle.OK
+    J, P, sigma, used = rid.rid_decompose(h, dev(A), k, l, seed=0, q=q)
+    J, P, s = host(J), host(P), float(host(sigma)[0])
+    assert used == r["seed_used"]
+    assert _compare_J(J, r["J"], r["gaps"]) == k
+    assert np.array_equal(P[:, J], np.eye(k))
+    dP = P - r["P"]
+    assert np.abs(dP).max() <= 1e-10 * max(1.0, np.abs(r["P"]).max())
+    tol = 1e-10 * r["sigma"] + 2 * np.linalg.norm(A[:, J]) * np.linalg.norm(dP)
+    assert abs(s - r["sigma"]) <= tol + 1e-300
+    assert np.abs(P).max() <= 2.0
+
+
+def test_decompose_rank_deficient_fails_every_draw(h):
+    A = _lowrank(120, 60, 3, 0.0, seed=2)
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_decompose(h, dev(A), 4, 8, seed=0, q=2, max_retries=2)
+    assert ei.value.status == rid.RID_ERR_RANK
+
+
+def test_decompose_is_deterministic_and_scale_equivariant(h):
+    A = _lowrank(700, 300, 15, 1e-9, seed=7)
+    J1, P1, s1, _ = rid.rid_decompose(h, dev(A), 15, 25, seed=1, q=5)
+    J2, P2, s2, _ = rid.rid_decompose(h, dev(A), 15, 25, seed=1, q=5)
+    J3, P3, s3, _ = rid.rid_decompose(h, dev(2 * A), 15, 25, seed=1, q=5)
+    assert torch.equal(J1, J2) and torch.equal(P1, P2) and torch.equal(s1, s2)
+    assert torch.equal(J1, J3) and torch.equal(P1, P3)
+    assert float(s3[0]) == 2 * float(s1[0])
+
+
+def test_invalid_arguments_rejected(h):
+    A = dev(_lowrank(50, 20, 3, 0.0, seed=1))
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_decompose(h, A, 5, 4, seed=0)          # l < k
+    assert ei.value.status == rid.RID_ERR_INVALID_ARG
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_decompose(h, A, 3, 60, seed=0)         # l > m
+    assert ei.value.status == rid.RID_ERR_INVALID_ARG
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_decompose(h, A, 3, 5, seed=0, q=0)     # q < 1
+    assert ei.value.status == rid.RID_ERR_INVALID_ARG
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_decompose(h, A.to(torch.complex64), 3, 5, seed=0)
+    assert ei.value.status == rid.RID_ERR_UNSUPPORTED
