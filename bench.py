@@ -75,7 +75,7 @@ def main() -> int:
     ap.add_argument("--l", type=int, default=108)
     ap.add_argument("--q", type=int, default=10)
     ap.add_argument("--noise", type=float, default=1e-12)
-    ap.add_argument("--cpu-cols", type=int, default=128)
+    ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 

@@ -11,8 +11,9 @@
 //   ax_partial : z = A x~ ; a workgroup streams a 512-row slab of a range of
 //                columns (each column slab is one contiguous 8 KB read).
 //   ahz_partial: u = A^H z ; a workgroup stages a 2048-row chunk of z in LDS
-//                and each wave streams 4 columns of that chunk (32 KB
-//                contiguous reads), reducing in registers then across lanes.
+//                and each wave streams 8 columns of that chunk (32 KB
+//                contiguous reads each), reducing in registers then across
+//                lanes.
 // Partial sums over column splits (resp. row splits) are reduced in a fixed
 // order by separate kernels, so results are bitwise reproducible.
 #include "rid_internal.hpp"
@@ -21,7 +22,8 @@ namespace {
 
 constexpr int AX_ROWS = 512;   // rows per ax workgroup (2 per thread)
 constexpr int AHZ_RS = 2048;   // rows per ahz split (z chunk in LDS, 32 KB)
-constexpr int AHZ_COLS = 16;   // columns per ahz workgroup (4 per wave)
+constexpr int AHZ_CPW = 8;     // columns per ahz wave
+constexpr int AHZ_COLS = 4 * AHZ_CPW;  // columns per ahz workgroup
 constexpr int PX_JC = 256;     // columns per workgroup of the P x partials
 constexpr int RES_KMAX = 1024; // LDS holds u_J for k <= RES_KMAX
 
@@ -327,7 +329,7 @@ __global__ __launch_bounds__(256) void sigma_final_kernel(int64_t nparts, const 
   }
 }
 
-// u partials: columns [16 cb, +16) x rows of split s; z chunk staged in LDS
+// u partials: columns [32 cb, +32) x rows of split s; z chunk staged in LDS
 __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
                                                           const double2 *__restrict__ A,
                                                           int64_t lda,
@@ -343,23 +345,23 @@ __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t jb = int64_t(blockIdx.x) * AHZ_COLS + wave * 4;
-  double sr[4], cr[4], si[4], ci[4];
-  const double2 *cp[4];
-  bool cok[4];
+  const int64_t jb = int64_t(blockIdx.x) * AHZ_COLS + wave * AHZ_CPW;
+  double sr[AHZ_CPW], cr[AHZ_CPW], si[AHZ_CPW], ci[AHZ_CPW];
+  const double2 *cp[AHZ_CPW];
+  bool cok[AHZ_CPW];
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < AHZ_CPW; ++u) {
     sr[u] = cr[u] = si[u] = ci[u] = 0.0;
     cok[u] = (jb + u) < n;
     cp[u] = A + (cok[u] ? (jb + u) : 0) * lda + r0;
   }
   for (int i = lane; i < rows; i += 64) {
     const double2 zz = zs[i];
-    double2 a[4];
+    double2 a[AHZ_CPW];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = cok[u] ? cp[u][i] : make_double2(0.0, 0.0);
+    for (int u = 0; u < AHZ_CPW; ++u) a[u] = cok[u] ? cp[u][i] : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < AHZ_CPW; ++u) {
       // conj(a) z = (ar zr + ai zi) + i (ar zi - ai zr)
       dot2_acc(sr[u], cr[u], a[u].x, zz.x);
       dot2_acc(sr[u], cr[u], a[u].y, zz.y);
@@ -368,7 +370,7 @@ __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
     }
   }
 #pragma unroll
-  for (int u = 0; u < 4; ++u) {
+  for (int u = 0; u < AHZ_CPW; ++u) {
     wave_sum_dd(sr[u], cr[u]);
     wave_sum_dd(si[u], ci[u]);
     if (lane == 0 && cok[u]) {

@@ -8,15 +8,18 @@
 // is [[Re g, -Im g], [Im g, Re g]] with g = G(i, p).  Ge is never stored:
 // each lane builds its matrix-core operand from the complex G entry.
 //
-// Tiling (wave64): a workgroup of 4 waves owns 64 columns of A; each wave
-// owns 16 columns and MT 16-row tiles of Yr (all of Yr when 2l <= 16 MT).
-// One K step covers 16 complex rows of A: lane (r16 = lane % 16, q = lane/16)
-// loads A(p0+4q .. p0+4q+3, col r16) -- 64 contiguous bytes -- and the
-// matching 4 entries of row i of G.  The matrix-core k-slot q of MFMA number
-// s (s = 0..7) stands for real row 8q + s of the step, so the 8 MFMAs of a
-// tile consume the 64-byte vectors lane by lane without any shuffle.
-// Split-K over m is reduced in a fixed order by a second kernel, so the
-// result is deterministic.
+// Tiling (wave64): a workgroup of 4 waves owns 64 columns of A and MT
+// 16-row tiles of Yr (all of Yr when 2l <= 16 MT, else a z-slice of them);
+// each wave owns 16 of the columns.  One K step covers 16 complex rows of A:
+// lane (r16 = lane % 16, q = lane / 16) holds A(p0+4q .. p0+4q+3, column r16)
+// -- 64 contiguous bytes, loaded one step ahead -- and the matrix-core k-slot
+// q of MFMA number s (s = 0..7) stands for real row 8q + s of the step, so
+// the 8 MFMAs of a tile consume those vectors without any shuffle.  The G
+// rows of the step (8 MT rows x 16 complex entries) are staged by the whole
+// workgroup in LDS, double buffered and loaded one step ahead, with a row
+// stride of 17 entries so that the 8 rows read by one MFMA operand fetch
+// fall in different banks.  Split-K over m is reduced in a fixed order by a
+// second kernel, so the result is deterministic.
 #include "rid_internal.hpp"
 
 namespace {
@@ -28,8 +31,13 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(
     int64_t m, int64_t n, int64_t l, const double2 *__restrict__ A, int64_t lda,
     const double2 *__restrict__ G, int64_t ldg, double *__restrict__ out, int64_t ldo,
     int64_t split_stride, int64_t pchunk) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
+  constexpr int NR = 8 * MT;                       // G rows of the slab
+  constexpr int RS = 17;                           // LDS row stride (complex entries)
+  constexpr int PER = (NR * 16 + 255) / 256;       // staged entries per thread
+  __shared__ double2 gs[2][NR * RS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
   const int q = lane >> 4;
   const int r16 = lane & 15;
   const int c = lane & 1;
@@ -37,16 +45,32 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(
   const bool colok = jcol < n;
   const int64_t pbeg = int64_t(blockIdx.y) * pchunk;
   const int64_t pend = min(m, pbeg + pchunk);
-  const int mt0 = blockIdx.z * MT;
+  const int64_t g0 = int64_t(blockIdx.z) * NR;     // first G row of this z-slice
 
   d4 acc[MT];
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
   const double2 *Acol = A + (colok ? jcol : 0) * lda;
-  for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
+  double2 stg[PER];
+  auto load_g = [&](int64_t p0) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 256 * r;
+      const int row = e >> 4, col = e & 15;
+      const int64_t i = g0 + row, p = p0 + col;
+      stg[r] = (e < NR * 16 && i < l && p < pend) ? G[i * ldg + p] : make_double2(0.0, 0.0);
+    }
+  };
+  auto store_g = [&](int b) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 256 * r;
+      if (e < NR * 16) gs[b][(e >> 4) * RS + (e & 15)] = stg[r];
+    }
+  };
+  auto load_a = [&](int64_t p0, double2 *a4) {
     const int64_t pb = p0 + 4 * q;
-    double2 a4[4];
     if (colok && pb + 4 <= pend) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) a4[u] = Acol[pb + u];
@@ -55,19 +79,27 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(
       for (int u = 0; u < 4; ++u)
         a4[u] = (colok && pb + u < pend) ? Acol[pb + u] : make_double2(0.0, 0.0);
     }
+  };
+
+  double2 a4[4], an[4];
+  load_g(pbeg);
+  store_g(0);
+  load_a(pbeg, a4);
+  __syncthreads();
+  int b = 0;
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
+    const bool more = p0 + 16 < pend;
+    if (more) {
+      load_g(p0 + 16);
+      load_a(p0 + 16, an);
+    }
+    const double2 *gb = gs[b];
 #pragma unroll
     for (int t = 0; t < MT; ++t) {
-      const int64_t i = int64_t(mt0 + t) * 8 + (r16 >> 1);
+      const int row = 8 * t + (r16 >> 1);
       double2 g4[4];
-      if (i < l && pb + 4 <= pend) {
-        const double2 *Gr = G + i * ldg + pb;
 #pragma unroll
-        for (int u = 0; u < 4; ++u) g4[u] = Gr[u];
-      } else {
-#pragma unroll
-        for (int u = 0; u < 4; ++u)
-          g4[u] = (i < l && pb + u < pend) ? G[i * ldg + pb + u] : make_double2(0.0, 0.0);
-      }
+      for (int u = 0; u < 4; ++u) g4[u] = gb[row * RS + 4 * q + u];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         // row 2i (c = 0): [Re g, -Im g];  row 2i+1 (c = 1): [Im g, Re g]
@@ -77,17 +109,25 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(
         acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(o1, a4[u].y, acc[t], 0, 0, 0);
       }
     }
+    if (more) {
+      store_g(b ^ 1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] = an[u];
+    }
+    __syncthreads();
+    b ^= 1;
   }
   if (!colok) return;
   // D layout of the f64 16x16x4 MFMA: lane, register r -> row 4r + lane/16,
   // column lane % 16.
   double *o = out + int64_t(blockIdx.y) * split_stride + jcol * ldo;
   const int64_t rows = 2 * l;
+  const int64_t mu0 = 2 * g0;
 #pragma unroll
   for (int t = 0; t < MT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t mu = int64_t(mt0 + t) * 16 + 4 * r + q;
+      const int64_t mu = mu0 + int64_t(t) * 16 + 4 * r + q;
       if (mu < rows) o[mu] = acc[t][r];
     }
 }
