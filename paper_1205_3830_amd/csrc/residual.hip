@@ -7,7 +7,8 @@
 // FMA, TwoSum for the running sum, errors collected in a second double) and
 // x~, u and the P-corrections are carried as double-double pairs.
 //
-// The two passes over A are the HBM-bound kernels of the whole ID:
+// The two passes over A are the HBM-bound kernels of the whole ID; both read
+// A with non-temporal loads (A is touched once per pass):
 //   ax_partial : z = A x~ ; a workgroup streams a 512-row slab of a range of
 //                columns (each column slab is one contiguous 8 KB read).
 //   ahz_partial: u = A^H z ; a workgroup stages a 2048-row chunk of z in LDS
@@ -228,8 +229,8 @@ __global__ __launch_bounds__(256) void ax_partial_kernel(int64_t m, int64_t n,
     double2 a0[4], a1[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-      a0[u] = ok0 ? a0p[(j + u) * lda] : make_double2(0.0, 0.0);
-      a1[u] = ok1 ? a1p[(j + u) * lda] : make_double2(0.0, 0.0);
+      a0[u] = ok0 ? ld_stream(a0p + (j + u) * lda) : make_double2(0.0, 0.0);
+      a1[u] = ok1 ? ld_stream(a1p + (j + u) * lda) : make_double2(0.0, 0.0);
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
@@ -253,8 +254,8 @@ __global__ __launch_bounds__(256) void ax_partial_kernel(int64_t m, int64_t n,
     }
   }
   for (; j < je; ++j) {
-    const double2 a0 = ok0 ? a0p[j * lda] : make_double2(0.0, 0.0);
-    const double2 a1 = ok1 ? a1p[j * lda] : make_double2(0.0, 0.0);
+    const double2 a0 = ok0 ? ld_stream(a0p + j * lda) : make_double2(0.0, 0.0);
+    const double2 a1 = ok1 ? ld_stream(a1p + j * lda) : make_double2(0.0, 0.0);
     const double2 xh = xth[j], xl = xtl[j];
     dot2_acc(s0r, c0r, a0.x, xh.x);
     dot2_acc(s0r, c0r, -a0.y, xh.y);
@@ -359,7 +360,7 @@ __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
     const double2 zz = zs[i];
     double2 a[AHZ_CPW];
 #pragma unroll
-    for (int u = 0; u < AHZ_CPW; ++u) a[u] = cok[u] ? cp[u][i] : make_double2(0.0, 0.0);
+    for (int u = 0; u < AHZ_CPW; ++u) a[u] = cok[u] ? ld_stream(cp[u] + i) : make_double2(0.0, 0.0);
 #pragma unroll
     for (int u = 0; u < AHZ_CPW; ++u) {
       // conj(a) z = (ar zr + ai zi) + i (ar zi - ai zr)

@@ -121,6 +121,14 @@ RID_DEV double2 rid_gauss(uint64_t seed, uint32_t stream, uint32_t row, uint64_t
   return make_double2(rad * cos(ang), rad * sin(ang));
 }
 
+// Streaming load of one complex128 that is read once per pass (non-temporal:
+// it does not displace cached data such as the vectors the pass reuses).
+typedef double rid_dv2 __attribute__((ext_vector_type(2)));
+RID_DEV double2 ld_stream(const double2 *p) {
+  const rid_dv2 v = __builtin_nontemporal_load(reinterpret_cast<const rid_dv2 *>(p));
+  return make_double2(v.x, v.y);
+}
+
 // Error-free transformations (Knuth TwoSum; TwoProd through FMA).  Each
 // helper turns off FMA contraction: fusing the product a*b into a following
 // sum would make the rounded product and its error term disagree.
