@@ -77,6 +77,9 @@ def main() -> int:
     ap.add_argument("--noise", type=float, default=1e-12)
     ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run three plain 1 GiB device copies (torch copy_), the "
+                         "reference kernel for scaling HBM counter readings")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -95,6 +98,13 @@ def main() -> int:
     print("generating A %d x %d complex128 on the GPU" % (m, n), file=sys.stderr, flush=True)
     A = synth.lowrank_device(m, n, k, args.noise, seed=0).t()      # (m, n), stride (1, m)
     torch.cuda.synchronize()
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     h = rid.rid_create(0)
     rid.rid_reserve(h, m, n, l, k)
     J = torch.empty(k, dtype=torch.int64, device="cuda")
