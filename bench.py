@@ -28,11 +28,15 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_PEAK_TFS = 78.6         # MI355X FP64 matrix (dense)
+FP32_PEAK_TFS = 157.3        # MI355X FP32 matrix (dense)
 
 
-def _traffic(kernel_name: str, src_file: str):
+def _traffic(kernel_name: str, src_file: str, measured_config: bool = True):
     """HBM bytes per launch from a committed counter summary, if it was
-    taken on the current kernel source (matching sha256); else None."""
+    taken on the current kernel source (matching sha256) and on this
+    configuration; else None."""
+    if not measured_config:
+        return None
     path = os.path.join(ROOT, "profiles", "traffic_%s.json" % kernel_name)
     if not os.path.exists(path):
         return None
@@ -75,6 +79,12 @@ def main() -> int:
     ap.add_argument("--l", type=int, default=108)
     ap.add_argument("--q", type=int, default=10)
     ap.add_argument("--noise", type=float, default=1e-12)
+    ap.add_argument("--rho", type=float, default=None,
+                    help="set the noise so that sigma_{k+1} ~ rho ||A||_2 (overrides --noise)")
+    ap.add_argument("--dtype", choices=["c128", "c64"], default="c128",
+                    help="storage of A")
+    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64",
+                    help="arithmetic of the sketch products (QR, solve, residual stay double)")
     ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -95,8 +105,15 @@ def main() -> int:
 
     m, n, k, l, q = args.m, args.n, args.k, args.l, args.q
     torch.cuda.set_device(0)
-    print("generating A %d x %d complex128 on the GPU" % (m, n), file=sys.stderr, flush=True)
-    A = synth.lowrank_device(m, n, k, args.noise, seed=0).t()      # (m, n), stride (1, m)
+    tdt = torch.complex128 if args.dtype == "c128" else torch.complex64
+    esize = 16 if args.dtype == "c128" else 8
+    prec = rid.RID_FP64 if args.prec == "fp64" else rid.RID_FP32
+    noise = args.noise
+    if args.rho is not None:
+        # ||X W||_2 ~ (sqrt(m) + sqrt(k)) (sqrt(n) + sqrt(k)) for Gaussian factors
+        noise = args.rho * (m ** 0.5 + k ** 0.5) * (n ** 0.5 + k ** 0.5) / (m ** 0.5 + n ** 0.5)
+    print("generating A %d x %d %s on the GPU" % (m, n, args.dtype), file=sys.stderr, flush=True)
+    A = synth.lowrank_device(m, n, k, noise, seed=0, dtype=tdt).t()  # (m, n), stride (1, m)
     torch.cuda.synchronize()
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
@@ -112,7 +129,8 @@ def main() -> int:
     sigma = torch.zeros(1, dtype=torch.float64, device="cuda")
 
     def step():
-        return rid.rid_decompose(h, A, k, l, seed=0, q=q, J=J, P=P, sigma=sigma)
+        return rid.rid_decompose(h, A, k, l, seed=0, q=q, J=J, P=P, sigma=sigma, prec=prec,
+                                 rank_tol=1e-12 if prec == rid.RID_FP64 else 1e-5)
 
     for i in range(args.warmup):
         step()
@@ -126,7 +144,7 @@ def main() -> int:
     t1 = time.perf_counter()
     rid.rid_profile(h, False)
     ms = (t1 - t0) * 1e3 / args.steps
-    bytes_a = 16.0 * m * n
+    bytes_a = float(esize) * m * n
     passes = 2 * q
     gbs = passes * bytes_a / (ms * 1e-3) / 1e9
 
@@ -135,6 +153,8 @@ def main() -> int:
         tot, cnt = rid.rid_profile_read(h, kid)
         if cnt:
             kern[name] = {"total_ms": tot, "launches": cnt, "avg_ms": tot / cnt}
+    default_cfg = (args.dtype == "c128" and args.prec == "fp64" and (m, n, k, l, q) ==
+                   (131072, 16384, 100, 108, 10))
     rooflines = {}
     for name, src in (("residual_ax", "residual.hip"), ("residual_ahz", "residual.hip")):
         if name in kern:
@@ -142,15 +162,16 @@ def main() -> int:
             ach = bytes_a / avg / 1e9
             rooflines[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-                               "traffic": _traffic(name, src),
+                               "traffic": _traffic(name, src, default_cfg),
                                "algorithmic_bytes_per_launch": bytes_a,
                                "avg_launch_ms": kern[name]["avg_ms"]}
     if "sketch" in kern:
         avg = kern["sketch"]["avg_ms"] * 1e-3
         ach = 8.0 * l * m * n / avg / 1e12
-        rooflines["sketch"] = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFS,
-                               "unit": "TFLOP/s", "frac": ach / FP64_PEAK_TFS,
-                               "traffic": _traffic("sketch", "sketch_f64.hip"),
+        peak = FP64_PEAK_TFS if args.prec == "fp64" else FP32_PEAK_TFS
+        rooflines["sketch"] = {"bound": "mfma", "achieved": ach, "peak": peak,
+                               "unit": "TFLOP/s", "frac": ach / peak,
+                               "traffic": _traffic("sketch", "sketch_f64.hip", default_cfg),
                                "algorithmic_flops_per_launch": 8.0 * l * m * n,
                                "avg_launch_ms": kern["sketch"]["avg_ms"]}
     dominant = max(kern, key=lambda x: kern[x]["total_ms"]) if kern else None
@@ -173,19 +194,22 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if args.prec == "fp64" else "f32 sketch products, f64 QR/solve/residual",
         "data": "synthetic",
-        "config": {"workload": "plain FP64 randomized ID, A = X W + %g N complex128, "
+        "config": {"workload": "%s randomized ID, A = X W + %g N %s, "
                                "%d x %d, k=%d, l=%d, q=%d power steps (%d passes over A)"
-                               % (args.noise, m, n, k, l, q, passes),
-                   "m": m, "n": n, "k": k, "l": l, "q": q, "bytes_A": bytes_a},
+                               % ("plain FP64" if args.prec == "fp64" and args.dtype == "c128"
+                                  else "%s storage, %s sketch" % (args.dtype, args.prec),
+                                  noise, args.dtype, m, n, k, l, q, passes),
+                   "m": m, "n": n, "k": k, "l": l, "q": q, "bytes_A": bytes_a,
+                   "storage": args.dtype, "sketch_products": args.prec},
         "roofline": roof,
         "kernels": kern,
         "rooflines": rooflines,
         "sigma": float(sigma.cpu()[0]),
         "identity_on_J": ok,
     }
-    if not args.no_cpu_baseline and args.cpu_cols > 0:
+    if not args.no_cpu_baseline and args.cpu_cols > 0 and args.dtype == "c128":
         print("timing the CPU oracle on a column sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(A, k, l, q, min(args.cpu_cols, n))
     rid.rid_destroy(h)

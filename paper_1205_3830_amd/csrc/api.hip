@@ -55,10 +55,10 @@ rid_status ensure_ws(rid_handle h, size_t bytes) {
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
-size_t bytes_sketch(int64_t m, int64_t n, int64_t l, bool with_g) {
+size_t bytes_sketch(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t l, bool with_g) {
   WsCarve c(nullptr);
   if (with_g) c.take<double2>(size_t(l) * size_t(m));
-  c.take<double>(sketch_f64_ws_doubles(m, n, l));
+  c.take<char>(sketch_ws_bytes(dt, pr, m, n, l));
   return c.off + 256;
 }
 
@@ -71,11 +71,12 @@ struct DecompWs {
   double *gaps;
   void *scratch;
   double2 *G;
-  double *part;
+  void *part;
 };
 
 template <class C>
-DecompWs carve_decomp(C &c, int64_t m, int64_t n, int64_t k, int64_t l) {
+DecompWs carve_decomp(C &c, rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k,
+                      int64_t l) {
   DecompWs d;
   d.Y = c.template take<double2>(size_t(l) * size_t(n));
   d.perm = c.template take<int64_t>(n);
@@ -84,13 +85,14 @@ DecompWs carve_decomp(C &c, int64_t m, int64_t n, int64_t k, int64_t l) {
   c.off = base;
   d.scratch = c.base ? c.base + base : nullptr;
   d.G = c.template take<double2>(size_t(l) * size_t(m));
-  d.part = c.template take<double>(sketch_f64_ws_doubles(m, n, l));
+  d.part = c.template take<char>(sketch_ws_bytes(dt, pr, m, n, l));
   return d;
 }
 
-size_t bytes_decomp(int64_t m, int64_t n, int64_t k, int64_t l, int q) {
+size_t bytes_decomp(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, int64_t l,
+                    int q) {
   WsCarve c(nullptr);
-  carve_decomp(c, m, n, k, l);
+  carve_decomp(c, dt, pr, m, n, k, l);
   // the region after `scratch` must also hold each later step's workspace
   WsCarve c2(nullptr);
   c2.take<double2>(size_t(l) * size_t(n));
@@ -168,9 +170,13 @@ rid_status rid_reserve(rid_handle h, int64_t max_m, int64_t max_n, int64_t max_l
   if (!h || max_m < 0 || max_n < 0 || max_l < 0 || max_k < 0) return RID_ERR_INVALID_ARG;
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
-  size_t need = bytes_sketch(max_m, max_n, max_l, true);
-  const size_t d = bytes_decomp(max_m, max_n, max_k, max_l, 1);
-  if (d > need) need = d;
+  size_t need = 0;
+  for (rid_prec pr : {RID_FP64, RID_FP32}) {
+    const size_t sk = bytes_sketch(RID_C128, pr, max_m, max_n, max_l, true);
+    const size_t d = bytes_decomp(RID_C128, pr, max_m, max_n, max_k, max_l, 1);
+    if (sk > need) need = sk;
+    if (d > need) need = d;
+  }
   return ensure_ws(h, need);
 }
 
@@ -195,7 +201,7 @@ static rid_status check_sketch_args(rid_handle h, rid_dtype dtype, rid_prec prec
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
   if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
   if (A && !aligned(A, dtype == RID_C128 ? 16 : 8)) return RID_ERR_INVALID_ARG;
-  if (dtype != RID_C128 || prec != RID_FP64) return RID_ERR_UNSUPPORTED;
+  if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
   return RID_OK;
 }
 
@@ -216,13 +222,13 @@ rid_status rid_sketch_explicit(rid_handle h, hipStream_t stream, rid_dtype dtype
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
   if (m == 0) return zero_fill(h, stream, Y, ldy, l, n);
-  s = ensure_ws(h, bytes_sketch(m, n, l, false));
+  s = ensure_ws(h, bytes_sketch(dtype, prec, m, n, l, false));
   if (s != RID_OK) return s;
   WsCarve c(h->ws);
-  double *part = c.take<double>(sketch_f64_ws_doubles(m, n, l));
-  hipError_t e = launch_sketch_f64(stream, m, n, l, static_cast<const double2 *>(A), lda,
-                                   static_cast<const double2 *>(G), ldg,
-                                   static_cast<double2 *>(Y), ldy, part, &h->prof);
+  void *part = c.take<char>(sketch_ws_bytes(dtype, prec, m, n, l));
+  hipError_t e = launch_sketch(stream, dtype, prec, m, n, l, A, lda,
+                               static_cast<const double2 *>(G), ldg, static_cast<double2 *>(Y),
+                               ldy, part, &h->prof);
   return e == hipSuccess ? RID_OK : fail_hip(h, e);
 }
 
@@ -235,15 +241,15 @@ rid_status rid_sketch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_pre
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
   if (m == 0) return zero_fill(h, stream, Y, ldy, l, n);
-  s = ensure_ws(h, bytes_sketch(m, n, l, true));
+  s = ensure_ws(h, bytes_sketch(dtype, prec, m, n, l, true));
   if (s != RID_OK) return s;
   WsCarve c(h->ws);
   double2 *G = c.take<double2>(size_t(l) * size_t(m));
-  double *part = c.take<double>(sketch_f64_ws_doubles(m, n, l));
+  void *part = c.take<char>(sketch_ws_bytes(dtype, prec, m, n, l));
   hipError_t e = launch_gaussian(stream, l, m, seed, 0, G, m);
   if (e != hipSuccess) return fail_hip(h, e);
-  e = launch_sketch_f64(stream, m, n, l, static_cast<const double2 *>(A), lda, G, m,
-                        static_cast<double2 *>(Y), ldy, part, &h->prof);
+  e = launch_sketch(stream, dtype, prec, m, n, l, A, lda, G, m, static_cast<double2 *>(Y), ldy,
+                    part, &h->prof);
   return e == hipSuccess ? RID_OK : fail_hip(h, e);
 }
 
@@ -287,12 +293,12 @@ rid_status rid_residual(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_p
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
   if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
   if (!aligned(A, dtype == RID_C128 ? 16 : 8)) return RID_ERR_INVALID_ARG;
-  if (dtype != RID_C128 || prec != RID_FP64 || k > 1024) return RID_ERR_UNSUPPORTED;
+  if (prec != RID_FP64 || k > 1024) return RID_ERR_UNSUPPORTED;
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
   rid_status s = ensure_ws(h, residual_ws_bytes(m, n, k, q));
   if (s != RID_OK) return s;
-  hipError_t e = launch_residual(stream, m, n, k, static_cast<const double2 *>(A), lda, J,
+  hipError_t e = launch_residual(stream, dtype, m, n, k, A, lda, J,
                                  static_cast<const double2 *>(P), k > 0 ? ldp : 1, q, seed,
                                  sigma, hist, h->ws, &h->prof);
   return e == hipSuccess ? RID_OK : fail_hip(h, e);
@@ -352,20 +358,19 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
   if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
   if (!aligned(A, dtype == RID_C128 ? 16 : 8)) return RID_ERR_INVALID_ARG;
-  if (dtype != RID_C128 || prec != RID_FP64) return RID_ERR_UNSUPPORTED;
+  if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
   if (!pivqr_supported(l) || !interp_supported(k)) return RID_ERR_UNSUPPORTED;
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
-  rid_status s = ensure_ws(h, bytes_decomp(m, n, k, l, q));
+  rid_status s = ensure_ws(h, bytes_decomp(dtype, prec, m, n, k, l, q));
   if (s != RID_OK) return s;
   WsCarve c(h->ws);
-  const DecompWs d = carve_decomp(c, m, n, k, l);
-  const double2 *Ad = static_cast<const double2 *>(A);
+  const DecompWs d = carve_decomp(c, dtype, prec, m, n, k, l);
   for (int attempt = 0; attempt <= max_retries; ++attempt) {
     const uint64_t sd = seed + static_cast<uint64_t>(attempt);
     hipError_t e = launch_gaussian(stream, l, m, sd, 0, d.G, m);
     if (e == hipSuccess)
-      e = launch_sketch_f64(stream, m, n, l, Ad, lda, d.G, m, d.Y, l, d.part, &h->prof);
+      e = launch_sketch(stream, dtype, prec, m, n, l, A, lda, d.G, m, d.Y, l, d.part, &h->prof);
     if (e == hipSuccess)
       e = launch_pivqr(stream, l, n, k, d.Y, l, d.perm, d.gaps, rank_tol, d.scratch,
                        h->d_status, &h->prof);
@@ -381,8 +386,9 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
       e = launch_interp(stream, n, k, d.Y, l, d.perm, static_cast<double2 *>(P), ldp,
                         d.scratch, &h->prof);
     if (e == hipSuccess)
-      e = launch_residual(stream, m, n, k, Ad, lda, d.perm, static_cast<const double2 *>(P),
-                          ldp, q, sd, sigma, nullptr, d.scratch, &h->prof);
+      e = launch_residual(stream, dtype, m, n, k, A, lda, d.perm,
+                          static_cast<const double2 *>(P), ldp, q, sd, sigma, nullptr, d.scratch,
+                          &h->prof);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail_hip(h, e);
     if (seed_used) *seed_used = sd;

@@ -206,57 +206,60 @@ __global__ __launch_bounds__(256) void px_final_kernel(int64_t n, int64_t k, int
   xtl[jt] = make_double2(lr, li);
 }
 
-// z partials: rows [512 rb, +512) x columns of split s
+// Two rows of A, widened to double, at column offset `off` (elements).  For
+// complex128 the thread's rows are i0 and i0 + 256 (two 16-byte loads); for
+// complex64 they are the adjacent rows i0, i0 + 1, read with one 16-byte
+// load when the address is 16-byte aligned (PAIR) and with two 8-byte loads
+// otherwise.
+template <class TA, bool PAIR>
+struct RowPair;
+template <bool PAIR>
+struct RowPair<double2, PAIR> {
+  static constexpr int STEP = 256;  // distance between the thread's two rows
+  static constexpr int LANE = 1;    // rows per thread index
+  RID_DEV static void load(const double2 *p0, const double2 *p1, bool ok0, bool ok1,
+                           int64_t off, double2 &a0, double2 &a1) {
+    a0 = ok0 ? ld_stream(p0 + off) : make_double2(0.0, 0.0);
+    a1 = ok1 ? ld_stream(p1 + off) : make_double2(0.0, 0.0);
+  }
+};
+template <bool PAIR>
+struct RowPair<float2, PAIR> {
+  static constexpr int STEP = 1;
+  static constexpr int LANE = 2;
+  RID_DEV static void load(const float2 *p0, const float2 *p1, bool ok0, bool ok1, int64_t off,
+                           double2 &a0, double2 &a1) {
+    if (PAIR && ok1) {
+      ld_stream_pair(p0 + off, a0, a1);
+    } else {
+      a0 = ok0 ? ld_stream(p0 + off) : make_double2(0.0, 0.0);
+      a1 = ok1 ? ld_stream(p1 + off) : make_double2(0.0, 0.0);
+    }
+  }
+};
+
+// z partials: rows [512 rb, +512) x columns of split s.  TA is the storage
+// type of A (complex128 or complex64, widened to double on load).
+template <class TA, bool PAIR>
 __global__ __launch_bounds__(256) void ax_partial_kernel(int64_t m, int64_t n,
-                                                         const double2 *__restrict__ A,
+                                                         const TA *__restrict__ A,
                                                          int64_t lda,
                                                          const double2 *__restrict__ xth,
                                                          const double2 *__restrict__ xtl,
                                                          int64_t cpz, double *zpart,
                                                          const double *scal) {
+  using RP = RowPair<TA, PAIR>;
   if (stopped(scal)) return;
-  const int64_t i0 = int64_t(blockIdx.x) * AX_ROWS + threadIdx.x;
-  const int64_t i1 = i0 + 256;
+  const int64_t i0 = int64_t(blockIdx.x) * AX_ROWS + RP::LANE * threadIdx.x;
+  const int64_t i1 = i0 + RP::STEP;
   const bool ok0 = i0 < m, ok1 = i1 < m;
   const int64_t jb = int64_t(blockIdx.y) * cpz;
   const int64_t je = min(n, jb + cpz);
   double s0r = 0, c0r = 0, s0i = 0, c0i = 0;
   double s1r = 0, c1r = 0, s1i = 0, c1i = 0;
-  const double2 *a0p = A + (ok0 ? i0 : 0);
-  const double2 *a1p = A + (ok1 ? i1 : 0);
-  int64_t j = jb;
-  for (; j + 4 <= je; j += 4) {
-    double2 a0[4], a1[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      a0[u] = ok0 ? ld_stream(a0p + (j + u) * lda) : make_double2(0.0, 0.0);
-      a1[u] = ok1 ? ld_stream(a1p + (j + u) * lda) : make_double2(0.0, 0.0);
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const double2 xh = xth[j + u], xl = xtl[j + u];
-      dot2_acc(s0r, c0r, a0[u].x, xh.x);
-      dot2_acc(s0r, c0r, -a0[u].y, xh.y);
-      dot2_acc(s0i, c0i, a0[u].x, xh.y);
-      dot2_acc(s0i, c0i, a0[u].y, xh.x);
-      c0r = fma(a0[u].x, xl.x, c0r);
-      c0r = fma(-a0[u].y, xl.y, c0r);
-      c0i = fma(a0[u].x, xl.y, c0i);
-      c0i = fma(a0[u].y, xl.x, c0i);
-      dot2_acc(s1r, c1r, a1[u].x, xh.x);
-      dot2_acc(s1r, c1r, -a1[u].y, xh.y);
-      dot2_acc(s1i, c1i, a1[u].x, xh.y);
-      dot2_acc(s1i, c1i, a1[u].y, xh.x);
-      c1r = fma(a1[u].x, xl.x, c1r);
-      c1r = fma(-a1[u].y, xl.y, c1r);
-      c1i = fma(a1[u].x, xl.y, c1i);
-      c1i = fma(a1[u].y, xl.x, c1i);
-    }
-  }
-  for (; j < je; ++j) {
-    const double2 a0 = ok0 ? ld_stream(a0p + j * lda) : make_double2(0.0, 0.0);
-    const double2 a1 = ok1 ? ld_stream(a1p + j * lda) : make_double2(0.0, 0.0);
-    const double2 xh = xth[j], xl = xtl[j];
+  const TA *a0p = A + (ok0 ? i0 : 0);
+  const TA *a1p = A + (ok1 ? i1 : 0);
+  auto acc = [&](const double2 &a0, const double2 &a1, const double2 &xh, const double2 &xl) {
     dot2_acc(s0r, c0r, a0.x, xh.x);
     dot2_acc(s0r, c0r, -a0.y, xh.y);
     dot2_acc(s0i, c0i, a0.x, xh.y);
@@ -273,6 +276,19 @@ __global__ __launch_bounds__(256) void ax_partial_kernel(int64_t m, int64_t n,
     c1r = fma(-a1.y, xl.y, c1r);
     c1i = fma(a1.x, xl.y, c1i);
     c1i = fma(a1.y, xl.x, c1i);
+  };
+  int64_t j = jb;
+  for (; j + 4 <= je; j += 4) {
+    double2 a0[4], a1[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) RP::load(a0p, a1p, ok0, ok1, (j + u) * lda, a0[u], a1[u]);
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc(a0[u], a1[u], xth[j + u], xtl[j + u]);
+  }
+  for (; j < je; ++j) {
+    double2 a0, a1;
+    RP::load(a0p, a1p, ok0, ok1, j * lda, a0, a1);
+    acc(a0, a1, xth[j], xtl[j]);
   }
   double *zp = zpart + int64_t(blockIdx.y) * m * 4;
   if (ok0) {
@@ -330,13 +346,17 @@ __global__ __launch_bounds__(256) void sigma_final_kernel(int64_t nparts, const 
   }
 }
 
-// u partials: columns [32 cb, +32) x rows of split s; z chunk staged in LDS
+// u partials: columns [32 cb, +32) x rows of split s; z chunk staged in LDS.
+// A lane takes one row per step for complex128 and two adjacent rows (one
+// 16-byte load when aligned) for complex64.
+template <class TA, bool PAIR>
 __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
-                                                          const double2 *__restrict__ A,
+                                                          const TA *__restrict__ A,
                                                           int64_t lda,
                                                           const double2 *__restrict__ z,
                                                           int64_t rpu, double *upart,
                                                           const double *scal) {
+  constexpr bool C64 = sizeof(TA) == 8;
   __shared__ double2 zs[AHZ_RS];
   if (stopped(scal)) return;
   const int64_t r0 = int64_t(blockIdx.y) * rpu;
@@ -348,7 +368,7 @@ __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
   const int wave = threadIdx.x >> 6;
   const int64_t jb = int64_t(blockIdx.x) * AHZ_COLS + wave * AHZ_CPW;
   double sr[AHZ_CPW], cr[AHZ_CPW], si[AHZ_CPW], ci[AHZ_CPW];
-  const double2 *cp[AHZ_CPW];
+  const TA *cp[AHZ_CPW];
   bool cok[AHZ_CPW];
 #pragma unroll
   for (int u = 0; u < AHZ_CPW; ++u) {
@@ -356,18 +376,45 @@ __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
     cok[u] = (jb + u) < n;
     cp[u] = A + (cok[u] ? (jb + u) : 0) * lda + r0;
   }
-  for (int i = lane; i < rows; i += 64) {
-    const double2 zz = zs[i];
-    double2 a[AHZ_CPW];
+  auto acc = [&](int u, const double2 &a, const double2 &zz) {
+    // conj(a) z = (ar zr + ai zi) + i (ar zi - ai zr)
+    dot2_acc(sr[u], cr[u], a.x, zz.x);
+    dot2_acc(sr[u], cr[u], a.y, zz.y);
+    dot2_acc(si[u], ci[u], a.x, zz.y);
+    dot2_acc(si[u], ci[u], -a.y, zz.x);
+  };
+  if (!C64) {
+    for (int i = lane; i < rows; i += 64) {
+      const double2 zz = zs[i];
+      double2 a[AHZ_CPW];
 #pragma unroll
-    for (int u = 0; u < AHZ_CPW; ++u) a[u] = cok[u] ? ld_stream(cp[u] + i) : make_double2(0.0, 0.0);
+      for (int u = 0; u < AHZ_CPW; ++u)
+        a[u] = cok[u] ? ld_stream(cp[u] + i) : make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < AHZ_CPW; ++u) {
-      // conj(a) z = (ar zr + ai zi) + i (ar zi - ai zr)
-      dot2_acc(sr[u], cr[u], a[u].x, zz.x);
-      dot2_acc(sr[u], cr[u], a[u].y, zz.y);
-      dot2_acc(si[u], ci[u], a[u].x, zz.y);
-      dot2_acc(si[u], ci[u], -a[u].y, zz.x);
+      for (int u = 0; u < AHZ_CPW; ++u) acc(u, a[u], zz);
+    }
+  } else {
+    for (int i = 2 * lane; i < rows; i += 128) {
+      const bool two = i + 1 < rows;
+      const double2 z0 = zs[i];
+      const double2 z1 = two ? zs[i + 1] : make_double2(0.0, 0.0);
+      double2 a0[AHZ_CPW], a1[AHZ_CPW];
+#pragma unroll
+      for (int u = 0; u < AHZ_CPW; ++u) {
+        if (!cok[u]) {
+          a0[u] = a1[u] = make_double2(0.0, 0.0);
+        } else if (PAIR && two) {
+          ld_stream_pair(reinterpret_cast<const float2 *>(cp[u]) + i, a0[u], a1[u]);
+        } else {
+          a0[u] = ld_stream(cp[u] + i);
+          a1[u] = two ? ld_stream(cp[u] + i + 1) : make_double2(0.0, 0.0);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < AHZ_CPW; ++u) {
+        acc(u, a0[u], z0);
+        acc(u, a1[u], z1);
+      }
     }
   }
 #pragma unroll
@@ -458,10 +505,10 @@ size_t residual_ws_bytes(int64_t m, int64_t n, int64_t k, int q) {
   return c.off + 256;
 }
 
-hipError_t launch_residual(hipStream_t st, int64_t m, int64_t n, int64_t k,
-                           const double2 *A, int64_t lda, const int64_t *J,
-                           const double2 *P, int64_t ldp, int q, uint64_t seed,
-                           double *sigma, double *hist, void *ws, RidProf *prof) {
+template <class TA, bool PAIR>
+hipError_t residual_impl(hipStream_t st, int64_t m, int64_t n, int64_t k, const TA *A,
+                         int64_t lda, const int64_t *J, const double2 *P, int64_t ldp, int q,
+                         uint64_t seed, double *sigma, double *hist, void *ws, RidProf *prof) {
   if (k > RES_KMAX) return hipErrorInvalidValue;
   const ResPlan p = plan_res(m, n);
   WsCarve c(ws);
@@ -482,7 +529,7 @@ hipError_t launch_residual(hipStream_t st, int64_t m, int64_t n, int64_t k,
     }
     {
       ProfScope ps(prof, st, RID_KERNEL_AX);
-      hipLaunchKernelGGL(ax_partial_kernel,
+      hipLaunchKernelGGL((ax_partial_kernel<TA, PAIR>),
                          dim3(static_cast<unsigned>(p.nb_ax), static_cast<unsigned>(p.S_z)),
                          blk, 0, st, m, n, A, lda, w.xth, w.xtl, p.cpz, w.zpart, w.scal);
     }
@@ -493,7 +540,7 @@ hipError_t launch_residual(hipStream_t st, int64_t m, int64_t n, int64_t k,
     if (t + 1 < q) {
       {
         ProfScope ps(prof, st, RID_KERNEL_AHZ);
-        hipLaunchKernelGGL(ahz_partial_kernel,
+        hipLaunchKernelGGL((ahz_partial_kernel<TA, PAIR>),
                            dim3(static_cast<unsigned>((n + AHZ_COLS - 1) / AHZ_COLS),
                                 static_cast<unsigned>(p.S_u)),
                            blk, 0, st, m, n, A, lda, w.z, p.rpu, w.upart, w.scal);
@@ -507,4 +554,21 @@ hipError_t launch_residual(hipStream_t st, int64_t m, int64_t n, int64_t k,
     }
   }
   return hipGetLastError();
+}
+
+hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t k,
+                           const void *A, int64_t lda, const int64_t *J, const double2 *P,
+                           int64_t ldp, int q, uint64_t seed, double *sigma, double *hist,
+                           void *ws, RidProf *prof) {
+  if (dtype == RID_C64) {
+    // pairs of adjacent entries are 16-byte aligned when A is and lda is even
+    const bool pair = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
+    if (pair)
+      return residual_impl<float2, true>(st, m, n, k, static_cast<const float2 *>(A), lda, J, P,
+                                         ldp, q, seed, sigma, hist, ws, prof);
+    return residual_impl<float2, false>(st, m, n, k, static_cast<const float2 *>(A), lda, J, P,
+                                        ldp, q, seed, sigma, hist, ws, prof);
+  }
+  return residual_impl<double2, false>(st, m, n, k, static_cast<const double2 *>(A), lda, J, P,
+                                       ldp, q, seed, sigma, hist, ws, prof);
 }

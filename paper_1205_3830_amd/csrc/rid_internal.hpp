@@ -129,6 +129,31 @@ RID_DEV double2 ld_stream(const double2 *p) {
   return make_double2(v.x, v.y);
 }
 
+// complex64 streaming load, widened to double
+typedef float rid_fv2 __attribute__((ext_vector_type(2)));
+RID_DEV double2 ld_stream(const float2 *p) {
+  const rid_fv2 v = __builtin_nontemporal_load(reinterpret_cast<const rid_fv2 *>(p));
+  return make_double2(static_cast<double>(v.x), static_cast<double>(v.y));
+}
+
+// two adjacent complex64 entries in one 16-byte non-temporal load (p must be
+// 16-byte aligned)
+typedef float rid_fv4 __attribute__((ext_vector_type(4)));
+RID_DEV void ld_stream_pair(const float2 *p, double2 &a, double2 &b) {
+  const rid_fv4 v = __builtin_nontemporal_load(reinterpret_cast<const rid_fv4 *>(p));
+  a = make_double2(static_cast<double>(v.x), static_cast<double>(v.y));
+  b = make_double2(static_cast<double>(v.z), static_cast<double>(v.w));
+}
+
+RID_DEV double2 to_d2(double2 v) { return v; }
+RID_DEV double2 to_d2(float2 v) {
+  return make_double2(static_cast<double>(v.x), static_cast<double>(v.y));
+}
+RID_DEV float2 to_f2(double2 v) {
+  return make_float2(static_cast<float>(v.x), static_cast<float>(v.y));
+}
+RID_DEV float2 to_f2(float2 v) { return v; }
+
 // Error-free transformations (Knuth TwoSum; TwoProd through FMA).  Each
 // helper turns off FMA contraction: fusing the product a*b into a following
 // sum would make the rounded product and its error term disagree.
@@ -195,12 +220,26 @@ hipError_t launch_zero(hipStream_t st, int64_t rows, int64_t cols, double2 *out,
 hipError_t launch_gaussian(hipStream_t st, int64_t rows, int64_t cols, uint64_t seed,
                            uint32_t stream_id, double2 *out, int64_t ld);
 
-// Y = G A in double, G row-major (l x m, ldg), A column-major (m x n, lda).
-// part: workspace of sketch_f64_ws_doubles(m, n, l) doubles.
-size_t sketch_f64_ws_doubles(int64_t m, int64_t n, int64_t l);
-hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l,
-                             const double2 *A, int64_t lda, const double2 *G, int64_t ldg,
-                             double2 *Y, int64_t ldy, double *part, RidProf *prof);
+// Y (complex128) = G A, G complex128 row-major (l x m, ldg), A column-major
+// (m x n, lda) of storage type `dtype`, products in precision `prec`.
+// part: workspace of sketch_ws_bytes(...) bytes.
+bool sketch_supported(rid_dtype dtype, rid_prec prec);
+size_t sketch_ws_bytes(rid_dtype dtype, rid_prec prec, int64_t m, int64_t n, int64_t l);
+hipError_t launch_sketch(hipStream_t st, rid_dtype dtype, rid_prec prec, int64_t m, int64_t n,
+                         int64_t l, const void *A, int64_t lda, const double2 *G, int64_t ldg,
+                         double2 *Y, int64_t ldy, void *part, RidProf *prof);
+
+// per-precision launchers behind launch_sketch
+size_t sketch_f64_ws_bytes(int64_t m, int64_t n, int64_t l);
+template <class TA>
+hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
+                             int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
+                             int64_t ldy, void *part, RidProf *prof);
+size_t sketch_f32_ws_bytes(int64_t m, int64_t n, int64_t l);
+template <class TA>
+hipError_t launch_sketch_f32(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
+                             int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
+                             int64_t ldy, void *part, RidProf *prof);
 
 // Pivoted QR workspace and launch.
 size_t pivqr_ws_bytes(int64_t l, int64_t n);
@@ -216,7 +255,7 @@ hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R,
                          RidProf *prof);
 
 size_t residual_ws_bytes(int64_t m, int64_t n, int64_t k, int q);
-hipError_t launch_residual(hipStream_t st, int64_t m, int64_t n, int64_t k,
-                           const double2 *A, int64_t lda, const int64_t *J,
+hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t k,
+                           const void *A, int64_t lda, const int64_t *J,
                            const double2 *P, int64_t ldp, int q, uint64_t seed,
                            double *sigma, double *hist, void *ws, RidProf *prof);

@@ -1,0 +1,258 @@
+// sketch_f32.hip -- randomization step Y = G A (Sec. 2) with single-precision
+// products on the FP32 matrix cores (v_mfma_f32_16x16x4f32), FP32
+// accumulation within a K split, and the K splits summed in double into the
+// complex128 Y.  The reduced-precision form of the sketch: the pivoted QR,
+// the triangular solve and the residual that follow stay in double.
+//
+// Same real embedding and tiling as the double-precision kernel
+// (sketch_f64.hip): a workgroup of 4 waves owns 64 columns of A and MT
+// 16-row tiles of Yr; lane (r16, q) holds four consecutive complex entries
+// of its column for each 16-row K step and k-slot q of MFMA s stands for
+// real row 8q + s.  G (complex128 in memory) is rounded to complex64 as it
+// is staged into LDS, double buffered, row stride 17 entries.  The FP32 MFMA
+// output layout differs from the FP64 one: lane l, register r holds row
+// 4 (l / 16) + r, column l % 16 (measured on gfx950).
+#include "rid_internal.hpp"
+
+namespace {
+
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <int MT, class TA>
+__global__ __launch_bounds__(256) void sketch_f32_kernel(
+    int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
+    const double2 *__restrict__ G, int64_t ldg, float *__restrict__ out, int64_t ldo,
+    int64_t split_stride, int64_t pchunk) {
+  constexpr int NR = 8 * MT;
+  constexpr int RS = 17;
+  constexpr int PER = (NR * 16 + 255) / 256;
+  __shared__ float2 gs[2][NR * RS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int q = lane >> 4;
+  const int r16 = lane & 15;
+  const int c = lane & 1;
+  const int64_t jcol = int64_t(blockIdx.x) * 64 + wave * 16 + r16;
+  const bool colok = jcol < n;
+  const int64_t pbeg = int64_t(blockIdx.y) * pchunk;
+  const int64_t pend = min(m, pbeg + pchunk);
+  const int64_t g0 = int64_t(blockIdx.z) * NR;
+
+  f4 acc[MT];
+#pragma unroll
+  for (int t = 0; t < MT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  const TA *Acol = A + (colok ? jcol : 0) * lda;
+  float2 stg[PER];
+  auto load_g = [&](int64_t p0) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 256 * r;
+      const int row = e >> 4, col = e & 15;
+      const int64_t i = g0 + row, p = p0 + col;
+      stg[r] = (e < NR * 16 && i < l && p < pend) ? to_f2(G[i * ldg + p])
+                                                  : make_float2(0.0f, 0.0f);
+    }
+  };
+  auto store_g = [&](int b) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 256 * r;
+      if (e < NR * 16) gs[b][(e >> 4) * RS + (e & 15)] = stg[r];
+    }
+  };
+  auto load_a = [&](int64_t p0, float2 *a4) {
+    const int64_t pb = p0 + 4 * q;
+    if (colok && pb + 4 <= pend) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] = to_f2(Acol[pb + u]);
+    } else {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        a4[u] = (colok && pb + u < pend) ? to_f2(Acol[pb + u]) : make_float2(0.0f, 0.0f);
+    }
+  };
+
+  float2 a4[4], an[4];
+  load_g(pbeg);
+  store_g(0);
+  load_a(pbeg, a4);
+  __syncthreads();
+  int b = 0;
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
+    const bool more = p0 + 16 < pend;
+    if (more) {
+      load_g(p0 + 16);
+      load_a(p0 + 16, an);
+    }
+    const float2 *gb = gs[b];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      const int row = 8 * t + (r16 >> 1);
+      float2 g4[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) g4[u] = gb[row * RS + 4 * q + u];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const float o0 = c ? g4[u].y : g4[u].x;
+        const float o1 = c ? g4[u].x : -g4[u].y;
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(o0, a4[u].x, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(o1, a4[u].y, acc[t], 0, 0, 0);
+      }
+    }
+    if (more) {
+      store_g(b ^ 1);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a4[u] = an[u];
+    }
+    __syncthreads();
+    b ^= 1;
+  }
+  if (!colok) return;
+  float *o = out + int64_t(blockIdx.y) * split_stride + jcol * ldo;
+  const int64_t rows = 2 * l;
+  const int64_t mu0 = 2 * g0;
+#pragma unroll
+  for (int t = 0; t < MT; ++t)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t mu = mu0 + int64_t(t) * 16 + 4 * q + r;
+      if (mu < rows) o[mu] = acc[t][r];
+    }
+}
+
+// Y(mu, j) = sum over splits (in order, in double) of part[s](mu, j).
+__global__ __launch_bounds__(256) void sketch_f32_reduce_kernel(int64_t rows, int64_t n, int S,
+                                                                const float *__restrict__ part,
+                                                                double *__restrict__ Y,
+                                                                int64_t ldy2) {
+  const int64_t total = rows * n;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = e / rows;
+    const int64_t mu = e - j * rows;
+    double s = 0.0;
+    for (int sp = 0; sp < S; ++sp) s += static_cast<double>(part[sp * total + e]);
+    Y[j * ldy2 + mu] = s;
+  }
+}
+
+struct Plan32 {
+  int MT, nbz;
+  int64_t nbx;
+  int S;
+  int64_t pchunk;
+};
+
+int pick_mt32(int64_t tiles) {
+  static const int options[] = {1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16,
+                                18, 20, 22, 24, 26, 28};
+  for (int o : options)
+    if (o >= tiles) return o;
+  return 16;
+}
+
+Plan32 plan32(int64_t m, int64_t n, int64_t l) {
+  Plan32 p;
+  const int64_t tiles = (2 * l + 15) / 16;
+  p.MT = pick_mt32(tiles);
+  p.nbz = static_cast<int>((tiles + p.MT - 1) / p.MT);
+  p.nbx = (n + 63) / 64;
+  const int64_t base = p.nbx * p.nbz;
+  int64_t S = (2048 + base - 1) / base;
+  const int64_t maxS = (m + 255) / 256;
+  if (S > maxS) S = maxS;
+  if (S < 1) S = 1;
+  int64_t pchunk = (m + S - 1) / S;
+  pchunk = (pchunk + 15) / 16 * 16;
+  if (pchunk < 16) pchunk = 16;
+  S = (m + pchunk - 1) / pchunk;
+  if (S < 1) S = 1;
+  p.S = static_cast<int>(S);
+  p.pchunk = pchunk;
+  return p;
+}
+
+template <int MT, class TA>
+void launch32(hipStream_t st, const Plan32 &p, int64_t m, int64_t n, int64_t l, const TA *A,
+              int64_t lda, const double2 *G, int64_t ldg, float *part) {
+  dim3 grid(static_cast<unsigned>(p.nbx), static_cast<unsigned>(p.S),
+            static_cast<unsigned>(p.nbz));
+  hipLaunchKernelGGL((sketch_f32_kernel<MT, TA>), grid, dim3(256), 0, st, m, n, l, A, lda, G,
+                     ldg, part, 2 * l, 2 * l * n, p.pchunk);
+}
+
+}  // namespace
+
+size_t sketch_f32_ws_bytes(int64_t m, int64_t n, int64_t l) {
+  const Plan32 p = plan32(m, n, l);
+  return size_t(p.S) * size_t(2 * l) * size_t(n) * sizeof(float);
+}
+
+template <class TA>
+hipError_t launch_sketch_f32(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
+                             int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
+                             int64_t ldy, void *partv, RidProf *prof) {
+  if (n == 0 || l == 0) return hipSuccess;
+  float *part = static_cast<float *>(partv);
+  const Plan32 p = plan32(m, n, l);
+  ProfScope ps(prof, st, RID_KERNEL_SKETCH);
+  switch (p.MT) {
+#define RID_MT_CASE(X) \
+  case X:              \
+    launch32<X, TA>(st, p, m, n, l, A, lda, G, ldg, part); \
+    break;
+    RID_MT_CASE(1) RID_MT_CASE(2) RID_MT_CASE(3) RID_MT_CASE(4) RID_MT_CASE(5)
+    RID_MT_CASE(6) RID_MT_CASE(7) RID_MT_CASE(8) RID_MT_CASE(9) RID_MT_CASE(10)
+    RID_MT_CASE(11) RID_MT_CASE(12) RID_MT_CASE(13) RID_MT_CASE(14) RID_MT_CASE(15)
+    RID_MT_CASE(16) RID_MT_CASE(18) RID_MT_CASE(20) RID_MT_CASE(22) RID_MT_CASE(24)
+    RID_MT_CASE(26) RID_MT_CASE(28)
+#undef RID_MT_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  ps.stop();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = 2 * l * n;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(sketch_f32_reduce_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                     st, 2 * l, n, p.S, part, reinterpret_cast<double *>(Y), 2 * ldy);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sketch_f32<double2>(hipStream_t, int64_t, int64_t, int64_t,
+                                               const double2 *, int64_t, const double2 *,
+                                               int64_t, double2 *, int64_t, void *, RidProf *);
+template hipError_t launch_sketch_f32<float2>(hipStream_t, int64_t, int64_t, int64_t,
+                                              const float2 *, int64_t, const double2 *, int64_t,
+                                              double2 *, int64_t, void *, RidProf *);
+
+// ---------------------------------------------------------------- dispatch
+bool sketch_supported(rid_dtype dtype, rid_prec prec) {
+  return (dtype == RID_C128 || dtype == RID_C64) && (prec == RID_FP64 || prec == RID_FP32);
+}
+
+size_t sketch_ws_bytes(rid_dtype dtype, rid_prec prec, int64_t m, int64_t n, int64_t l) {
+  (void)dtype;
+  return prec == RID_FP32 ? sketch_f32_ws_bytes(m, n, l) : sketch_f64_ws_bytes(m, n, l);
+}
+
+hipError_t launch_sketch(hipStream_t st, rid_dtype dtype, rid_prec prec, int64_t m, int64_t n,
+                         int64_t l, const void *A, int64_t lda, const double2 *G, int64_t ldg,
+                         double2 *Y, int64_t ldy, void *part, RidProf *prof) {
+  if (prec == RID_FP32) {
+    if (dtype == RID_C64)
+      return launch_sketch_f32(st, m, n, l, static_cast<const float2 *>(A), lda, G, ldg, Y, ldy,
+                               part, prof);
+    return launch_sketch_f32(st, m, n, l, static_cast<const double2 *>(A), lda, G, ldg, Y, ldy,
+                             part, prof);
+  }
+  if (dtype == RID_C64)
+    return launch_sketch_f64(st, m, n, l, static_cast<const float2 *>(A), lda, G, ldg, Y, ldy,
+                             part, prof);
+  return launch_sketch_f64(st, m, n, l, static_cast<const double2 *>(A), lda, G, ldg, Y, ldy,
+                           part, prof);
+}

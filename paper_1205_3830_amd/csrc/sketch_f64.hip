@@ -26,9 +26,9 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-template <int MT>
+template <int MT, class TA>
 __global__ __launch_bounds__(256) void sketch_f64_kernel(
-    int64_t m, int64_t n, int64_t l, const double2 *__restrict__ A, int64_t lda,
+    int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
     const double2 *__restrict__ G, int64_t ldg, double *__restrict__ out, int64_t ldo,
     int64_t split_stride, int64_t pchunk) {
   constexpr int NR = 8 * MT;                       // G rows of the slab
@@ -51,7 +51,7 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(
 #pragma unroll
   for (int t = 0; t < MT; ++t) acc[t] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const double2 *Acol = A + (colok ? jcol : 0) * lda;
+  const TA *Acol = A + (colok ? jcol : 0) * lda;
   double2 stg[PER];
   auto load_g = [&](int64_t p0) {
 #pragma unroll
@@ -73,11 +73,11 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(
     const int64_t pb = p0 + 4 * q;
     if (colok && pb + 4 <= pend) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a4[u] = Acol[pb + u];
+      for (int u = 0; u < 4; ++u) a4[u] = to_d2(Acol[pb + u]);
     } else {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        a4[u] = (colok && pb + u < pend) ? Acol[pb + u] : make_double2(0.0, 0.0);
+        a4[u] = (colok && pb + u < pend) ? to_d2(Acol[pb + u]) : make_double2(0.0, 0.0);
     }
   };
 
@@ -186,27 +186,29 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t l) {
   return p;
 }
 
-template <int MT>
+template <int MT, class TA>
 void launch_mt(hipStream_t st, const SketchPlan &p, int64_t m, int64_t n, int64_t l,
-               const double2 *A, int64_t lda, const double2 *G, int64_t ldg, double *out,
+               const TA *A, int64_t lda, const double2 *G, int64_t ldg, double *out,
                int64_t ldo, int64_t split_stride) {
   dim3 grid(static_cast<unsigned>(p.nbx), static_cast<unsigned>(p.S),
             static_cast<unsigned>(p.nbz));
-  hipLaunchKernelGGL(sketch_f64_kernel<MT>, grid, dim3(256), 0, st, m, n, l, A, lda, G, ldg,
-                     out, ldo, split_stride, p.pchunk);
+  hipLaunchKernelGGL((sketch_f64_kernel<MT, TA>), grid, dim3(256), 0, st, m, n, l, A, lda, G,
+                     ldg, out, ldo, split_stride, p.pchunk);
 }
 
 }  // namespace
 
-size_t sketch_f64_ws_doubles(int64_t m, int64_t n, int64_t l) {
+size_t sketch_f64_ws_bytes(int64_t m, int64_t n, int64_t l) {
   const SketchPlan p = plan_sketch(m, n, l);
   if (p.S <= 1) return 0;
-  return size_t(p.S) * size_t(2 * l) * size_t(n);
+  return size_t(p.S) * size_t(2 * l) * size_t(n) * sizeof(double);
 }
 
-hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l,
-                             const double2 *A, int64_t lda, const double2 *G, int64_t ldg,
-                             double2 *Y, int64_t ldy, double *part, RidProf *prof) {
+template <class TA>
+hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
+                             int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
+                             int64_t ldy, void *partv, RidProf *prof) {
+  double *part = static_cast<double *>(partv);
   if (n == 0 || l == 0) return hipSuccess;
   const SketchPlan p = plan_sketch(m, n, l);
   double *out;
@@ -224,7 +226,7 @@ hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l,
   switch (p.MT) {
 #define RID_MT_CASE(X) \
   case X:              \
-    launch_mt<X>(st, p, m, n, l, A, lda, G, ldg, out, ldo, split_stride); \
+    launch_mt<X, TA>(st, p, m, n, l, A, lda, G, ldg, out, ldo, split_stride); \
     break;
     RID_MT_CASE(1) RID_MT_CASE(2) RID_MT_CASE(3) RID_MT_CASE(4) RID_MT_CASE(5)
     RID_MT_CASE(6) RID_MT_CASE(7) RID_MT_CASE(8) RID_MT_CASE(9) RID_MT_CASE(10)
@@ -245,3 +247,10 @@ hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l,
                      st, 2 * l, n, p.S, part, reinterpret_cast<double *>(Y), 2 * ldy);
   return hipGetLastError();
 }
+
+template hipError_t launch_sketch_f64<double2>(hipStream_t, int64_t, int64_t, int64_t,
+                                               const double2 *, int64_t, const double2 *,
+                                               int64_t, double2 *, int64_t, void *, RidProf *);
+template hipError_t launch_sketch_f64<float2>(hipStream_t, int64_t, int64_t, int64_t,
+                                              const float2 *, int64_t, const double2 *, int64_t,
+                                              double2 *, int64_t, void *, RidProf *);

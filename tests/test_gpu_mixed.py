@@ -1,0 +1,122 @@
+"""GPU parity of the reduced-precision form: A stored complex64, sketch
+products in FP32 (single-precision accumulation within a K split), QR,
+triangular solve and residual sums in double.  The oracle runs in double on
+exactly the same complex64 values (converted to complex128, which is exact).
+
+Stated accuracy of the FP32 sketch, against the double oracle:
+  Y      : ||dY||_F <= 2e-5 ||Y||_F  (u32 sqrt(K) per split, splits summed in double)
+  J      : equal at every step whose relative pivot gap exceeds 1e-4
+  P      : max|dP| <= 1e-3 max(1, max|P|)   (kappa(R1) times the Y error)
+  sigma  : within a factor 2 of the oracle's (the ID error is dominated by
+           sigma_{k+1}, set to 1e-3 of ||A||_2 here)
+Everything computed in double on complex64 storage (the residual, and the
+sketch with RID_FP64 products) keeps the double-precision bars.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+rid = pytest.importorskip("paper_1205_3830_amd")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = rid.rid_create(0)
+    yield hd
+    rid.rid_destroy(hd)
+
+
+def dev(A):
+    A = np.asarray(A)
+    return torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda").t()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def lowrank64(m, n, k, rho, seed):
+    """complex64 A with sigma_{k+1} ~ rho ||A||_2."""
+    A = synth.lowrank(m, n, k, 0.0, seed=seed)
+    nrm = np.linalg.norm(A, 2)
+    c = rho * nrm / (np.sqrt(m) + np.sqrt(n))
+    A = synth.lowrank(m, n, k, c, seed=seed)
+    return np.asfortranarray(A.astype(np.complex64))
+
+
+@pytest.mark.parametrize("m,n,l", [(1000, 500, 30), (1037, 131, 30), (600, 97, 108)])
+def test_sketch_fp64_products_on_complex64(h, m, n, l):
+    A = lowrank64(m, n, 8, 1e-3, seed=m)
+    G = oracle.sketch_operator(l, m, seed=1)
+    Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda(), prec=rid.RID_FP64))
+    ref = oracle.sketch(A.astype(np.complex128), G)
+    assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+@pytest.mark.parametrize("dt", [np.complex64, np.complex128])
+@pytest.mark.parametrize("m,n,l", [(1000, 500, 30), (4096, 300, 108), (333, 65, 208)])
+def test_sketch_fp32_products(h, dt, m, n, l):
+    A = lowrank64(m, n, 8, 1e-3, seed=n).astype(dt)
+    G = oracle.sketch_operator(l, m, seed=2)
+    Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda(), prec=rid.RID_FP32))
+    ref = oracle.sketch(A.astype(np.complex128), G)
+    err = np.linalg.norm(Y - ref) / np.linalg.norm(ref)
+    assert err <= 2e-5, err
+    assert err > 0.0          # the products really are single precision
+
+
+@pytest.mark.parametrize("m,n,k,l,q", [(1000, 500, 20, 30, 8), (777, 333, 9, 17, 6)])
+def test_residual_complex64_call_for_call(h, m, n, k, l, q):
+    A = lowrank64(m, n, k, 1e-3, seed=k)
+    A128 = A.astype(np.complex128)
+    r = oracle.decompose(A128, k, l, seed=3, q=q)
+    sigma, hist = rid.rid_residual(h, dev(A), torch.from_numpy(r["J"]).cuda(), dev(r["P"]), q, 3)
+    assert abs(float(host(sigma)[0]) - r["sigma"]) <= 1e-10 * r["sigma"]
+    assert np.all(np.abs(host(hist) - r["hist"]) <= 1e-10 * r["hist"])
+
+
+@pytest.mark.parametrize("m,n,k,l", [(1000, 500, 20, 30), (2048, 700, 64, 72)])
+def test_decompose_complex64_fp32(h, m, n, k, l):
+    A = lowrank64(m, n, k, 1e-3, seed=m + k)
+    A128 = A.astype(np.complex128)
+    ref = oracle.decompose(A128, k, l, seed=0, q=8)
+    J, P, sigma, used = rid.rid_decompose(h, dev(A), k, l, seed=0, q=8, prec=rid.RID_FP32,
+                                          rank_tol=1e-5)
+    J, P, s = host(J), host(P), float(host(sigma)[0])
+    assert used == ref["seed_used"]
+    for t in range(k):
+        if ref["gaps"][t] <= 1e-4:
+            break
+        assert J[t] == ref["J"][t], t
+    assert np.array_equal(P[:, J], np.eye(k))
+    if np.array_equal(J, ref["J"]):
+        assert np.abs(P - ref["P"]).max() <= 1e-3 * max(1.0, np.abs(ref["P"]).max())
+    assert 0.5 * ref["sigma"] <= s <= 2.0 * ref["sigma"]
+
+
+def test_decompose_complex64_fp64_matches_double_oracle(h):
+    m, n, k, l = 1000, 500, 20, 30
+    A = lowrank64(m, n, k, 1e-3, seed=5)
+    ref = oracle.decompose(A.astype(np.complex128), k, l, seed=0, q=8)
+    J, P, sigma, used = rid.rid_decompose(h, dev(A), k, l, seed=0, q=8, prec=rid.RID_FP64)
+    J, P, s = host(J), host(P), float(host(sigma)[0])
+    assert np.array_equal(J, ref["J"])
+    dP = P - ref["P"]
+    assert np.abs(dP).max() <= 1e-10 * max(1.0, np.abs(ref["P"]).max())
+    A128 = A.astype(np.complex128)
+    tol = 1e-10 * ref["sigma"] + 2 * np.linalg.norm(A128[:, J]) * np.linalg.norm(dP)
+    assert abs(s - ref["sigma"]) <= tol
+
+
+def test_bf16x3_not_built_yet_is_reported(h):
+    A = dev(lowrank64(100, 40, 4, 1e-3, seed=1))
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_sketch(h, A, 8, 0, prec=rid.RID_BF16X3)
+    assert ei.value.status == rid.RID_ERR_UNSUPPORTED

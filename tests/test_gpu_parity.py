@@ -259,5 +259,5 @@ def test_invalid_arguments_rejected(h):
         rid.rid_decompose(h, A, 3, 5, seed=0, q=0)     # q < 1
     assert ei.value.status == rid.RID_ERR_INVALID_ARG
     with pytest.raises(rid.RidError) as ei:
-        rid.rid_decompose(h, A.to(torch.complex64), 3, 5, seed=0)
+        rid.rid_decompose(h, A, 3, 5, seed=0, prec=rid.RID_BF16X3)
     assert ei.value.status == rid.RID_ERR_UNSUPPORTED
