@@ -113,10 +113,36 @@ rid_status rid_reserve(rid_handle h, int64_t max_m, int64_t max_n, int64_t max_l
 rid_status rid_gaussian(rid_handle h, hipStream_t stream, int64_t rows, int64_t cols,
                         uint64_t seed, uint32_t stream_id, void *out, int64_t ld);
 
-/* Randomization step (Sec. 2) with the Gaussian operator of `seed`:
+/* Kind of random operator that rid_sketch and rid_decompose draw. */
+typedef enum {
+  RID_SKETCH_GAUSSIAN = 0, /* complex Gaussian G (rid_gaussian, stream 0); default */
+  RID_SKETCH_SRFT = 1      /* the paper's S F D (rid_srft_operator)              */
+} rid_sketch_kind;
+
+/* Select the operator kind of this handle's later rid_sketch and
+ * rid_decompose calls (Sec. 2 names S F D and allows a faster
+ * randomization in its place).  Errors: INVALID_ARG.                     */
+rid_status rid_set_sketch(rid_handle h, int kind);
+
+/* The paper's randomization operator (Sec. 2, eqs. (4)-(7)) written out as
+ * rows x m complex128, row-major (entry (i, p) at out[i * ld + p], ld >= m):
+ *   out(i, p) = exp(2 pi i (phi_p - (s_i p mod m) / m)),
+ * i.e. row s_i of the unnormalised DFT F times D = diag(exp(2 pi i phi_p)).
+ * phi_p = the first uniform (u1 of rid_gaussian's construction) of the
+ * Philox block with counter (p, 0, 0, 5); s_i = floor(u1 m) of the block
+ * with counter (i, 0, 0, 6) -- rows are drawn i.i.d. with replacement, as
+ * eq. (5) specifies.  Applying it costs 8 rows m n flops like the Gaussian
+ * operator; the FFT of eq. (6) is never formed.  Requires 1 <= m < 2^31.
+ * Errors: INVALID_ARG, HIP.                                               */
+rid_status rid_srft_operator(rid_handle h, hipStream_t stream, int64_t rows, int64_t m,
+                             uint64_t seed, void *out, int64_t ld);
+
+/* Randomization step (Sec. 2) with the operator of `seed` (the handle's
+ * kind, Gaussian unless rid_set_sketch chose S F D):
  *   Y (l x n complex128, ldy >= l) = G(seed) (l x m) * A (m x n, lda >= m).
  * A is complex128 or complex64 per `dtype`; `prec` selects the product
- * arithmetic.  G is drawn into the handle's workspace (16 l m bytes).
+ * arithmetic.  The operator is drawn into the handle's workspace (16 l m
+ * bytes).
  * Requires 1 <= l, 0 <= m, 0 <= n; A 16-byte aligned for RID_C128 (8 for
  * RID_C64), Y 16-byte aligned.  Errors: INVALID_ARG, UNSUPPORTED (dtype/prec
  * pair not built), NOMEM, HIP.                                            */

@@ -63,6 +63,11 @@ def _load():
                                         ctypes.c_uint64, P]
         lib.orc_gaussian_rowmajor.argtypes = [I64, I64, ctypes.c_uint64, ctypes.c_uint32, P, I64]
         lib.orc_sketch.argtypes = [I64, I64, I64, P, I64, P, I64, P, I64]
+        lib.orc_srft_operator.argtypes = [I64, I64, ctypes.c_uint64, P, I64]
+        lib.orc_srft_row.argtypes = [ctypes.c_uint64, ctypes.c_uint64, I64]
+        lib.orc_srft_row.restype = I64
+        lib.orc_srft_phase.argtypes = [ctypes.c_uint64, ctypes.c_uint64]
+        lib.orc_srft_phase.restype = ctypes.c_double
         lib.orc_sketch_seeded.argtypes = [I64, I64, I64, P, I64, ctypes.c_uint64, P, I64]
         lib.orc_select.argtypes = [I64, I64, I64, P, I64, ctypes.c_double, P, P, I64, P]
         lib.orc_select.restype = ctypes.c_int
@@ -111,6 +116,24 @@ def gaussian(rows: int, cols: int, seed: int, stream: int) -> np.ndarray:
 def sketch_operator(l: int, m: int, seed: int) -> np.ndarray:
     """The l x m Gaussian sketch operator G (stream 0)."""
     return gaussian(l, m, seed, 0)
+
+
+def srft_rows(l: int, m: int, seed: int) -> np.ndarray:
+    """Rows s_0..s_{l-1} kept by S (eq. (5)), i.i.d. uniform on {0..m-1}."""
+    return np.array([_load().orc_srft_row(seed, i, m) for i in range(l)], dtype=np.int64)
+
+
+def srft_phases(m: int, seed: int) -> np.ndarray:
+    """phi_0..phi_{m-1} of D (eq. (7)), uniform on (0, 1)."""
+    return np.array([_load().orc_srft_phase(seed, p) for p in range(m)], dtype=np.float64)
+
+
+def srft_operator(l: int, m: int, seed: int) -> np.ndarray:
+    """G = S F D as an explicit l x m operator (Sec. 2, eqs. (4)-(7))."""
+    out = np.zeros((l, m), dtype=np.complex128)
+    if l and m:
+        _load().orc_srft_operator(l, m, seed, _ptr(out), m)
+    return out
 
 
 def start_vector(n: int, seed: int) -> np.ndarray:
@@ -191,7 +214,7 @@ def residual(A, J, P, x0, q: int):
 
 
 def decompose(A, k: int, l: int, seed: int = 0, q: int = 10, max_retries: int = 3,
-              rank_tol: float = 1e-12, G=None):
+              rank_tol: float = 1e-12, G=None, kind: str = "gaussian"):
     """Full ID: sketch, select, interp, residual; redraw with seed+1 on a
     rank failure, at most max_retries more times (Sec. 2 failure remedy).
 
@@ -204,7 +227,12 @@ def decompose(A, k: int, l: int, seed: int = 0, q: int = 10, max_retries: int = 
     s = seed
     attempts = 1 if G is not None else 1 + max_retries
     for _ in range(attempts):
-        Gs = G if G is not None else sketch_operator(l, m, s)
+        if G is not None:
+            Gs = G
+        elif kind == "srft":
+            Gs = srft_operator(l, m, s)
+        else:
+            Gs = sketch_operator(l, m, s)
         Y = sketch(A, Gs)
         st, J, R, gaps = select(Y, k, rank_tol)
         if st == OK:

@@ -116,6 +116,44 @@ void orc_gaussian_rowmajor(int64_t rows, int64_t cols, uint64_t seed, uint32_t s
 }
 
 /* ------------------------------------------------------------------------ */
+/* The paper's own randomization, Y = S F D A (Sec. 2, eqs. (4)-(7)):        */
+/*   D = diag(exp(2 pi i phi_p)), phi_p uniform on (0,1)    (stream 5)        */
+/*   F(s, p) = exp(-2 pi i s p / m), the unnormalised DFT                    */
+/*   S keeps rows s_0..s_{l-1} of F D A, i.i.d. uniform on {0..m-1}, drawn    */
+/*     with replacement                                      (stream 6)        */
+/* so Y = G A with G(i, p) = exp(2 pi i (phi_p - (s_i p mod m) / m)).         */
+/* phi_p = u1 of Philox counter (p, 0, 0, 5); s_i = floor(u1 * m) of counter */
+/* (i, 0, 0, 6).  Written row-major like the Gaussian operator.             */
+/* ------------------------------------------------------------------------ */
+static double orc_u1(uint64_t seed, uint32_t stream, uint64_t col) {
+  const uint32_t ctr[4] = {(uint32_t)col, (uint32_t)(col >> 32), 0u, stream};
+  const uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+  uint32_t w[4];
+  orc_philox4x32_10(ctr, key, w);
+  return u52(w[0], w[1]);
+}
+
+int64_t orc_srft_row(uint64_t seed, uint64_t i, int64_t m) {
+  int64_t s = (int64_t)floor(orc_u1(seed, 6u, i) * (double)m);
+  return s < m ? s : m - 1;
+}
+
+double orc_srft_phase(uint64_t seed, uint64_t p) { return orc_u1(seed, 5u, p); }
+
+void orc_srft_operator(int64_t l, int64_t m, uint64_t seed, double *out, int64_t ld) {
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < l; ++i) {
+    const int64_t si = orc_srft_row(seed, (uint64_t)i, m);
+    for (int64_t p = 0; p < m; ++p) {
+      const int64_t r = (int64_t)(((__int128)si * p) % m);
+      const double ang = ORC_TWO_PI * (orc_srft_phase(seed, (uint64_t)p) - (double)r / (double)m);
+      out[2 * (i * ld + p)] = cos(ang);
+      out[2 * (i * ld + p) + 1] = sin(ang);
+    }
+  }
+}
+
+/* ------------------------------------------------------------------------ */
 /* Sketch, Sec. 2 randomization step with a Gaussian operator:               */
 /*   Y(i, j) = sum_p G(i, p) A(p, j),  G l x m row-major (ld ldg),           */
 /*   A m x n column-major (lda), Y l x n column-major (ldy).                 */

@@ -38,7 +38,10 @@ RID_BF16X3 = 2
 EXPORTED = ["rid_create", "rid_destroy", "rid_status_string", "rid_last_hip_error",
             "rid_reserve", "rid_gaussian", "rid_sketch", "rid_sketch_explicit", "rid_pivqr",
             "rid_interp", "rid_residual", "rid_decompose", "rid_query_status", "rid_profile",
-            "rid_profile_read"]
+            "rid_profile_read", "rid_set_sketch", "rid_srft_operator"]
+
+RID_SKETCH_GAUSSIAN = 0
+RID_SKETCH_SRFT = 1
 
 RID_KERNEL_SKETCH = 0
 RID_KERNEL_AX = 1
@@ -75,6 +78,8 @@ _sig = {
                        _P, _I64, _P, ctypes.POINTER(_U64)], _I),
     "rid_query_status": ([_P, _P], _I),
     "rid_profile": ([_P, _I], _I),
+    "rid_set_sketch": ([_P, _I], _I),
+    "rid_srft_operator": ([_P, _P, _I64, _I64, _U64, _P, _I64], _I),
     "rid_profile_read": ([_P, _I, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I),
 }
 
@@ -188,6 +193,22 @@ def rid_gaussian(h, rows: int, cols: int, seed: int, stream_id: int, out=None, s
     ld = out.stride(0) if rows > 1 else max(cols, 1)
     _check(_L.rid_gaussian(h, _stream(stream), rows, cols, seed, stream_id, _ptr(out), ld),
            "rid_gaussian")
+    return out
+
+
+def rid_set_sketch(h, kind: int) -> None:
+    """Choose the random operator of later rid_sketch / rid_decompose calls."""
+    _check(_L.rid_set_sketch(h, kind), "rid_set_sketch")
+
+
+def rid_srft_operator(h, rows: int, m: int, seed: int, out=None, stream=None):
+    """rows x m block of the S F D operator (row-major complex128)."""
+    torch = _torch()
+    if out is None:
+        out = torch.empty((rows, m), dtype=torch.complex128, device="cuda")
+    ld = out.stride(0) if rows > 1 else max(m, 1)
+    _check(_L.rid_srft_operator(h, _stream(stream), rows, m, seed, _ptr(out), ld),
+           "rid_srft_operator")
     return out
 
 

@@ -191,6 +191,23 @@ rid_status rid_gaussian(rid_handle h, hipStream_t stream, int64_t rows, int64_t 
   return e == hipSuccess ? RID_OK : fail_hip(h, e);
 }
 
+rid_status rid_set_sketch(rid_handle h, int kind) {
+  if (!h || (kind != RID_SKETCH_GAUSSIAN && kind != RID_SKETCH_SRFT)) return RID_ERR_INVALID_ARG;
+  h->sketch_kind = kind;
+  return RID_OK;
+}
+
+rid_status rid_srft_operator(rid_handle h, hipStream_t stream, int64_t rows, int64_t m,
+                             uint64_t seed, void *out, int64_t ld) {
+  if (!h || rows < 0 || m < 1 || m > 0x7FFFFFFFll || ld < m || (rows > 0 && !out))
+    return RID_ERR_INVALID_ARG;
+  if (out && !aligned(out, 16)) return RID_ERR_INVALID_ARG;
+  DeviceGuard g(h->device);
+  if (g.err != hipSuccess) return fail_hip(h, g.err);
+  hipError_t e = launch_srft(stream, rows, m, seed, static_cast<double2 *>(out), ld);
+  return e == hipSuccess ? RID_OK : fail_hip(h, e);
+}
+
 static rid_status check_sketch_args(rid_handle h, rid_dtype dtype, rid_prec prec, int64_t m,
                                     int64_t n, int64_t l, const void *A, int64_t lda, void *Y,
                                     int64_t ldy) {
@@ -202,6 +219,7 @@ static rid_status check_sketch_args(rid_handle h, rid_dtype dtype, rid_prec prec
   if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
   if (A && !aligned(A, dtype == RID_C128 ? 16 : 8)) return RID_ERR_INVALID_ARG;
   if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
+  if (h->sketch_kind == RID_SKETCH_SRFT && m > 0x7FFFFFFFll) return RID_ERR_UNSUPPORTED;
   return RID_OK;
 }
 
@@ -246,7 +264,7 @@ rid_status rid_sketch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_pre
   WsCarve c(h->ws);
   double2 *G = c.take<double2>(size_t(l) * size_t(m));
   void *part = c.take<char>(sketch_ws_bytes(dtype, prec, m, n, l));
-  hipError_t e = launch_gaussian(stream, l, m, seed, 0, G, m);
+  hipError_t e = launch_operator(stream, h->sketch_kind, l, m, seed, G, m);
   if (e != hipSuccess) return fail_hip(h, e);
   e = launch_sketch(stream, dtype, prec, m, n, l, A, lda, G, m, static_cast<double2 *>(Y), ldy,
                     part, &h->prof);
@@ -360,6 +378,7 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
   if (!aligned(A, dtype == RID_C128 ? 16 : 8)) return RID_ERR_INVALID_ARG;
   if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
   if (!pivqr_supported(l) || !interp_supported(k)) return RID_ERR_UNSUPPORTED;
+  if (h->sketch_kind == RID_SKETCH_SRFT && m > 0x7FFFFFFFll) return RID_ERR_UNSUPPORTED;
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
   rid_status s = ensure_ws(h, bytes_decomp(dtype, prec, m, n, k, l, q));
@@ -368,7 +387,7 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
   const DecompWs d = carve_decomp(c, dtype, prec, m, n, k, l);
   for (int attempt = 0; attempt <= max_retries; ++attempt) {
     const uint64_t sd = seed + static_cast<uint64_t>(attempt);
-    hipError_t e = launch_gaussian(stream, l, m, sd, 0, d.G, m);
+    hipError_t e = launch_operator(stream, h->sketch_kind, l, m, sd, d.G, m);
     if (e == hipSuccess)
       e = launch_sketch(stream, dtype, prec, m, n, l, A, lda, d.G, m, d.Y, l, d.part, &h->prof);
     if (e == hipSuccess)

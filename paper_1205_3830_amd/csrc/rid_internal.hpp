@@ -63,6 +63,7 @@ struct rid_ctx {
   void *ws = nullptr;       // grow-only workspace
   size_t ws_bytes = 0;
   RidProf prof;
+  int sketch_kind = RID_SKETCH_GAUSSIAN;  // operator drawn by rid_sketch / rid_decompose
 };
 
 // Bump allocator over the handle workspace (256-byte aligned pieces).
@@ -219,6 +220,15 @@ hipError_t launch_zero(hipStream_t st, int64_t rows, int64_t cols, double2 *out,
 
 hipError_t launch_gaussian(hipStream_t st, int64_t rows, int64_t cols, uint64_t seed,
                            uint32_t stream_id, double2 *out, int64_t ld);
+
+// rows x m block of the subsampled randomized Fourier operator S F D
+// (row-major, ld); requires m < 2^31.
+hipError_t launch_srft(hipStream_t st, int64_t rows, int64_t m, uint64_t seed, double2 *out,
+                       int64_t ld);
+
+// The sketch operator of the handle's kind (rows = l, cols = m).
+hipError_t launch_operator(hipStream_t st, int kind, int64_t rows, int64_t cols, uint64_t seed,
+                           double2 *out, int64_t ld);
 
 // Y (complex128) = G A, G complex128 row-major (l x m, ldg), A column-major
 // (m x n, lda) of storage type `dtype`, products in precision `prec`.

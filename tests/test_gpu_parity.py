@@ -261,3 +261,30 @@ def test_invalid_arguments_rejected(h):
     with pytest.raises(rid.RidError) as ei:
         rid.rid_decompose(h, A, 3, 5, seed=0, prec=rid.RID_BF16X3)
     assert ei.value.status == rid.RID_ERR_UNSUPPORTED
+
+
+# ------------------------------------------------------------------ S F D operator
+@pytest.mark.parametrize("rows,m,seed", [(10, 64, 3), (108, 5000, 7), (1, 1, 0)])
+def test_srft_operator_matches_oracle(h, rows, m, seed):
+    g = host(rid.rid_srft_operator(h, rows, m, seed))
+    ref = oracle.srft_operator(rows, m, seed)
+    assert np.abs(g - ref).max() <= 1e-13
+
+
+def test_decompose_with_srft_matches_oracle(h):
+    m, n, k, l = 1000, 500, 20, 40
+    A = _lowrank(m, n, k, 1e-10, seed=0)
+    r = oracle.decompose(A, k, l, seed=0, q=8, kind="srft")
+    rid.rid_set_sketch(h, rid.RID_SKETCH_SRFT)
+    try:
+        J, P, sigma, used = rid.rid_decompose(h, dev(A), k, l, seed=0, q=8)
+        Y = host(rid.rid_sketch(h, dev(A), l, 0))
+    finally:
+        rid.rid_set_sketch(h, rid.RID_SKETCH_GAUSSIAN)
+    assert np.linalg.norm(Y - r["Y"]) <= 1e-12 * np.linalg.norm(r["Y"])
+    J, P, s = host(J), host(P), float(host(sigma)[0])
+    assert _compare_J(J, r["J"], r["gaps"]) == k
+    dP = P - r["P"]
+    assert np.abs(dP).max() <= 1e-10 * max(1.0, np.abs(r["P"]).max())
+    tol = 1e-10 * r["sigma"] + 2 * np.linalg.norm(A[:, J]) * np.linalg.norm(dP)
+    assert abs(s - r["sigma"]) <= tol

@@ -362,3 +362,43 @@ def test_precision_floor_of_noise_free_products():
     s = np.linalg.svd(A, compute_uv=False)
     floor = np.sqrt(2 * 128) * 1e-16 * np.abs(A).max()
     assert s[8] < 100 * floor
+
+
+# ---------------------------------------------------------------- S F D (eqs. (4)-(7))
+@pytest.mark.parametrize("m,n,l", [(64, 5, 10), (1000, 7, 30), (97, 3, 40)])
+def test_srft_operator_equals_sampled_fft(m, n, l):
+    # Y = S F D A computed the long way: phases, a full FFT down each column
+    # (numpy), then the sampled rows -- against the operator product.
+    rng = np.random.default_rng(m)
+    A = rng.normal(size=(m, n)) + 1j * rng.normal(size=(m, n))
+    G = oracle.srft_operator(l, m, seed=3)
+    s = oracle.srft_rows(l, m, seed=3)
+    ph = oracle.srft_phases(m, seed=3)
+    Yf = np.fft.fft(np.exp(2j * np.pi * ph)[:, None] * A, axis=0)[s, :]
+    Y = oracle.sketch(A, G)
+    assert np.abs(Y - Yf).max() <= 1e-13 * np.sqrt(m) * np.abs(Yf).max()
+    assert np.allclose(np.abs(G), 1.0, rtol=0, atol=1e-15)
+
+
+def test_srft_rows_and_phases_are_uniform():
+    m, l = 10, 20000
+    s = oracle.srft_rows(l, m, seed=1)
+    counts = np.bincount(s, minlength=m)
+    expected = l / m
+    chi2 = np.sum((counts - expected) ** 2 / expected)
+    assert chi2 < 40.0                                     # 9 dof, far tail
+    assert len(np.unique(oracle.srft_rows(30, 40, seed=2))) < 30   # drawn with replacement
+    ph = oracle.srft_phases(50000, seed=4)
+    assert abs(ph.mean() - 0.5) < 5 * np.sqrt(1 / 12 / 50000)
+    assert abs(ph.var() - 1 / 12) < 5e-3
+    assert ph.min() > 0.0 and ph.max() < 1.0
+
+
+def test_srft_decompose_matches_pivoted_qr_of_its_sketch():
+    A = synth.lowrank(1000, 500, 20, 1e-10, seed=0)
+    r = oracle.decompose(A, 20, 40, seed=0, q=6, kind="srft")
+    assert r["status"] == oracle.OK
+    _, _, piv = sl.qr(r["Y"], pivoting=True, mode="economic")
+    assert np.array_equal(r["J"], piv[:20])
+    E = A - A[:, r["J"]] @ r["P"]
+    assert r["sigma"] <= np.linalg.norm(E, 2) * (1 + 1e-6)
