@@ -249,6 +249,39 @@ rid_status rid_profile(rid_handle h, int enable);
  * Synchronises on the recorded events.  Errors: INVALID_ARG, HIP.        */
 rid_status rid_profile_read(rid_handle h, int kernel, double *total_ms, int64_t *launches);
 
+/* ---------------------------------------------------------------- batches */
+
+/* One ID of a batch.  A: m x n column-major of the batch's dtype (lda >= m,
+ * device); J: k int64 (device, out); P: k x n complex128 column-major
+ * (ldp >= k, device, out); sigma: one double (device, out). */
+typedef struct {
+  int64_t m, n, k, l;
+  const void *A;
+  int64_t lda;
+  uint64_t seed;
+  int64_t *J;
+  void *P;
+  int64_t ldp;
+  double *sigma;
+} rid_job;
+
+/* Many independent IDs of uneven sizes (Sec. 2 for each), each with its own
+ * seed: every step runs as one launch over all jobs (the pivoted QR as one
+ * workgroup per job), captured into a HIP graph and replayed on `stream`
+ * (set RID_BATCH_GRAPH=0 in the environment to launch directly).  A job
+ * whose sketch has rank < k is redrawn with seed + 1, up to max_retries
+ * times.  Results per job are those of rid_decompose with the same inputs
+ * and arguments, up to the split order of the sketch sums.
+ * jobs: host array of `count`; job_status (host, count, or null) receives
+ * RID_OK / RID_ERR_RANK per job; seed_used (host, count, or null) the seed
+ * of each job's last draw.  Limits per job: 1 <= k <= l <= m, k <= n,
+ * k <= 256, l <= 224, n <= 4096.  SYNCHRONISES the stream.  Errors:
+ * INVALID_ARG, UNSUPPORTED, NOMEM, HIP, RANK (some job failed every draw;
+ * the others hold their results).                                        */
+rid_status rid_decompose_batched(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                                 const rid_job *jobs, int count, int q, int max_retries,
+                                 double rank_tol, int *job_status, uint64_t *seed_used);
+
 /* Synchronise `stream` and return the handle's status word: RID_OK, or
  * RID_ERR_RANK if the last rid_pivqr on this handle met rank(Y) < k.
  * Errors: HIP.                                                            */

@@ -38,7 +38,7 @@ RID_BF16X3 = 2
 EXPORTED = ["rid_create", "rid_destroy", "rid_status_string", "rid_last_hip_error",
             "rid_reserve", "rid_gaussian", "rid_sketch", "rid_sketch_explicit", "rid_pivqr",
             "rid_interp", "rid_residual", "rid_decompose", "rid_query_status", "rid_profile",
-            "rid_profile_read", "rid_set_sketch", "rid_srft_operator"]
+            "rid_profile_read", "rid_set_sketch", "rid_srft_operator", "rid_decompose_batched"]
 
 RID_SKETCH_GAUSSIAN = 0
 RID_SKETCH_SRFT = 1
@@ -60,6 +60,15 @@ _D = ctypes.c_double
 
 _lib = None
 
+
+class rid_job(ctypes.Structure):
+    """Mirror of the C struct rid_job (one ID of a batch)."""
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("l", ctypes.c_int64), ("A", ctypes.c_void_p), ("lda", ctypes.c_int64),
+                ("seed", ctypes.c_uint64), ("J", ctypes.c_void_p), ("P", ctypes.c_void_p),
+                ("ldp", ctypes.c_int64), ("sigma", ctypes.c_void_p)]
+
+
 _sig = {
     "rid_create": ([ctypes.POINTER(_P), _I], _I),
     "rid_destroy": ([_P], _I),
@@ -79,6 +88,8 @@ _sig = {
     "rid_query_status": ([_P, _P], _I),
     "rid_profile": ([_P, _I], _I),
     "rid_set_sketch": ([_P, _I], _I),
+    "rid_decompose_batched": ([_P, _P, _I, _I, ctypes.POINTER(rid_job), _I, _I, _I, _D,
+                               ctypes.POINTER(_I), ctypes.POINTER(_U64)], _I),
     "rid_srft_operator": ([_P, _P, _I64, _I64, _U64, _P, _I64], _I),
     "rid_profile_read": ([_P, _I, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I),
 }
@@ -335,3 +346,39 @@ def rid_profile_read(h, kernel: int):
     _check(_L.rid_profile_read(h, kernel, ctypes.byref(ms), ctypes.byref(cnt)),
            "rid_profile_read")
     return ms.value, cnt.value
+
+
+def rid_decompose_batched(h, As, ks, ls, seeds, q: int = 10, max_retries: int = 3,
+                          rank_tol: float = 1e-12, prec: int = RID_FP64, stream=None,
+                          raise_on_rank: bool = True):
+    """Many IDs in one call.  As: list of column-major device tensors (one
+    dtype); ks, ls, seeds: per-job ints.  Returns (Js, Ps, sigmas, status,
+    seeds_used) with per-job device tensors and host lists."""
+    torch = _torch()
+    count = len(As)
+    arr = (rid_job * max(count, 1))()
+    Js, Ps, sig = [], [], []
+    dt = None
+    for i, A in enumerate(As):
+        m, n = A.shape
+        k, l = int(ks[i]), int(ls[i])
+        c = _dtype_code(A)
+        if dt is None:
+            dt = c
+        elif c != dt:
+            raise ValueError("all matrices of a batch must share one dtype")
+        J = torch.empty(k, dtype=torch.int64, device="cuda")
+        P = _new_colmajor(k, n, torch.complex128)
+        s = torch.zeros(1, dtype=torch.float64, device="cuda")
+        Js.append(J)
+        Ps.append(P)
+        sig.append(s)
+        arr[i] = rid_job(m, n, k, l, A.data_ptr(), _ld_colmajor(A, "A"), int(seeds[i]),
+                         J.data_ptr(), P.data_ptr(), _ld_colmajor(P, "P"), s.data_ptr())
+    status = (_I * max(count, 1))()
+    used = (_U64 * max(count, 1))()
+    st = _L.rid_decompose_batched(h, _stream(stream), RID_C128 if dt is None else dt, prec, arr,
+                                  count, q, max_retries, rank_tol, status, used)
+    if st != RID_OK and not (st == RID_ERR_RANK and not raise_on_rank):
+        raise RidError(st, "rid_decompose_batched")
+    return Js, Ps, sig, [status[i] for i in range(count)], [int(used[i]) for i in range(count)]

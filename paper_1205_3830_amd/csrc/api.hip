@@ -157,6 +157,7 @@ rid_status rid_destroy(rid_handle h) {
   if (!h) return RID_OK;
   DeviceGuard g(h->device);
   for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->ws) (void)hipFree(h->ws);
   if (h->d_status) (void)hipFree(h->d_status);
   delete h;

@@ -1,0 +1,569 @@
+// batched.hip -- many independent IDs of uneven sizes in one call
+// (rid_decompose_batched).  Every step of the ID runs as one launch over all
+// jobs: blocks find their (job, block) pair in host-built tables, so a batch
+// costs the same number of launches as one ID.  The launch sequence is
+// captured into a HIP graph and replayed on the caller's stream.
+//
+// The pivoted QR of a job's sketch (l x n, small) runs in one workgroup per
+// job that loops over the k steps with block barriers only -- no
+// cross-workgroup waits.  Jobs are ordered largest first so the long QRs
+// start early.  A job whose sketch has rank < k is redrawn with seed + 1
+// (Sec. 2), up to max_retries times, in a follow-up batch of the failures.
+#include <algorithm>
+#include <climits>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+
+#include "rid_internal.hpp"
+
+namespace {
+
+constexpr int QR_NMAX = 4096;  // columns per job held in LDS by the batch QR
+
+struct QrJob {
+  int64_t l, n, k, ldy;
+  double2 *Y;
+  int64_t *J;    // caller's J (k entries)
+  int *mark;     // n: step at which the column was picked, -1 otherwise
+  int *status;   // per-job status word
+  double rank_tol;
+};
+
+struct OpJob {
+  int64_t rows, cols, ld;
+  uint64_t seed;
+  double2 *out;
+  int kind;
+};
+
+// ---------------------------------------------------------------- operators
+__global__ __launch_bounds__(256) void operator_grouped_kernel(const OpJob *__restrict__ jobs,
+                                                               const int4 *__restrict__ tab) {
+  const int4 en = tab[blockIdx.x];
+  const OpJob &jb = jobs[en.x];
+  const int64_t total = jb.rows * jb.cols;
+  for (int64_t e = int64_t(en.y) * 256 + threadIdx.x; e < total; e += int64_t(en.z) * 256) {
+    const int64_t i = e / jb.cols;
+    const int64_t p = e - i * jb.cols;
+    double2 g;
+    if (jb.kind == RID_SKETCH_SRFT) {
+      uint32_t c[4] = {static_cast<uint32_t>(i), static_cast<uint32_t>(uint64_t(i) >> 32), 0u, 6u};
+      rid_philox10(c, static_cast<uint32_t>(jb.seed), static_cast<uint32_t>(jb.seed >> 32));
+      int64_t si = static_cast<int64_t>(floor(rid_u52(c[0], c[1]) * static_cast<double>(jb.cols)));
+      if (si >= jb.cols) si = jb.cols - 1;
+      uint32_t d[4] = {static_cast<uint32_t>(p), static_cast<uint32_t>(uint64_t(p) >> 32), 0u, 5u};
+      rid_philox10(d, static_cast<uint32_t>(jb.seed), static_cast<uint32_t>(jb.seed >> 32));
+      const int64_t r = static_cast<int64_t>((static_cast<uint64_t>(si) * static_cast<uint64_t>(p)) %
+                                             static_cast<uint64_t>(jb.cols));
+      const double ang = 6.283185307179586476925286766559 *
+                         (rid_u52(d[0], d[1]) - static_cast<double>(r) / static_cast<double>(jb.cols));
+      g = make_double2(cos(ang), sin(ang));
+    } else {
+      g = rid_gauss(jb.seed, 0u, static_cast<uint32_t>(i), static_cast<uint64_t>(p));
+    }
+    jb.out[i * jb.ld + p] = g;
+  }
+}
+
+// ---------------------------------------------------------------- QR, one block per job
+template <int LPC>
+RID_DEV double group_sum(double v) {
+#pragma unroll
+  for (int off = LPC / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Householder QR with exact column pivoting of one job's Y (as rid_pivqr,
+// Sec. 2), all k steps in this workgroup.  Columns are processed LPC lanes
+// per column (RPL rows per lane, l <= LPC RPL), 64 / LPC columns per wave.
+template <int LPC, int RPL>
+__global__ __launch_bounds__(256) void pivqr_job_kernel(const QrJob *__restrict__ jobs,
+                                                        const int4 *__restrict__ order) {
+  constexpr int CPW = 64 / LPC;
+  constexpr int CPB = 4 * CPW;
+  __shared__ double nrm[QR_NMAX];
+  __shared__ int picked[QR_NMAX];
+  __shared__ double2 v_s[LPC * RPL];
+  __shared__ double rv1[256], rv2[256];
+  __shared__ int64_t ri[256];
+  __shared__ double2 tau_s;
+  __shared__ double beta_s;
+  __shared__ int64_t jstar_s;
+  __shared__ int fail_s;
+  __shared__ double nu0_s;
+
+  const QrJob jb = jobs[order[blockIdx.x].x];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int grp = lane / LPC;
+  const int gl = lane % LPC;
+  const int64_t l = jb.l, n = jb.n, k = jb.k;
+  for (int64_t j = tid; j < n; j += 256) picked[j] = -1;
+  if (tid == 0) *jb.status = RID_OK;
+  __syncthreads();
+
+  double2 tau = make_double2(0.0, 0.0);
+  for (int64_t t = 0; t <= k; ++t) {
+    const int64_t r0 = t > 0 ? t - 1 : 0;
+    // 1. apply the reflector of step t-1; trailing norms for step t
+    for (int64_t c0 = 0; c0 < n; c0 += CPB) {
+      const int64_t j = c0 + wave * CPW + grp;
+      const bool act = j < n && picked[j] < 0;
+      double2 *col = jb.Y + (act ? j : 0) * jb.ldy;
+      double2 y[RPL];
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) {
+        const int64_t row = r0 + gl + LPC * h;
+        y[h] = (act && row < l) ? col[row] : make_double2(0.0, 0.0);
+      }
+      if (t > 0) {
+        double dr = 0.0, di = 0.0;
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+          const double2 v = v_s[gl + LPC * h];
+          dr += v.x * y[h].x + v.y * y[h].y;
+          di += v.x * y[h].y - v.y * y[h].x;
+        }
+        dr = group_sum<LPC>(dr);
+        di = group_sum<LPC>(di);
+        const double cr = tau.x * dr + tau.y * di;
+        const double ci = tau.x * di - tau.y * dr;
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+          const double2 v = v_s[gl + LPC * h];
+          y[h].x -= v.x * cr - v.y * ci;
+          y[h].y -= v.x * ci + v.y * cr;
+          const int64_t row = r0 + gl + LPC * h;
+          if (act && row < l) col[row] = y[h];
+        }
+      }
+      if (t < k) {
+        double ss = 0.0;
+#pragma unroll
+        for (int h = 0; h < RPL; ++h) {
+          const int64_t row = r0 + gl + LPC * h;
+          if (row >= t && row < l) ss += y[h].x * y[h].x + y[h].y * y[h].y;
+        }
+        ss = group_sum<LPC>(ss);
+        if (gl == 0 && j < n) nrm[j] = act ? sqrt(ss) : -1.0;
+      }
+    }
+    if (t == k) break;
+    __syncthreads();
+
+    // 2. pivot: largest trailing norm, lowest index on exact ties
+    double b1 = -1.0, b2 = -1.0;
+    int64_t bi = INT64_MAX;
+    for (int64_t j = tid; j < n; j += 256) {
+      const double v = nrm[j];
+      if (v < 0.0) continue;
+      if (v > b1 || (v == b1 && j < bi)) {
+        b2 = fmax(b2, b1);
+        b1 = v;
+        bi = j;
+      } else {
+        b2 = fmax(b2, v);
+      }
+    }
+    rv1[tid] = b1;
+    rv2[tid] = b2;
+    ri[tid] = bi;
+    __syncthreads();
+    for (int s = 128; s >= 1; s >>= 1) {
+      if (tid < s) {
+        const double a1 = rv1[tid], c1 = rv1[tid + s];
+        const int64_t ai = ri[tid], ci = ri[tid + s];
+        const bool other = (c1 > a1) || (c1 == a1 && ci < ai);
+        const double lose = other ? a1 : c1;
+        rv2[tid] = fmax(fmax(rv2[tid], rv2[tid + s]), lose);
+        if (other) {
+          rv1[tid] = c1;
+          ri[tid] = ci;
+        }
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const double nu1 = rv1[0];
+      if (t == 0) nu0_s = nu1;
+      const bool fail = !(nu1 > 0.0) || nu1 <= jb.rank_tol * nu0_s;
+      fail_s = fail ? 1 : 0;
+      jstar_s = ri[0];
+      if (fail) {
+        *jb.status = RID_ERR_RANK;
+      } else {
+        jb.J[t] = ri[0];
+      }
+    }
+    __syncthreads();
+    if (fail_s) return;
+    const int64_t js = jstar_s;
+
+    // 3. reflector of step t from column js, built by the lanes that own it
+    const int owner_wave = static_cast<int>((js % CPB) / CPW);
+    const int owner_grp = static_cast<int>(js % CPW);
+    if (wave == owner_wave && grp == owner_grp) {
+      double2 *col = jb.Y + js * jb.ldy;
+      double2 x[RPL];
+      double ss = 0.0;
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) {
+        const int64_t row = t + gl + LPC * h;
+        x[h] = row < l ? col[row] : make_double2(0.0, 0.0);
+        if (gl + LPC * h >= 1) ss += x[h].x * x[h].x + x[h].y * x[h].y;
+      }
+      const double xnorm2 = group_sum<LPC>(ss);
+      const double ar = __shfl(x[0].x, grp * LPC, 64);
+      const double ai = __shfl(x[0].y, grp * LPC, 64);
+      double2 tv;
+      double beta;
+      double2 scale;
+      if (xnorm2 == 0.0 && ai == 0.0) {
+        tv = make_double2(0.0, 0.0);
+        beta = ar;
+        scale = make_double2(0.0, 0.0);
+      } else {
+        const double mag = sqrt(ar * ar + ai * ai + xnorm2);
+        beta = (ar >= 0.0) ? -mag : mag;
+        tv = make_double2((beta - ar) / beta, -ai / beta);
+        const double dr = ar - beta, di = ai;
+        const double den = dr * dr + di * di;
+        scale = make_double2(dr / den, -di / den);
+      }
+#pragma unroll
+      for (int h = 0; h < RPL; ++h) {
+        const int idx = gl + LPC * h;
+        const int64_t row = t + idx;
+        double2 v;
+        if (idx == 0)
+          v = make_double2(1.0, 0.0);
+        else
+          v = make_double2(x[h].x * scale.x - x[h].y * scale.y,
+                           x[h].x * scale.y + x[h].y * scale.x);
+        // v_s is indexed from row t - 1 + 1 = t in the next apply (r0 = t)
+        v_s[idx] = row < l ? v : make_double2(0.0, 0.0);
+        if (row < l) col[row] = (idx == 0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
+      }
+      if (gl == 0) {
+        tau_s = tv;
+        beta_s = beta;
+        picked[js] = static_cast<int>(t);
+      }
+    }
+    __syncthreads();
+    tau = tau_s;
+  }
+  for (int64_t j = tid; j < n; j += 256) jb.mark[j] = picked[j];
+}
+
+// ---------------------------------------------------------------- host side
+struct Buf {
+  std::vector<char> bytes;
+  template <class T>
+  size_t put(const T *p, size_t count) {
+    size_t off = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(off + sizeof(T) * count);
+    if (count) memcpy(bytes.data() + off, p, sizeof(T) * count);
+    return off;
+  }
+};
+
+bool use_graph() {
+  const char *e = getenv("RID_BATCH_GRAPH");
+  return !(e && e[0] == '0');
+}
+
+}  // namespace
+
+bool batch_job_supported(const RidBatchJob &j) {
+  return j.l <= 256 && j.n <= QR_NMAX && j.k <= 256 && sketch_pick_mt(j.l) > 0;
+}
+
+// Runs one batch (each job once, with the seeds in bj); writes per-job
+// status (host).  ws: device workspace of batch_ws_bytes(...) bytes.
+hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                     const RidBatchJob *bj, int count, int q, double rank_tol, int *status) {
+  // ---- plans and workspace layout
+  std::vector<SketchJob> sk(count);
+  std::vector<OpJob> op(count);
+  std::vector<QrJob> qr(count);
+  std::vector<InterpJob> in(count);
+  std::vector<int> mt(count);
+  int kmax = 1;
+  int64_t lmax = 1;
+  for (int i = 0; i < count; ++i) {
+    kmax = std::max<int>(kmax, static_cast<int>(bj[i].k));
+    lmax = std::max<int64_t>(lmax, bj[i].l);
+  }
+  // persistent region: Y, mark, status; scratch region: G + partials, or the
+  // residual workspace (the sketch is done before the residual starts)
+  WsCarve pc(nullptr);
+  std::vector<size_t> offY(count), offMark(count);
+  for (int i = 0; i < count; ++i) {
+    offY[i] = pc.take_off<double2>(size_t(bj[i].l) * size_t(bj[i].n));
+    offMark[i] = pc.take_off<int>(bj[i].n);
+  }
+  const size_t offStatus = pc.take_off<int>(count);
+  const size_t persist = (pc.off + 255) & ~size_t(255);
+  WsCarve sc(nullptr);
+  std::vector<size_t> offG(count), offPart(count);
+  const int64_t pchunk = 1024;
+  for (int i = 0; i < count; ++i) {
+    const int64_t S = (bj[i].m + pchunk - 1) / pchunk;
+    offG[i] = sc.take_off<double2>(size_t(bj[i].l) * size_t(bj[i].m));
+    const size_t el = prec == RID_FP32 ? sizeof(float) : sizeof(double);
+    offPart[i] = sc.take_off<char>(size_t(S) * size_t(2 * bj[i].l) * size_t(bj[i].n) * el);
+  }
+  GroupedHost res;
+  residual_batch_setup(bj, count, dtype, nullptr, &res);
+  const size_t scratch = std::max(sc.off, res.ws_bytes) + 256;
+
+  // ---- descriptor + table upload region goes first
+  // (sizes are known only after the tables are built; build them with a
+  // provisional base, then fix pointers once the base is known)
+  Buf tabs;
+  std::vector<int4> t_op, t_red, t_qr, t_in;
+  std::vector<std::vector<int4>> t_sk;
+  std::vector<int> mts;
+  for (int i = 0; i < count; ++i) {
+    const int64_t tot = bj[i].l * bj[i].m;
+    const int nb = static_cast<int>(std::min<int64_t>((tot + 255) / 256, 256));
+    for (int b = 0; b < nb; ++b) t_op.push_back(make_int4(i, b, nb, 0));
+    const int64_t totY = 2 * bj[i].l * bj[i].n;
+    const int nr = static_cast<int>(std::min<int64_t>((totY + 255) / 256, 64));
+    for (int b = 0; b < nr; ++b) t_red.push_back(make_int4(i, b, nr, 0));
+    mt[i] = sketch_pick_mt(bj[i].l);
+    int bucket = -1;
+    for (size_t u = 0; u < mts.size(); ++u)
+      if (mts[u] == mt[i]) bucket = static_cast<int>(u);
+    if (bucket < 0) {
+      mts.push_back(mt[i]);
+      t_sk.emplace_back();
+      bucket = static_cast<int>(mts.size()) - 1;
+    }
+    const int64_t nbx = (bj[i].n + 63) / 64;
+    const int64_t S = (bj[i].m + pchunk - 1) / pchunk;
+    for (int64_t s = 0; s < S; ++s)
+      for (int64_t x = 0; x < nbx; ++x)
+        t_sk[bucket].push_back(make_int4(i, static_cast<int>(x), static_cast<int>(s), 0));
+    const int64_t nq = (bj[i].n + 3) / 4;
+    for (int64_t x = 0; x < nq; ++x) t_in.push_back(make_int4(i, static_cast<int>(x), 0, 0));
+  }
+  // QR: largest jobs first
+  std::vector<int> ord(count);
+  std::iota(ord.begin(), ord.end(), 0);
+  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
+    return bj[a].l * bj[a].n * bj[a].k > bj[b].l * bj[b].n * bj[b].k;
+  });
+  for (int i : ord) t_qr.push_back(make_int4(i, 0, 0, 0));
+
+  // descriptor region size
+  const size_t nbuck = mts.size();
+  size_t tabbytes;
+  {
+    Buf probe;
+    probe.put(sk.data(), count);
+    probe.put(op.data(), count);
+    probe.put(qr.data(), count);
+    probe.put(in.data(), count);
+    probe.put(res.jobs.data(), res.jobs.size());
+    probe.put(t_op.data(), t_op.size());
+    probe.put(t_red.data(), t_red.size());
+    probe.put(t_qr.data(), t_qr.size());
+    probe.put(t_in.data(), t_in.size());
+    probe.put(res.tab.data(), res.tab.size());
+    for (size_t u = 0; u < nbuck; ++u) probe.put(t_sk[u].data(), t_sk[u].size());
+    tabbytes = (probe.bytes.size() + 255) & ~size_t(255);
+  }
+  const size_t total = tabbytes + persist + scratch + 256;
+  // the residual descriptors need the final scratch base: set it up now
+  hipError_t err = hipSuccess;
+  {
+    // ensure the workspace (may reallocate; callers synchronise around it)
+    if (total > h->ws_bytes) {
+      hipError_t e = hipDeviceSynchronize();
+      if (e != hipSuccess) return e;
+      if (h->ws) (void)hipFree(h->ws);
+      h->ws = nullptr;
+      h->ws_bytes = 0;
+      e = hipMalloc(&h->ws, total);
+      if (e != hipSuccess) {
+        h->ws = nullptr;
+        return e;
+      }
+      h->ws_bytes = total;
+    }
+  }
+  char *base = static_cast<char *>(h->ws);
+  char *pbase = base + tabbytes;
+  char *sbase = pbase + persist;
+  residual_batch_setup(bj, count, dtype, sbase, &res);
+  int *dstatus = reinterpret_cast<int *>(pbase + offStatus);
+  for (int i = 0; i < count; ++i) {
+    double2 *Y = reinterpret_cast<double2 *>(pbase + offY[i]);
+    int *mark = reinterpret_cast<int *>(pbase + offMark[i]);
+    double2 *G = reinterpret_cast<double2 *>(sbase + offG[i]);
+    sk[i] = SketchJob{bj[i].m, bj[i].n, bj[i].l, bj[i].lda, bj[i].m, pchunk, bj[i].A, G,
+                      sbase + offPart[i], Y, (bj[i].m + pchunk - 1) / pchunk, 0};
+    op[i] = OpJob{bj[i].l, bj[i].m, bj[i].m, bj[i].seed, G, h->sketch_kind};
+    qr[i] = QrJob{bj[i].l, bj[i].n, bj[i].k, bj[i].l, Y, bj[i].J, mark, dstatus + i, rank_tol};
+    in[i] = InterpJob{bj[i].n, bj[i].k, bj[i].l, bj[i].ldp, Y, bj[i].J, bj[i].P, mark};
+  }
+  const size_t o_sk = tabs.put(sk.data(), count);
+  const size_t o_op = tabs.put(op.data(), count);
+  const size_t o_qr = tabs.put(qr.data(), count);
+  const size_t o_in = tabs.put(in.data(), count);
+  const size_t o_res = tabs.put(res.jobs.data(), res.jobs.size());
+  const size_t o_top = tabs.put(t_op.data(), t_op.size());
+  const size_t o_tred = tabs.put(t_red.data(), t_red.size());
+  const size_t o_tqr = tabs.put(t_qr.data(), t_qr.size());
+  const size_t o_tin = tabs.put(t_in.data(), t_in.size());
+  const size_t o_tres = tabs.put(res.tab.data(), res.tab.size());
+  std::vector<int64_t> skoff(nbuck), skcnt(nbuck);
+  size_t o_tsk0 = 0;
+  for (size_t u = 0; u < nbuck; ++u) {
+    const size_t o = tabs.put(t_sk[u].data(), t_sk[u].size());
+    if (u == 0) o_tsk0 = o;
+    skoff[u] = static_cast<int64_t>((o - o_tsk0) / sizeof(int4));
+    skcnt[u] = static_cast<int64_t>(t_sk[u].size());
+  }
+  err = hipMemcpyAsync(base, tabs.bytes.data(), tabs.bytes.size(), hipMemcpyHostToDevice, stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
+  if (err != hipSuccess) return err;
+
+  // ---- the launch sequence
+  const SketchJob *d_sk = reinterpret_cast<const SketchJob *>(base + o_sk);
+  const OpJob *d_op = reinterpret_cast<const OpJob *>(base + o_op);
+  const QrJob *d_qr = reinterpret_cast<const QrJob *>(base + o_qr);
+  const InterpJob *d_in = reinterpret_cast<const InterpJob *>(base + o_in);
+  const void *d_res = base + o_res;
+  const int4 *d_top = reinterpret_cast<const int4 *>(base + o_top);
+  const int4 *d_tqr = reinterpret_cast<const int4 *>(base + o_tqr);
+  const int4 *d_tin = reinterpret_cast<const int4 *>(base + o_tin);
+  const int4 *d_tres = reinterpret_cast<const int4 *>(base + o_tres);
+  const int4 *d_tsk = reinterpret_cast<const int4 *>(base + o_tsk0);
+  // the sketch reduce table is appended to the sketch tables' index space
+  auto sequence = [&](hipStream_t st) -> hipError_t {
+    hipLaunchKernelGGL(operator_grouped_kernel, dim3(static_cast<unsigned>(t_op.size())),
+                       dim3(256), 0, st, d_op, d_top);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // grouped sketch per MT bucket, then the grouped split reduce (its table
+    // sits before the sketch tables: a negative offset from d_tsk)
+    const int64_t red_off = (static_cast<int64_t>(o_tred) - static_cast<int64_t>(o_tsk0)) /
+                            static_cast<int64_t>(sizeof(int4));
+    e = launch_sketch_batch(st, dtype, prec, d_sk, d_tsk, mts.data(), skoff.data(), skcnt.data(),
+                            static_cast<int>(nbuck), red_off, static_cast<int64_t>(t_red.size()),
+                            nullptr);
+    if (e != hipSuccess) return e;
+    if (lmax <= 80)
+      hipLaunchKernelGGL((pivqr_job_kernel<16, 5>), dim3(static_cast<unsigned>(count)), dim3(256),
+                         0, st, d_qr, d_tqr);
+    else if (lmax <= 128)
+      hipLaunchKernelGGL((pivqr_job_kernel<16, 8>), dim3(static_cast<unsigned>(count)), dim3(256),
+                         0, st, d_qr, d_tqr);
+    else
+      hipLaunchKernelGGL((pivqr_job_kernel<32, 8>), dim3(static_cast<unsigned>(count)), dim3(256),
+                         0, st, d_qr, d_tqr);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = launch_interp_batch(st, kmax, d_in, d_tin, static_cast<int64_t>(t_in.size()), nullptr);
+    if (e != hipSuccess) return e;
+    return launch_residual_batch(st, dtype, d_res, d_tres, res, q, nullptr);
+  };
+
+  if (use_graph()) {
+    if (!h->cap_stream) {
+      err = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
+      if (err != hipSuccess) return err;
+    }
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    err = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
+    if (err == hipSuccess) {
+      hipError_t e1 = sequence(h->cap_stream);
+      err = hipStreamEndCapture(h->cap_stream, &graph);
+      if (e1 != hipSuccess) err = e1;
+    }
+    if (err == hipSuccess) err = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (err == hipSuccess) err = hipGraphLaunch(exec, stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(stream);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (err != hipSuccess) return err;
+  } else {
+    err = sequence(stream);
+    if (err == hipSuccess) err = hipStreamSynchronize(stream);
+    if (err != hipSuccess) return err;
+  }
+  err = hipMemcpy(status, dstatus, sizeof(int) * count, hipMemcpyDeviceToHost);
+  return err;
+}
+
+extern "C" rid_status rid_decompose_batched(rid_handle h, hipStream_t stream, rid_dtype dtype,
+                                            rid_prec prec, const rid_job *jobs, int count, int q,
+                                            int max_retries, double rank_tol, int *job_status,
+                                            uint64_t *seed_used) {
+  if (!h || count < 0 || (count > 0 && !jobs) || q < 1 || max_retries < 0 ||
+      !(rank_tol >= 0.0) || rank_tol > 1.0)
+    return RID_ERR_INVALID_ARG;
+  if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
+  if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
+  if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
+  const size_t align = dtype == RID_C128 ? 16 : 8;
+  std::vector<RidBatchJob> bj(count);
+  for (int i = 0; i < count; ++i) {
+    const rid_job &j = jobs[i];
+    if (j.k < 1 || j.k > j.l || j.k > j.n || j.l > j.m || j.lda < j.m || j.ldp < j.k || !j.A ||
+        !j.J || !j.P || !j.sigma || reinterpret_cast<uintptr_t>(j.A) % align != 0 ||
+        reinterpret_cast<uintptr_t>(j.P) % 16 != 0 || j.n > 0x7FFFFFFFll)
+      return RID_ERR_INVALID_ARG;
+    bj[i] = RidBatchJob{j.m, j.n, j.k, j.l, j.lda, j.ldp, j.A, j.seed, j.J,
+                        static_cast<double2 *>(j.P), j.sigma};
+    if (!batch_job_supported(bj[i])) return RID_ERR_UNSUPPORTED;
+    if (h->sketch_kind == RID_SKETCH_SRFT && j.m > 0x7FFFFFFFll) return RID_ERR_UNSUPPORTED;
+  }
+  if (count == 0) return RID_OK;
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) return RID_ERR_HIP;
+  if (prev != h->device && hipSetDevice(h->device) != hipSuccess) return RID_ERR_HIP;
+  std::vector<int> st(count, RID_ERR_RANK);
+  std::vector<uint64_t> used(count);
+  for (int i = 0; i < count; ++i) used[i] = jobs[i].seed;
+  std::vector<int> pending(count);
+  std::iota(pending.begin(), pending.end(), 0);
+  rid_status out = RID_OK;
+  for (int attempt = 0; attempt <= max_retries && !pending.empty(); ++attempt) {
+    std::vector<RidBatchJob> sub;
+    for (int i : pending) {
+      sub.push_back(bj[i]);
+      sub.back().seed = jobs[i].seed + static_cast<uint64_t>(attempt);
+    }
+    std::vector<int> sst(sub.size(), RID_ERR_HIP);
+    hipError_t e = run_batch(h, stream, dtype, prec, sub.data(), static_cast<int>(sub.size()), q,
+                             rank_tol, sst.data());
+    if (e != hipSuccess) {
+      h->last_hip_error = static_cast<int>(e);
+      out = RID_ERR_HIP;
+      break;
+    }
+    std::vector<int> next;
+    for (size_t u = 0; u < pending.size(); ++u) {
+      st[pending[u]] = sst[u];
+      used[pending[u]] = sub[u].seed;
+      if (sst[u] == RID_ERR_RANK) next.push_back(pending[u]);
+    }
+    pending.swap(next);
+  }
+  if (out == RID_OK)
+    for (int i = 0; i < count; ++i)
+      if (st[i] != RID_OK) out = RID_ERR_RANK;
+  if (job_status)
+    for (int i = 0; i < count; ++i) job_status[i] = st[i];
+  if (seed_used)
+    for (int i = 0; i < count; ++i) seed_used[i] = used[i];
+  if (prev != h->device) (void)hipSetDevice(prev);
+  return out;
+}

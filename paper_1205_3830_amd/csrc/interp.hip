@@ -26,11 +26,9 @@ __global__ void interp_mark_set_kernel(int64_t n, int64_t k, const int64_t *J, i
 }
 
 template <int RR>
-__global__ __launch_bounds__(256) void interp_kernel(int64_t n, int64_t k,
-                                                     const double2 *__restrict__ R,
-                                                     int64_t ldr, const int64_t *__restrict__ J,
-                                                     double2 *__restrict__ P, int64_t ldp,
-                                                     const int *__restrict__ mark) {
+RID_DEV void interp_body(int64_t n, int64_t k, const double2 *__restrict__ R, int64_t ldr,
+                         const int64_t *__restrict__ J, double2 *__restrict__ P, int64_t ldp,
+                         const int *__restrict__ mark, int64_t bx) {
   __shared__ int64_t Js[64 * RR];
   for (int t = threadIdx.x; t < 64 * RR; t += blockDim.x) {
     int64_t jt = (t < k) ? J[t] : 0;
@@ -39,7 +37,7 @@ __global__ __launch_bounds__(256) void interp_kernel(int64_t n, int64_t k,
   }
   __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int64_t j = int64_t(blockIdx.x) * 4 + (threadIdx.x >> 6);
+  const int64_t j = bx * 4 + (threadIdx.x >> 6);
   if (j >= n) return;
   double2 *pc = P + j * ldp;
   const int t0 = mark[j];
@@ -114,6 +112,24 @@ __global__ __launch_bounds__(256) void interp_kernel(int64_t n, int64_t k,
   }
 }
 
+template <int RR>
+__global__ __launch_bounds__(256) void interp_kernel(int64_t n, int64_t k,
+                                                     const double2 *__restrict__ R, int64_t ldr,
+                                                     const int64_t *__restrict__ J,
+                                                     double2 *__restrict__ P, int64_t ldp,
+                                                     const int *__restrict__ mark) {
+  interp_body<RR>(n, k, R, ldr, J, P, ldp, mark, blockIdx.x);
+}
+
+// A batch: block b solves the columns of quad tab[b].y of job tab[b].x.
+template <int RR>
+__global__ __launch_bounds__(256) void interp_kernel_grouped(const InterpJob *__restrict__ jobs,
+                                                             const int4 *__restrict__ tab) {
+  const int4 e = tab[blockIdx.x];
+  const InterpJob &jb = jobs[e.x];
+  interp_body<RR>(jb.n, jb.k, jb.R, jb.ldr, jb.J, jb.P, jb.ldp, jb.mark, e.y);
+}
+
 }  // namespace
 
 bool interp_supported(int64_t k) { return k >= 1 && k <= 256; }
@@ -142,6 +158,23 @@ hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R,
   else
     hipLaunchKernelGGL(interp_kernel<4>, dim3(nb), dim3(256), 0, st, n, k, R, ldr, J, P, ldp,
                        mark);
+  ps.stop();
+  return hipGetLastError();
+}
+
+hipError_t launch_interp_batch(hipStream_t st, int kmax, const InterpJob *djobs,
+                               const int4 *dtab, int64_t count, RidProf *prof) {
+  if (count == 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(count));
+  ProfScope ps(prof, st, RID_KERNEL_INTERP);
+  if (kmax <= 64)
+    hipLaunchKernelGGL(interp_kernel_grouped<1>, grid, dim3(256), 0, st, djobs, dtab);
+  else if (kmax <= 128)
+    hipLaunchKernelGGL(interp_kernel_grouped<2>, grid, dim3(256), 0, st, djobs, dtab);
+  else if (kmax <= 192)
+    hipLaunchKernelGGL(interp_kernel_grouped<3>, grid, dim3(256), 0, st, djobs, dtab);
+  else
+    hipLaunchKernelGGL(interp_kernel_grouped<4>, grid, dim3(256), 0, st, djobs, dtab);
   ps.stop();
   return hipGetLastError();
 }

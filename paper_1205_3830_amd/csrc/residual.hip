@@ -9,14 +9,21 @@
 //
 // The two passes over A are the HBM-bound kernels of the whole ID; both read
 // A with non-temporal loads (A is touched once per pass):
-//   ax_partial : z = A x~ ; a workgroup streams a 512-row slab of a range of
-//                columns (each column slab is one contiguous 8 KB read).
-//   ahz_partial: u = A^H z ; a workgroup stages a 2048-row chunk of z in LDS
-//                and each wave streams 8 columns of that chunk (32 KB
-//                contiguous reads each), reducing in registers then across
-//                lanes.
+//   ax  : z = A x~ ; a workgroup streams a 512-row slab of a range of
+//         columns (each column slab is one contiguous 8 KB read).
+//   ahz : u = A^H z ; a workgroup stages a 2048-row chunk of z in LDS and
+//         each wave streams 8 columns of that chunk (32 KB contiguous reads
+//         each), reducing in registers then across lanes.
 // Partial sums over column splits (resp. row splits) are reduced in a fixed
 // order by separate kernels, so results are bitwise reproducible.
+//
+// Every kernel body takes a per-job descriptor (ResJob) and a block index
+// inside that job, so the same bodies serve one ID (one launch per step,
+// grid = the job's blocks) and a batch of IDs (one launch per step over all
+// jobs, each block looking up its (job, block) pair in a table).
+#include <cstring>
+#include <type_traits>
+
 #include "rid_internal.hpp"
 
 namespace {
@@ -34,15 +41,18 @@ struct ResPlan {
   int64_t cpz;     // columns per ax split
   int64_t S_u;     // ahz row splits
   int64_t rpu;     // rows per ahz split
+  int64_t nb_ahz;  // ahz column blocks
   int64_t nb_px;   // P x partial blocks
+  int64_t nb_k;    // 256-blocks over k
   int64_t nb_n;    // 256-blocks over n
   int64_t nb_m;    // 256-blocks over m
 };
 
-ResPlan plan_res(int64_t m, int64_t n) {
+// target_blocks: workgroups wanted for the ax pass of this job alone
+ResPlan plan_res(int64_t m, int64_t n, int64_t k, int64_t target_blocks) {
   ResPlan p;
   p.nb_ax = (m + AX_ROWS - 1) / AX_ROWS;
-  int64_t S = (2048 + p.nb_ax - 1) / p.nb_ax;
+  int64_t S = (target_blocks + p.nb_ax - 1) / p.nb_ax;
   const int64_t maxS = (n + 31) / 32;
   if (S > maxS) S = maxS;
   if (S < 1) S = 1;
@@ -53,33 +63,44 @@ ResPlan plan_res(int64_t m, int64_t n) {
   p.rpu = AHZ_RS;
   p.S_u = (m + p.rpu - 1) / p.rpu;
   if (p.S_u < 1) p.S_u = 1;
+  p.nb_ahz = (n + AHZ_COLS - 1) / AHZ_COLS;
   p.nb_px = (n + PX_JC - 1) / PX_JC;
+  p.nb_k = (k + 255) / 256;
   p.nb_n = (n + 255) / 256;
   p.nb_m = (m + 255) / 256;
   return p;
 }
 
-struct ResWs {
+// One power-iteration problem: sizes, inputs, plan and workspace.
+struct ResJob {
+  int64_t m, n, k, lda, ldp;
+  const void *A;
+  const int64_t *J;
+  const double2 *P;
+  uint64_t seed;
+  double *sigma, *hist;
+  int pair;  // complex64 A: adjacent entries may be read as one 16-byte load
+  ResPlan pl;
   double2 *x, *xth, *xtl, *z, *uh, *ul;
   double *pxpart, *zpart, *upart, *zn_part, *wn_part, *scal;
 };
 
 template <class C>
-ResWs carve_res(C &c, int64_t m, int64_t n, int64_t k, const ResPlan &p) {
-  ResWs w;
-  w.x = c.template take<double2>(n);
-  w.xth = c.template take<double2>(n);
-  w.xtl = c.template take<double2>(n);
-  w.z = c.template take<double2>(m);
-  w.uh = c.template take<double2>(n);
-  w.ul = c.template take<double2>(n);
-  w.pxpart = c.template take<double>(size_t(p.nb_px) * size_t(k > 0 ? k : 1) * 4);
-  w.zpart = c.template take<double>(size_t(p.S_z) * size_t(m) * 4);
-  w.upart = c.template take<double>(size_t(p.S_u) * size_t(n) * 4);
-  w.zn_part = c.template take<double>(p.nb_m);
-  w.wn_part = c.template take<double>(p.nb_n);
-  w.scal = c.template take<double>(4);
-  return w;
+void carve_res(C &c, ResJob &r) {
+  const ResPlan &p = r.pl;
+  const int64_t m = r.m, n = r.n, k = r.k;
+  r.x = c.template take<double2>(n);
+  r.xth = c.template take<double2>(n);
+  r.xtl = c.template take<double2>(n);
+  r.z = c.template take<double2>(m);
+  r.uh = c.template take<double2>(n);
+  r.ul = c.template take<double2>(n);
+  r.pxpart = c.template take<double>(size_t(p.nb_px) * size_t(k > 0 ? k : 1) * 4);
+  r.zpart = c.template take<double>(size_t(p.S_z) * size_t(m) * 4);
+  r.upart = c.template take<double>(size_t(p.S_u) * size_t(n) * 4);
+  r.zn_part = c.template take<double>(p.nb_m);
+  r.wn_part = c.template take<double>(p.nb_n);
+  r.scal = c.template take<double>(4);
 }
 
 // scal[0] = last sigma, scal[1] = stopped flag, scal[2] = norm divisor
@@ -97,81 +118,74 @@ RID_DEV double block_sum(double v, double *sh) {
   return t;
 }
 
-__global__ __launch_bounds__(256) void x0_kernel(int64_t n, uint64_t seed, double2 *x,
-                                                 double *parts, double *scal) {
+// ------------------------------------------------------------------ bodies
+RID_DEV void x0_body(const ResJob &r, int64_t bx) {
   __shared__ double sh[4];
-  const int64_t j = blockIdx.x * int64_t(256) + threadIdx.x;
+  const int64_t j = bx * 256 + threadIdx.x;
   double v = 0.0;
-  if (j < n) {
-    const double2 g = rid_gauss(seed, 1u, 0u, static_cast<uint64_t>(j));
-    x[j] = g;
+  if (j < r.n) {
+    const double2 g = rid_gauss(r.seed, 1u, 0u, static_cast<uint64_t>(j));
+    r.x[j] = g;
     v = g.x * g.x + g.y * g.y;
   }
   const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) parts[blockIdx.x] = s;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    scal[0] = 0.0;
-    scal[1] = 0.0;
+  if (threadIdx.x == 0) r.wn_part[bx] = s;
+  if (bx == 0 && threadIdx.x == 0) {
+    r.scal[0] = 0.0;
+    r.scal[1] = 0.0;
   }
 }
 
-// Norm of a vector from its block partial sums; sets the stop flag when zero.
-__global__ __launch_bounds__(256) void wnorm_final_kernel(int64_t nparts, const double *parts,
-                                                          double *scal) {
+// Norm of x from its block partial sums; sets the stop flag when zero.
+RID_DEV void wnorm_final_body(const ResJob &r) {
   __shared__ double sh[4];
-  if (stopped(scal)) return;
+  if (stopped(r.scal)) return;
   double v = 0.0;
-  for (int64_t i = threadIdx.x; i < nparts; i += 256) v += parts[i];
+  for (int64_t i = threadIdx.x; i < r.pl.nb_n; i += 256) v += r.wn_part[i];
   const double s = block_sum(v, sh);
   if (threadIdx.x == 0) {
     const double nrm = sqrt(s);
     if (nrm == 0.0)
-      scal[1] = 1.0;
+      r.scal[1] = 1.0;
     else
-      scal[2] = nrm;
+      r.scal[2] = nrm;
   }
 }
 
-__global__ __launch_bounds__(256) void x_scale_kernel(int64_t n, double2 *x,
-                                                      const double *scal) {
-  if (stopped(scal)) return;
-  const int64_t j = blockIdx.x * int64_t(256) + threadIdx.x;
-  if (j < n) {
-    const double d = scal[2];
-    x[j] = make_double2(x[j].x / d, x[j].y / d);
+RID_DEV void x_scale_body(const ResJob &r, int64_t bx) {
+  if (stopped(r.scal)) return;
+  const int64_t j = bx * 256 + threadIdx.x;
+  if (j < r.n) {
+    const double d = r.scal[2];
+    r.x[j] = make_double2(r.x[j].x / d, r.x[j].y / d);
   }
 }
 
-__global__ __launch_bounds__(256) void xt_init_kernel(int64_t n, const double2 *x, double2 *xth,
-                                                      double2 *xtl, const double *scal) {
-  if (stopped(scal)) return;
-  const int64_t j = blockIdx.x * int64_t(256) + threadIdx.x;
-  if (j < n) {
-    xth[j] = x[j];
-    xtl[j] = make_double2(0.0, 0.0);
+RID_DEV void xt_init_body(const ResJob &r, int64_t bx) {
+  if (stopped(r.scal)) return;
+  const int64_t j = bx * 256 + threadIdx.x;
+  if (j < r.n) {
+    r.xth[j] = r.x[j];
+    r.xtl[j] = make_double2(0.0, 0.0);
   }
 }
 
-// partial (P x)_t over the column block, compensated
-__global__ __launch_bounds__(256) void px_partial_kernel(int64_t n, int64_t k,
-                                                         const double2 *__restrict__ P,
-                                                         int64_t ldp,
-                                                         const double2 *__restrict__ x,
-                                                         double *pxpart, const double *scal) {
-  if (stopped(scal)) return;
-  const int64_t j0 = int64_t(blockIdx.x) * PX_JC;
-  const int64_t j1 = min(n, j0 + PX_JC);
-  for (int64_t t = threadIdx.x; t < k; t += 256) {
+// partial (P x)_t over a block of columns, compensated
+RID_DEV void px_partial_body(const ResJob &r, int64_t bx) {
+  if (stopped(r.scal)) return;
+  const int64_t j0 = bx * PX_JC;
+  const int64_t j1 = min(r.n, j0 + PX_JC);
+  for (int64_t t = threadIdx.x; t < r.k; t += 256) {
     double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
     for (int64_t j = j0; j < j1; ++j) {
-      const double2 pe = P[t + j * ldp];
-      const double2 xj = x[j];
+      const double2 pe = r.P[t + j * r.ldp];
+      const double2 xj = r.x[j];
       dot2_acc(sr, cr, pe.x, xj.x);
       dot2_acc(sr, cr, -pe.y, xj.y);
       dot2_acc(si, ci, pe.x, xj.y);
       dot2_acc(si, ci, pe.y, xj.x);
     }
-    double *o = pxpart + (int64_t(blockIdx.x) * k + t) * 4;
+    double *o = r.pxpart + (bx * r.k + t) * 4;
     o[0] = sr;
     o[1] = cr;
     o[2] = si;
@@ -180,56 +194,52 @@ __global__ __launch_bounds__(256) void px_partial_kernel(int64_t n, int64_t k,
 }
 
 // x~_{J[t]} = x_{J[t]} - (P x)_t as a double-double pair
-__global__ __launch_bounds__(256) void px_final_kernel(int64_t n, int64_t k, int64_t nparts,
-                                                       const int64_t *J, const double2 *x,
-                                                       const double *pxpart, double2 *xth,
-                                                       double2 *xtl, const double *scal) {
-  if (stopped(scal)) return;
-  const int64_t t = blockIdx.x * int64_t(256) + threadIdx.x;
-  if (t >= k) return;
+RID_DEV void px_final_body(const ResJob &r, int64_t bx) {
+  if (stopped(r.scal)) return;
+  const int64_t t = bx * 256 + threadIdx.x;
+  if (t >= r.k) return;
   double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
-  for (int64_t b = 0; b < nparts; ++b) {
-    const double *o = pxpart + (b * k + t) * 4;
+  for (int64_t b = 0; b < r.pl.nb_px; ++b) {
+    const double *o = r.pxpart + (b * r.k + t) * 4;
     dd_add(sr, cr, o[0], o[1]);
     dd_add(si, ci, o[2], o[3]);
   }
-  const int64_t jt = J[t];
-  if (jt < 0 || jt >= n) return;
-  const double2 xj = x[jt];
+  const int64_t jt = r.J[t];
+  if (jt < 0 || jt >= r.n) return;
+  const double2 xj = r.x[jt];
   double ar = xj.x, ac = 0.0, ai = xj.y, aci = 0.0;
   dd_add(ar, ac, -sr, -cr);
   dd_add(ai, aci, -si, -ci);
   double hr, lr, hi, li;
   dd_norm(ar, ac, hr, lr);
   dd_norm(ai, aci, hi, li);
-  xth[jt] = make_double2(hr, hi);
-  xtl[jt] = make_double2(lr, li);
+  r.xth[jt] = make_double2(hr, hi);
+  r.xtl[jt] = make_double2(lr, li);
 }
 
-// Two rows of A, widened to double, at column offset `off` (elements).  For
-// complex128 the thread's rows are i0 and i0 + 256 (two 16-byte loads); for
-// complex64 they are the adjacent rows i0, i0 + 1, read with one 16-byte
-// load when the address is 16-byte aligned (PAIR) and with two 8-byte loads
-// otherwise.
-template <class TA, bool PAIR>
+// Two rows of A, widened to double, at element offset `off`.  complex128:
+// the thread's rows are i0 and i0 + 256 (two 16-byte loads); complex64: the
+// adjacent rows i0, i0 + 1, one 16-byte load when the pair is 16-byte
+// aligned, else two 8-byte loads.
+template <class TA>
 struct RowPair;
-template <bool PAIR>
-struct RowPair<double2, PAIR> {
+template <>
+struct RowPair<double2> {
   static constexpr int STEP = 256;  // distance between the thread's two rows
   static constexpr int LANE = 1;    // rows per thread index
-  RID_DEV static void load(const double2 *p0, const double2 *p1, bool ok0, bool ok1,
-                           int64_t off, double2 &a0, double2 &a1) {
+  RID_DEV static void load(const double2 *p0, const double2 *p1, bool ok0, bool ok1, int64_t off,
+                           bool, double2 &a0, double2 &a1) {
     a0 = ok0 ? ld_stream(p0 + off) : make_double2(0.0, 0.0);
     a1 = ok1 ? ld_stream(p1 + off) : make_double2(0.0, 0.0);
   }
 };
-template <bool PAIR>
-struct RowPair<float2, PAIR> {
+template <>
+struct RowPair<float2> {
   static constexpr int STEP = 1;
   static constexpr int LANE = 2;
   RID_DEV static void load(const float2 *p0, const float2 *p1, bool ok0, bool ok1, int64_t off,
-                           double2 &a0, double2 &a1) {
-    if (PAIR && ok1) {
+                           bool pair, double2 &a0, double2 &a1) {
+    if (pair && ok1) {
       ld_stream_pair(p0 + off, a0, a1);
     } else {
       a0 = ok0 ? ld_stream(p0 + off) : make_double2(0.0, 0.0);
@@ -238,23 +248,21 @@ struct RowPair<float2, PAIR> {
   }
 };
 
-// z partials: rows [512 rb, +512) x columns of split s.  TA is the storage
-// type of A (complex128 or complex64, widened to double on load).
-template <class TA, bool PAIR>
-__global__ __launch_bounds__(256) void ax_partial_kernel(int64_t m, int64_t n,
-                                                         const TA *__restrict__ A,
-                                                         int64_t lda,
-                                                         const double2 *__restrict__ xth,
-                                                         const double2 *__restrict__ xtl,
-                                                         int64_t cpz, double *zpart,
-                                                         const double *scal) {
-  using RP = RowPair<TA, PAIR>;
-  if (stopped(scal)) return;
-  const int64_t i0 = int64_t(blockIdx.x) * AX_ROWS + RP::LANE * threadIdx.x;
+// z partials: rows [512 bx, +512) x columns of split by
+template <class TA>
+RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
+  using RP = RowPair<TA>;
+  if (stopped(r.scal)) return;
+  const TA *A = static_cast<const TA *>(r.A);
+  const int64_t m = r.m, lda = r.lda;
+  const int64_t i0 = bx * AX_ROWS + RP::LANE * threadIdx.x;
   const int64_t i1 = i0 + RP::STEP;
   const bool ok0 = i0 < m, ok1 = i1 < m;
-  const int64_t jb = int64_t(blockIdx.y) * cpz;
-  const int64_t je = min(n, jb + cpz);
+  const int64_t jb = by * r.pl.cpz;
+  const int64_t je = min(r.n, jb + r.pl.cpz);
+  const bool pair = r.pair != 0;
+  const double2 *__restrict__ xth = r.xth;
+  const double2 *__restrict__ xtl = r.xtl;
   double s0r = 0, c0r = 0, s0i = 0, c0i = 0;
   double s1r = 0, c1r = 0, s1i = 0, c1i = 0;
   const TA *a0p = A + (ok0 ? i0 : 0);
@@ -281,16 +289,16 @@ __global__ __launch_bounds__(256) void ax_partial_kernel(int64_t m, int64_t n,
   for (; j + 4 <= je; j += 4) {
     double2 a0[4], a1[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) RP::load(a0p, a1p, ok0, ok1, (j + u) * lda, a0[u], a1[u]);
+    for (int u = 0; u < 4; ++u) RP::load(a0p, a1p, ok0, ok1, (j + u) * lda, pair, a0[u], a1[u]);
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc(a0[u], a1[u], xth[j + u], xtl[j + u]);
   }
   for (; j < je; ++j) {
     double2 a0, a1;
-    RP::load(a0p, a1p, ok0, ok1, j * lda, a0, a1);
+    RP::load(a0p, a1p, ok0, ok1, j * lda, pair, a0, a1);
     acc(a0, a1, xth[j], xtl[j]);
   }
-  double *zp = zpart + int64_t(blockIdx.y) * m * 4;
+  double *zp = r.zpart + by * m * 4;
   if (ok0) {
     zp[i0 * 4 + 0] = s0r;
     zp[i0 * 4 + 1] = c0r;
@@ -305,68 +313,62 @@ __global__ __launch_bounds__(256) void ax_partial_kernel(int64_t m, int64_t n,
   }
 }
 
-__global__ __launch_bounds__(256) void z_final_kernel(int64_t m, int64_t S, const double *zpart,
-                                                      double2 *z, double *parts,
-                                                      const double *scal) {
+RID_DEV void z_final_body(const ResJob &r, int64_t bx) {
   __shared__ double sh[4];
-  if (stopped(scal)) return;
-  const int64_t i = blockIdx.x * int64_t(256) + threadIdx.x;
+  if (stopped(r.scal)) return;
+  const int64_t i = bx * 256 + threadIdx.x;
   double v = 0.0;
-  if (i < m) {
+  if (i < r.m) {
     double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
-    for (int64_t s = 0; s < S; ++s) {
-      const double *o = zpart + (s * m + i) * 4;
+    for (int64_t s = 0; s < r.pl.S_z; ++s) {
+      const double *o = r.zpart + (s * r.m + i) * 4;
       dd_add(sr, cr, o[0], o[1]);
       dd_add(si, ci, o[2], o[3]);
     }
     const double zr = sr + cr, zi = si + ci;
-    z[i] = make_double2(zr, zi);
+    r.z[i] = make_double2(zr, zi);
     v = zr * zr + zi * zi;
   }
   const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) parts[blockIdx.x] = s;
+  if (threadIdx.x == 0) r.zn_part[bx] = s;
 }
 
-__global__ __launch_bounds__(256) void sigma_final_kernel(int64_t nparts, const double *parts,
-                                                          double *scal, double *sigma,
-                                                          double *hist, int t) {
+RID_DEV void sigma_final_body(const ResJob &r, int t) {
   __shared__ double sh[4];
-  if (stopped(scal)) {
-    if (threadIdx.x == 0 && hist) hist[t] = scal[0];
+  if (stopped(r.scal)) {
+    if (threadIdx.x == 0 && r.hist) r.hist[t] = r.scal[0];
     return;
   }
   double v = 0.0;
-  for (int64_t i = threadIdx.x; i < nparts; i += 256) v += parts[i];
+  for (int64_t i = threadIdx.x; i < r.pl.nb_m; i += 256) v += r.zn_part[i];
   const double s = block_sum(v, sh);
   if (threadIdx.x == 0) {
     const double sg = sqrt(s);
-    scal[0] = sg;
-    *sigma = sg;
-    if (hist) hist[t] = sg;
+    r.scal[0] = sg;
+    *r.sigma = sg;
+    if (r.hist) r.hist[t] = sg;
   }
 }
 
-// u partials: columns [32 cb, +32) x rows of split s; z chunk staged in LDS.
+// u partials: columns [32 bx, +32) x rows of split by; z chunk staged in LDS.
 // A lane takes one row per step for complex128 and two adjacent rows (one
 // 16-byte load when aligned) for complex64.
-template <class TA, bool PAIR>
-__global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
-                                                          const TA *__restrict__ A,
-                                                          int64_t lda,
-                                                          const double2 *__restrict__ z,
-                                                          int64_t rpu, double *upart,
-                                                          const double *scal) {
+template <class TA>
+RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
   constexpr bool C64 = sizeof(TA) == 8;
   __shared__ double2 zs[AHZ_RS];
-  if (stopped(scal)) return;
-  const int64_t r0 = int64_t(blockIdx.y) * rpu;
-  const int64_t r1 = min(m, r0 + rpu);
+  if (stopped(r.scal)) return;
+  const TA *A = static_cast<const TA *>(r.A);
+  const int64_t m = r.m, n = r.n, lda = r.lda;
+  const bool pair = r.pair != 0;
+  const int64_t r0 = by * r.pl.rpu;
+  const int64_t r1 = min(m, r0 + r.pl.rpu);
   const int rows = static_cast<int>(r1 - r0);
-  for (int i = threadIdx.x; i < rows; i += 256) zs[i] = z[r0 + i];
+  for (int i = threadIdx.x; i < rows; i += 256) zs[i] = r.z[r0 + i];
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int64_t jb = int64_t(blockIdx.x) * AHZ_COLS + wave * AHZ_CPW;
+  const int64_t jb = bx * AHZ_COLS + wave * AHZ_CPW;
   double sr[AHZ_CPW], cr[AHZ_CPW], si[AHZ_CPW], ci[AHZ_CPW];
   const TA *cp[AHZ_CPW];
   bool cok[AHZ_CPW];
@@ -403,7 +405,7 @@ __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
       for (int u = 0; u < AHZ_CPW; ++u) {
         if (!cok[u]) {
           a0[u] = a1[u] = make_double2(0.0, 0.0);
-        } else if (PAIR && two) {
+        } else if (pair && two) {
           ld_stream_pair(reinterpret_cast<const float2 *>(cp[u]) + i, a0[u], a1[u]);
         } else {
           a0[u] = ld_stream(cp[u] + i);
@@ -422,7 +424,7 @@ __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
     wave_sum_dd(sr[u], cr[u]);
     wave_sum_dd(si[u], ci[u]);
     if (lane == 0 && cok[u]) {
-      double *o = upart + (int64_t(blockIdx.y) * n + jb + u) * 4;
+      double *o = r.upart + (by * n + jb + u) * 4;
       o[0] = sr[u];
       o[1] = cr[u];
       o[2] = si[u];
@@ -431,49 +433,43 @@ __global__ __launch_bounds__(256) void ahz_partial_kernel(int64_t m, int64_t n,
   }
 }
 
-__global__ __launch_bounds__(256) void u_final_kernel(int64_t n, int64_t S, const double *upart,
-                                                      double2 *uh, double2 *ul,
-                                                      const double *scal) {
-  if (stopped(scal)) return;
-  const int64_t j = blockIdx.x * int64_t(256) + threadIdx.x;
-  if (j >= n) return;
+RID_DEV void u_final_body(const ResJob &r, int64_t bx) {
+  if (stopped(r.scal)) return;
+  const int64_t j = bx * 256 + threadIdx.x;
+  if (j >= r.n) return;
   double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
-  for (int64_t s = 0; s < S; ++s) {
-    const double *o = upart + (s * n + j) * 4;
+  for (int64_t s = 0; s < r.pl.S_u; ++s) {
+    const double *o = r.upart + (s * r.n + j) * 4;
     dd_add(sr, cr, o[0], o[1]);
     dd_add(si, ci, o[2], o[3]);
   }
   double hr, lr, hi, li;
   dd_norm(sr, cr, hr, lr);
   dd_norm(si, ci, hi, li);
-  uh[j] = make_double2(hr, hi);
-  ul[j] = make_double2(lr, li);
+  r.uh[j] = make_double2(hr, hi);
+  r.ul[j] = make_double2(lr, li);
 }
 
 // w_j = u_j - sum_t conj(P(t, j)) u_{J[t]}, compensated; x <- w (unscaled)
-__global__ __launch_bounds__(256) void w_kernel(int64_t n, int64_t k,
-                                                const double2 *__restrict__ P, int64_t ldp,
-                                                const int64_t *__restrict__ J,
-                                                const double2 *__restrict__ uh,
-                                                const double2 *__restrict__ ul, double2 *x,
-                                                double *parts, const double *scal) {
+RID_DEV void w_body(const ResJob &r, int64_t bx) {
   __shared__ double2 ujh[RES_KMAX];
   __shared__ double2 ujl[RES_KMAX];
   __shared__ double sh[4];
-  if (stopped(scal)) return;
+  if (stopped(r.scal)) return;
+  const int64_t n = r.n, k = r.k;
   for (int64_t t = threadIdx.x; t < k; t += 256) {
-    const int64_t jt = J[t];
+    const int64_t jt = r.J[t];
     const bool ok = jt >= 0 && jt < n;
-    ujh[t] = ok ? uh[jt] : make_double2(0.0, 0.0);
-    ujl[t] = ok ? ul[jt] : make_double2(0.0, 0.0);
+    ujh[t] = ok ? r.uh[jt] : make_double2(0.0, 0.0);
+    ujl[t] = ok ? r.ul[jt] : make_double2(0.0, 0.0);
   }
   __syncthreads();
-  const int64_t j = blockIdx.x * int64_t(256) + threadIdx.x;
+  const int64_t j = bx * 256 + threadIdx.x;
   double v = 0.0;
   if (j < n) {
-    const double2 h = uh[j], lo = ul[j];
+    const double2 h = r.uh[j], lo = r.ul[j];
     double sr = h.x, cr = lo.x, si = h.y, ci = lo.y;
-    const double2 *pc = P + j * ldp;
+    const double2 *pc = r.P + j * r.ldp;
     for (int64_t t = 0; t < k; ++t) {
       const double2 pe = pc[t];
       const double2 a = ujh[t], b = ujl[t];
@@ -488,87 +484,246 @@ __global__ __launch_bounds__(256) void w_kernel(int64_t n, int64_t k,
       ci = fma(pe.y, b.x, ci);
     }
     const double wr = sr + cr, wi = si + ci;
-    x[j] = make_double2(wr, wi);
+    r.x[j] = make_double2(wr, wi);
     v = wr * wr + wi * wi;
   }
   const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) parts[blockIdx.x] = s;
+  if (threadIdx.x == 0) r.wn_part[bx] = s;
+}
+
+// ------------------------------------------------------------------ launches
+// The steps of the iteration.  Single: the descriptor is the kernel argument
+// and the grid is the job's own.  Grouped: block b runs entry tab[b] =
+// (job, bx, by) of the step's table.
+enum Step : int {
+  ST_X0, ST_WNORM, ST_XSCALE, ST_XTINIT, ST_PXP, ST_PXF, ST_AX, ST_ZF, ST_SIGMA, ST_AHZ, ST_UF,
+  ST_W, ST_COUNT
+};
+
+template <class TA, int STEP>
+RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
+  if constexpr (STEP == ST_X0) x0_body(r, bx);
+  if constexpr (STEP == ST_WNORM) wnorm_final_body(r);
+  if constexpr (STEP == ST_XSCALE) x_scale_body(r, bx);
+  if constexpr (STEP == ST_XTINIT) xt_init_body(r, bx);
+  if constexpr (STEP == ST_PXP) px_partial_body(r, bx);
+  if constexpr (STEP == ST_PXF) px_final_body(r, bx);
+  if constexpr (STEP == ST_AX) ax_body<TA>(r, bx, by);
+  if constexpr (STEP == ST_ZF) z_final_body(r, bx);
+  if constexpr (STEP == ST_SIGMA) sigma_final_body(r, t);
+  if constexpr (STEP == ST_AHZ) ahz_body<TA>(r, bx, by);
+  if constexpr (STEP == ST_UF) u_final_body(r, bx);
+  if constexpr (STEP == ST_W) w_body(r, bx);
+}
+
+template <class TA, int STEP>
+__global__ __launch_bounds__(256) void step_single(ResJob r, int t) {
+  run_step<TA, STEP>(r, blockIdx.x, blockIdx.y, t);
+}
+
+template <class TA, int STEP>
+__global__ __launch_bounds__(256) void step_grouped(const ResJob *__restrict__ jobs,
+                                                    const int4 *__restrict__ tab, int t) {
+  const int4 e = tab[blockIdx.x];
+  run_step<TA, STEP>(jobs[e.x], e.y, e.z, t);
+}
+
+// blocks of one step for one job (gx by gy)
+void step_grid(int step, const ResJob &r, int64_t &gx, int64_t &gy) {
+  const ResPlan &p = r.pl;
+  gy = 1;
+  switch (step) {
+    case ST_X0: case ST_XSCALE: case ST_XTINIT: case ST_UF: case ST_W: gx = p.nb_n; break;
+    case ST_WNORM: case ST_SIGMA: gx = 1; break;
+    case ST_PXP: gx = r.k > 0 ? p.nb_px : 0; break;
+    case ST_PXF: gx = r.k > 0 ? p.nb_k : 0; break;
+    case ST_AX: gx = p.nb_ax; gy = p.S_z; break;
+    case ST_ZF: gx = p.nb_m; break;
+    case ST_AHZ: gx = p.nb_ahz; gy = p.S_u; break;
+    default: gx = 0;
+  }
+}
+
+template <class TA, int STEP>
+void launch_single(hipStream_t st, const ResJob &r, int t, RidProf *prof, int kernel_id) {
+  int64_t gx, gy;
+  step_grid(STEP, r, gx, gy);
+  if (gx * gy == 0) return;
+  ProfScope ps(kernel_id >= 0 ? prof : nullptr, st, kernel_id);
+  hipLaunchKernelGGL((step_single<TA, STEP>),
+                     dim3(static_cast<unsigned>(gx), static_cast<unsigned>(gy)), dim3(256), 0, st,
+                     r, t);
+}
+
+template <class TA, int STEP>
+void launch_grouped(hipStream_t st, const ResJob *jobs, const int4 *tab, int64_t count, int t,
+                    RidProf *prof, int kernel_id) {
+  if (count == 0) return;
+  ProfScope ps(kernel_id >= 0 ? prof : nullptr, st, kernel_id);
+  hipLaunchKernelGGL((step_grouped<TA, STEP>), dim3(static_cast<unsigned>(count)), dim3(256), 0,
+                     st, jobs, tab, t);
+}
+
+// The q-step power iteration as a sequence of step launches; L(step, t, id)
+// launches one step.
+template <class L>
+void power_iteration(L &&launch, int q) {
+  launch(ST_X0, 0, -1);
+  launch(ST_WNORM, 0, -1);
+  launch(ST_XSCALE, 0, -1);
+  for (int t = 0; t < q; ++t) {
+    launch(ST_XTINIT, t, -1);
+    launch(ST_PXP, t, -1);
+    launch(ST_PXF, t, -1);
+    launch(ST_AX, t, RID_KERNEL_AX);
+    launch(ST_ZF, t, -1);
+    launch(ST_SIGMA, t, -1);
+    if (t + 1 < q) {
+      launch(ST_AHZ, t, RID_KERNEL_AHZ);
+      launch(ST_UF, t, -1);
+      launch(ST_W, t, -1);
+      launch(ST_WNORM, t, -1);
+      launch(ST_XSCALE, t, -1);
+    }
+  }
+}
+
+// dispatch of a runtime step number to the templated launchers
+template <class TA, class F>
+void by_step(int step, F &&f) {
+  switch (step) {
+    case ST_X0: f(std::integral_constant<int, ST_X0>()); break;
+    case ST_WNORM: f(std::integral_constant<int, ST_WNORM>()); break;
+    case ST_XSCALE: f(std::integral_constant<int, ST_XSCALE>()); break;
+    case ST_XTINIT: f(std::integral_constant<int, ST_XTINIT>()); break;
+    case ST_PXP: f(std::integral_constant<int, ST_PXP>()); break;
+    case ST_PXF: f(std::integral_constant<int, ST_PXF>()); break;
+    case ST_AX: f(std::integral_constant<int, ST_AX>()); break;
+    case ST_ZF: f(std::integral_constant<int, ST_ZF>()); break;
+    case ST_SIGMA: f(std::integral_constant<int, ST_SIGMA>()); break;
+    case ST_AHZ: f(std::integral_constant<int, ST_AHZ>()); break;
+    case ST_UF: f(std::integral_constant<int, ST_UF>()); break;
+    case ST_W: f(std::integral_constant<int, ST_W>()); break;
+    default: break;
+  }
+}
+
+template <class TA>
+void single_iteration(hipStream_t st, const ResJob &r, int q, RidProf *prof) {
+  power_iteration(
+      [&](int step, int t, int id) {
+        by_step<TA>(step, [&](auto S) { launch_single<TA, decltype(S)::value>(st, r, t, prof, id); });
+      },
+      q);
+}
+
+template <class TA>
+void grouped_iteration(hipStream_t st, const ResJob *jobs, const int4 *dtab,
+                       const GroupedHost &gh, int q, RidProf *prof) {
+  power_iteration(
+      [&](int step, int t, int id) {
+        by_step<TA>(step, [&](auto S) {
+          launch_grouped<TA, decltype(S)::value>(st, jobs, dtab + gh.off[step], gh.cnt[step], t,
+                                                 prof, id);
+        });
+      },
+      q);
+}
+
+bool pair_ok(rid_dtype dtype, const void *A, int64_t lda) {
+  return dtype == RID_C64 && (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
 }
 
 }  // namespace
 
+// ------------------------------------------------------------------ one ID
 size_t residual_ws_bytes(int64_t m, int64_t n, int64_t k, int q) {
   (void)q;
-  const ResPlan p = plan_res(m, n);
+  ResJob r{};
+  r.m = m;
+  r.n = n;
+  r.k = k;
+  r.pl = plan_res(m, n, k, 2048);
   WsCarve c(nullptr);
-  carve_res(c, m, n, k, p);
+  carve_res(c, r);
   return c.off + 256;
-}
-
-template <class TA, bool PAIR>
-hipError_t residual_impl(hipStream_t st, int64_t m, int64_t n, int64_t k, const TA *A,
-                         int64_t lda, const int64_t *J, const double2 *P, int64_t ldp, int q,
-                         uint64_t seed, double *sigma, double *hist, void *ws, RidProf *prof) {
-  if (k > RES_KMAX) return hipErrorInvalidValue;
-  const ResPlan p = plan_res(m, n);
-  WsCarve c(ws);
-  const ResWs w = carve_res(c, m, n, k, p);
-  const dim3 blk(256);
-  const dim3 gn(static_cast<unsigned>(p.nb_n));
-  const dim3 gm(static_cast<unsigned>(p.nb_m));
-  hipLaunchKernelGGL(x0_kernel, gn, blk, 0, st, n, seed, w.x, w.wn_part, w.scal);
-  hipLaunchKernelGGL(wnorm_final_kernel, dim3(1), blk, 0, st, p.nb_n, w.wn_part, w.scal);
-  hipLaunchKernelGGL(x_scale_kernel, gn, blk, 0, st, n, w.x, w.scal);
-  for (int t = 0; t < q; ++t) {
-    hipLaunchKernelGGL(xt_init_kernel, gn, blk, 0, st, n, w.x, w.xth, w.xtl, w.scal);
-    if (k > 0) {
-      hipLaunchKernelGGL(px_partial_kernel, dim3(static_cast<unsigned>(p.nb_px)), blk, 0, st,
-                         n, k, P, ldp, w.x, w.pxpart, w.scal);
-      hipLaunchKernelGGL(px_final_kernel, dim3(static_cast<unsigned>((k + 255) / 256)), blk, 0,
-                         st, n, k, p.nb_px, J, w.x, w.pxpart, w.xth, w.xtl, w.scal);
-    }
-    {
-      ProfScope ps(prof, st, RID_KERNEL_AX);
-      hipLaunchKernelGGL((ax_partial_kernel<TA, PAIR>),
-                         dim3(static_cast<unsigned>(p.nb_ax), static_cast<unsigned>(p.S_z)),
-                         blk, 0, st, m, n, A, lda, w.xth, w.xtl, p.cpz, w.zpart, w.scal);
-    }
-    hipLaunchKernelGGL(z_final_kernel, gm, blk, 0, st, m, p.S_z, w.zpart, w.z, w.zn_part,
-                       w.scal);
-    hipLaunchKernelGGL(sigma_final_kernel, dim3(1), blk, 0, st, p.nb_m, w.zn_part, w.scal,
-                       sigma, hist, t);
-    if (t + 1 < q) {
-      {
-        ProfScope ps(prof, st, RID_KERNEL_AHZ);
-        hipLaunchKernelGGL((ahz_partial_kernel<TA, PAIR>),
-                           dim3(static_cast<unsigned>((n + AHZ_COLS - 1) / AHZ_COLS),
-                                static_cast<unsigned>(p.S_u)),
-                           blk, 0, st, m, n, A, lda, w.z, p.rpu, w.upart, w.scal);
-      }
-      hipLaunchKernelGGL(u_final_kernel, gn, blk, 0, st, n, p.S_u, w.upart, w.uh, w.ul,
-                         w.scal);
-      hipLaunchKernelGGL(w_kernel, gn, blk, 0, st, n, k, P, ldp, J, w.uh, w.ul, w.x,
-                         w.wn_part, w.scal);
-      hipLaunchKernelGGL(wnorm_final_kernel, dim3(1), blk, 0, st, p.nb_n, w.wn_part, w.scal);
-      hipLaunchKernelGGL(x_scale_kernel, gn, blk, 0, st, n, w.x, w.scal);
-    }
-  }
-  return hipGetLastError();
 }
 
 hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t k,
                            const void *A, int64_t lda, const int64_t *J, const double2 *P,
                            int64_t ldp, int q, uint64_t seed, double *sigma, double *hist,
                            void *ws, RidProf *prof) {
-  if (dtype == RID_C64) {
-    // pairs of adjacent entries are 16-byte aligned when A is and lda is even
-    const bool pair = (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
-    if (pair)
-      return residual_impl<float2, true>(st, m, n, k, static_cast<const float2 *>(A), lda, J, P,
-                                         ldp, q, seed, sigma, hist, ws, prof);
-    return residual_impl<float2, false>(st, m, n, k, static_cast<const float2 *>(A), lda, J, P,
-                                        ldp, q, seed, sigma, hist, ws, prof);
+  if (k > RES_KMAX) return hipErrorInvalidValue;
+  ResJob r{};
+  r.m = m;
+  r.n = n;
+  r.k = k;
+  r.lda = lda;
+  r.ldp = ldp;
+  r.A = A;
+  r.J = J;
+  r.P = P;
+  r.seed = seed;
+  r.sigma = sigma;
+  r.hist = hist;
+  r.pair = pair_ok(dtype, A, lda) ? 1 : 0;
+  r.pl = plan_res(m, n, k, 2048);
+  WsCarve c(ws);
+  carve_res(c, r);
+  if (dtype == RID_C64)
+    single_iteration<float2>(st, r, q, prof);
+  else
+    single_iteration<double2>(st, r, q, prof);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ a batch of IDs
+void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, void *ws,
+                          GroupedHost *out) {
+  WsCarve c(ws);
+  std::vector<ResJob> jobs(count);
+  for (int i = 0; i < count; ++i) {
+    ResJob &r = jobs[i];
+    r = ResJob{};
+    r.m = bj[i].m;
+    r.n = bj[i].n;
+    r.k = bj[i].k;
+    r.lda = bj[i].lda;
+    r.ldp = bj[i].ldp;
+    r.A = bj[i].A;
+    r.J = bj[i].J;
+    r.P = bj[i].P;
+    r.seed = bj[i].seed;
+    r.sigma = bj[i].sigma;
+    r.hist = nullptr;
+    r.pair = pair_ok(dtype, bj[i].A, bj[i].lda) ? 1 : 0;
+    // a job's own passes need few workgroups: the batch fills the device
+    r.pl = plan_res(r.m, r.n, r.k, 64);
+    carve_res(c, r);
   }
-  return residual_impl<double2, false>(st, m, n, k, static_cast<const double2 *>(A), lda, J, P,
-                                       ldp, q, seed, sigma, hist, ws, prof);
+  out->ws_bytes = c.off + 256;
+  out->jobs.resize(sizeof(ResJob) * count);
+  if (count) memcpy(out->jobs.data(), jobs.data(), sizeof(ResJob) * count);
+  out->tab.clear();
+  for (int s = 0; s < ST_COUNT; ++s) {
+    out->off[s] = static_cast<int64_t>(out->tab.size());
+    for (int i = 0; i < count; ++i) {
+      int64_t gx, gy;
+      step_grid(s, jobs[i], gx, gy);
+      for (int64_t y = 0; y < gy; ++y)
+        for (int64_t x = 0; x < gx; ++x)
+          out->tab.push_back(make_int4(i, static_cast<int>(x), static_cast<int>(y), 0));
+    }
+    out->cnt[s] = static_cast<int64_t>(out->tab.size()) - out->off[s];
+  }
+}
+
+hipError_t launch_residual_batch(hipStream_t st, rid_dtype dtype, const void *djobs,
+                                 const int4 *dtab, const GroupedHost &gh, int q, RidProf *prof) {
+  const ResJob *jobs = static_cast<const ResJob *>(djobs);
+  if (dtype == RID_C64)
+    grouped_iteration<float2>(st, jobs, dtab, gh, q, prof);
+  else
+    grouped_iteration<double2>(st, jobs, dtab, gh, q, prof);
+  return hipGetLastError();
 }

@@ -64,6 +64,7 @@ struct rid_ctx {
   size_t ws_bytes = 0;
   RidProf prof;
   int sketch_kind = RID_SKETCH_GAUSSIAN;  // operator drawn by rid_sketch / rid_decompose
+  hipStream_t cap_stream = nullptr;       // stream used to capture batch graphs
 };
 
 // Bump allocator over the handle workspace (256-byte aligned pieces).
@@ -77,6 +78,15 @@ struct WsCarve {
     T *p = reinterpret_cast<T *>(base ? base + off : nullptr);
     off += count * sizeof(T);
     return p;
+  }
+  // the byte offset of the next piece (for layouts computed before the base
+  // address is known)
+  template <class T>
+  size_t take_off(size_t count) {
+    off = (off + 255) & ~size_t(255);
+    const size_t o = off;
+    off += count * sizeof(T);
+    return o;
   }
 };
 
@@ -211,6 +221,50 @@ RID_DEV void wave_sum_dd(double &s, double &c) {
   c = __shfl(c, 0, 64);
 }
 
+// ------------------------------------------------------------------ batches
+// One job of a batch as the library sees it (device pointers for data).
+struct RidBatchJob {
+  int64_t m, n, k, l, lda, ldp;
+  const void *A;
+  uint64_t seed;
+  int64_t *J;
+  double2 *P;
+  double *sigma;
+};
+
+// One sketch of a batch (device pointers).  part holds S x 2l x n partial
+// sums (double for FP64 products, float for FP32); Y is l x n, ldy = l.
+struct SketchJob {
+  int64_t m, n, l, lda, ldg, pchunk;
+  const void *A;
+  const double2 *G;
+  void *part;
+  double2 *Y;
+  int64_t S;
+  int64_t red_blocks;  // blocks of the reduce for this job
+};
+
+// One interpolation of a batch: R (k x n, ldr), J (k), P (k x n, ldp), and
+// mark[j] = t if column j is J[t], -1 otherwise.
+struct InterpJob {
+  int64_t n, k, ldr, ldp;
+  const double2 *R;
+  const int64_t *J;
+  double2 *P;
+  const int *mark;
+};
+
+// Host-side description of a grouped launch sequence: per-job descriptors
+// (opaque bytes, copied to the device as an array) and, per step, a table of
+// (job, block x, block y) entries, concatenated.
+struct GroupedHost {
+  std::vector<char> jobs;
+  std::vector<int4> tab;
+  int64_t off[16];
+  int64_t cnt[16];
+  size_t ws_bytes = 0;
+};
+
 // ------------------------------------------------------------------ launchers
 // Each returns hipSuccess or the launch error.  Sizes are validated by the
 // caller (api.hip); the kernels bound-check every access themselves.
@@ -239,6 +293,22 @@ hipError_t launch_sketch(hipStream_t st, rid_dtype dtype, rid_prec prec, int64_t
                          int64_t l, const void *A, int64_t lda, const double2 *G, int64_t ldg,
                          double2 *Y, int64_t ldy, void *part, RidProf *prof);
 
+// Grouped sketch over a batch: for each MT bucket the (job, bx, split)
+// table slice, then the grouped reduce over (job, block, blocks-of-job).
+hipError_t launch_sketch_batch(hipStream_t st, rid_dtype dtype, rid_prec prec,
+                               const SketchJob *djobs, const int4 *dtab, const int *mts,
+                               const int64_t *off, const int64_t *cnt, int nbuckets,
+                               int64_t red_off, int64_t red_cnt, RidProf *prof);
+int sketch_pick_mt(int64_t l);  // tiles per block for one batch job (0: unsupported)
+
+bool batch_job_supported(const RidBatchJob &j);
+hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                     const RidBatchJob *bj, int count, int q, double rank_tol, int *status);
+
+// Grouped interpolation (k <= 256): tab entries (job, column quad).
+hipError_t launch_interp_batch(hipStream_t st, int kmax, const InterpJob *djobs,
+                               const int4 *dtab, int64_t count, RidProf *prof);
+
 // per-precision launchers behind launch_sketch
 size_t sketch_f64_ws_bytes(int64_t m, int64_t n, int64_t l);
 template <class TA>
@@ -263,6 +333,13 @@ bool interp_supported(int64_t k);
 hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R, int64_t ldr,
                          const int64_t *J, double2 *P, int64_t ldp, void *ws,
                          RidProf *prof);
+
+// Grouped power iteration over a batch: setup on the host (ws == nullptr
+// only sizes the workspace), then one launch per step for all jobs.
+void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, void *ws,
+                          GroupedHost *out);
+hipError_t launch_residual_batch(hipStream_t st, rid_dtype dtype, const void *djobs,
+                                 const int4 *dtab, const GroupedHost &gh, int q, RidProf *prof);
 
 size_t residual_ws_bytes(int64_t m, int64_t n, int64_t k, int q);
 hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t k,

@@ -19,10 +19,10 @@ namespace {
 typedef float f4 __attribute__((ext_vector_type(4)));
 
 template <int MT, class TA>
-__global__ __launch_bounds__(256) void sketch_f32_kernel(
+RID_DEV void sketch_f32_body(
     int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
     const double2 *__restrict__ G, int64_t ldg, float *__restrict__ out, int64_t ldo,
-    int64_t split_stride, int64_t pchunk) {
+    int64_t split_stride, int64_t pchunk, int64_t bx, int64_t by, int64_t bz) {
   constexpr int NR = 8 * MT;
   constexpr int RS = 17;
   constexpr int PER = (NR * 16 + 255) / 256;
@@ -33,11 +33,11 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(
   const int q = lane >> 4;
   const int r16 = lane & 15;
   const int c = lane & 1;
-  const int64_t jcol = int64_t(blockIdx.x) * 64 + wave * 16 + r16;
+  const int64_t jcol = bx * 64 + wave * 16 + r16;
   const bool colok = jcol < n;
-  const int64_t pbeg = int64_t(blockIdx.y) * pchunk;
+  const int64_t pbeg = by * pchunk;
   const int64_t pend = min(m, pbeg + pchunk);
-  const int64_t g0 = int64_t(blockIdx.z) * NR;
+  const int64_t g0 = bz * NR;
 
   f4 acc[MT];
 #pragma unroll
@@ -110,7 +110,7 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(
     b ^= 1;
   }
   if (!colok) return;
-  float *o = out + int64_t(blockIdx.y) * split_stride + jcol * ldo;
+  float *o = out + by * split_stride + jcol * ldo;
   const int64_t rows = 2 * l;
   const int64_t mu0 = 2 * g0;
 #pragma unroll
@@ -120,6 +120,26 @@ __global__ __launch_bounds__(256) void sketch_f32_kernel(
       const int64_t mu = mu0 + int64_t(t) * 16 + 4 * q + r;
       if (mu < rows) o[mu] = acc[t][r];
     }
+}
+
+// One sketch: grid (column blocks, K splits, row slices).
+template <int MT, class TA>
+__global__ __launch_bounds__(256) void sketch_f32_kernel(
+    int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
+    const double2 *__restrict__ G, int64_t ldg, float *__restrict__ out, int64_t ldo,
+    int64_t split_stride, int64_t pchunk) {
+  sketch_f32_body<MT, TA>(m, n, l, A, lda, G, ldg, out, ldo, split_stride, pchunk, blockIdx.x,
+                          blockIdx.y, blockIdx.z);
+}
+
+// A batch: block b runs (job, column block, split) = tab[b] of that job.
+template <int MT, class TA>
+__global__ __launch_bounds__(256) void sketch_f32_kernel_grouped(const SketchJob *__restrict__ jobs,
+                                                     const int4 *__restrict__ tab) {
+  const int4 e = tab[blockIdx.x];
+  const SketchJob &j = jobs[e.x];
+  sketch_f32_body<MT, TA>(j.m, j.n, j.l, static_cast<const TA *>(j.A), j.lda, j.G, j.ldg,
+                   static_cast<float *>(j.part), 2 * j.l, 2 * j.l * j.n, j.pchunk, e.y, e.z, 0);
 }
 
 // Y(mu, j) = sum over splits (in order, in double) of part[s](mu, j).
@@ -135,6 +155,22 @@ __global__ __launch_bounds__(256) void sketch_f32_reduce_kernel(int64_t rows, in
     double s = 0.0;
     for (int sp = 0; sp < S; ++sp) s += static_cast<double>(part[sp * total + e]);
     Y[j * ldy2 + mu] = s;
+  }
+}
+
+// A batch of reduces: entry (job, block, blocks of the job).
+__global__ __launch_bounds__(256) void sketch_f32_reduce_kernel_grouped(const SketchJob *__restrict__ jobs,
+                                                     const int4 *__restrict__ tab) {
+  const int4 en = tab[blockIdx.x];
+  const SketchJob &jb = jobs[en.x];
+  const int64_t rows = 2 * jb.l;
+  const int64_t total = rows * jb.n;
+  const float *part = static_cast<const float *>(jb.part);
+  double *Y = reinterpret_cast<double *>(jb.Y);
+  for (int64_t e = int64_t(en.y) * 256 + threadIdx.x; e < total; e += int64_t(en.z) * 256) {
+    double s = 0.0;
+    for (int64_t sp = 0; sp < jb.S; ++sp) s += static_cast<double>(part[sp * total + e]);
+    Y[e] = s;
   }
 }
 
@@ -223,6 +259,41 @@ hipError_t launch_sketch_f32(hipStream_t st, int64_t m, int64_t n, int64_t l, co
   return hipGetLastError();
 }
 
+hipError_t launch_sketch_batch_f32(hipStream_t st, rid_dtype dtype, const SketchJob *djobs,
+                                     const int4 *dtab, const int *mts, const int64_t *off,
+                                     const int64_t *cnt, int nbuckets, int64_t red_off,
+                                     int64_t red_cnt, RidProf *prof) {
+  ProfScope ps(prof, st, RID_KERNEL_SKETCH);
+  for (int b = 0; b < nbuckets; ++b) {
+    if (cnt[b] == 0) continue;
+    const dim3 grid(static_cast<unsigned>(cnt[b]));
+    const int4 *tb = dtab + off[b];
+    switch (mts[b]) {
+#define RID_MT_CASE(X)                                                                    \
+  case X:                                                                                 \
+    if (dtype == RID_C64)                                                                 \
+      hipLaunchKernelGGL((sketch_f32_kernel_grouped<X, float2>), grid, dim3(256), 0, st, djobs, tb);  \
+    else                                                                                  \
+      hipLaunchKernelGGL((sketch_f32_kernel_grouped<X, double2>), grid, dim3(256), 0, st, djobs, tb); \
+    break;
+      RID_MT_CASE(1) RID_MT_CASE(2) RID_MT_CASE(3) RID_MT_CASE(4) RID_MT_CASE(5)
+      RID_MT_CASE(6) RID_MT_CASE(7) RID_MT_CASE(8) RID_MT_CASE(9) RID_MT_CASE(10)
+      RID_MT_CASE(11) RID_MT_CASE(12) RID_MT_CASE(13) RID_MT_CASE(14) RID_MT_CASE(15)
+      RID_MT_CASE(16) RID_MT_CASE(18) RID_MT_CASE(20) RID_MT_CASE(22) RID_MT_CASE(24)
+      RID_MT_CASE(26) RID_MT_CASE(28)
+#undef RID_MT_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  ps.stop();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || red_cnt == 0) return e;
+  hipLaunchKernelGGL(sketch_f32_reduce_kernel_grouped, dim3(static_cast<unsigned>(red_cnt)), dim3(256), 0, st, djobs,
+                     dtab + red_off);
+  return hipGetLastError();
+}
+
 template hipError_t launch_sketch_f32<double2>(hipStream_t, int64_t, int64_t, int64_t,
                                                const double2 *, int64_t, const double2 *,
                                                int64_t, double2 *, int64_t, void *, RidProf *);
@@ -231,6 +302,28 @@ template hipError_t launch_sketch_f32<float2>(hipStream_t, int64_t, int64_t, int
                                               double2 *, int64_t, void *, RidProf *);
 
 // ---------------------------------------------------------------- dispatch
+hipError_t launch_sketch_batch_f64(hipStream_t st, rid_dtype dtype, const SketchJob *djobs,
+                                   const int4 *dtab, const int *mts, const int64_t *off,
+                                   const int64_t *cnt, int nbuckets, int64_t red_off,
+                                   int64_t red_cnt, RidProf *prof);
+
+hipError_t launch_sketch_batch(hipStream_t st, rid_dtype dtype, rid_prec prec,
+                               const SketchJob *djobs, const int4 *dtab, const int *mts,
+                               const int64_t *off, const int64_t *cnt, int nbuckets,
+                               int64_t red_off, int64_t red_cnt, RidProf *prof) {
+  if (prec == RID_FP32)
+    return launch_sketch_batch_f32(st, dtype, djobs, dtab, mts, off, cnt, nbuckets, red_off,
+                                   red_cnt, prof);
+  return launch_sketch_batch_f64(st, dtype, djobs, dtab, mts, off, cnt, nbuckets, red_off,
+                                 red_cnt, prof);
+}
+
+int sketch_pick_mt(int64_t l) {
+  const int64_t tiles = (2 * l + 15) / 16;
+  const int mt = pick_mt32(tiles);
+  return mt >= tiles ? mt : 0;
+}
+
 bool sketch_supported(rid_dtype dtype, rid_prec prec) {
   return (dtype == RID_C128 || dtype == RID_C64) && (prec == RID_FP64 || prec == RID_FP32);
 }

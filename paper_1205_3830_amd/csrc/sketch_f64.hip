@@ -27,10 +27,10 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 template <int MT, class TA>
-__global__ __launch_bounds__(256) void sketch_f64_kernel(
+RID_DEV void sketch_f64_body(
     int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
     const double2 *__restrict__ G, int64_t ldg, double *__restrict__ out, int64_t ldo,
-    int64_t split_stride, int64_t pchunk) {
+    int64_t split_stride, int64_t pchunk, int64_t bx, int64_t by, int64_t bz) {
   constexpr int NR = 8 * MT;                       // G rows of the slab
   constexpr int RS = 17;                           // LDS row stride (complex entries)
   constexpr int PER = (NR * 16 + 255) / 256;       // staged entries per thread
@@ -41,11 +41,11 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(
   const int q = lane >> 4;
   const int r16 = lane & 15;
   const int c = lane & 1;
-  const int64_t jcol = int64_t(blockIdx.x) * 64 + wave * 16 + r16;
+  const int64_t jcol = bx * 64 + wave * 16 + r16;
   const bool colok = jcol < n;
-  const int64_t pbeg = int64_t(blockIdx.y) * pchunk;
+  const int64_t pbeg = by * pchunk;
   const int64_t pend = min(m, pbeg + pchunk);
-  const int64_t g0 = int64_t(blockIdx.z) * NR;     // first G row of this z-slice
+  const int64_t g0 = bz * NR;     // first G row of this z-slice
 
   d4 acc[MT];
 #pragma unroll
@@ -120,7 +120,7 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(
   if (!colok) return;
   // D layout of the f64 16x16x4 MFMA: lane, register r -> row 4r + lane/16,
   // column lane % 16.
-  double *o = out + int64_t(blockIdx.y) * split_stride + jcol * ldo;
+  double *o = out + by * split_stride + jcol * ldo;
   const int64_t rows = 2 * l;
   const int64_t mu0 = 2 * g0;
 #pragma unroll
@@ -130,6 +130,26 @@ __global__ __launch_bounds__(256) void sketch_f64_kernel(
       const int64_t mu = mu0 + int64_t(t) * 16 + 4 * r + q;
       if (mu < rows) o[mu] = acc[t][r];
     }
+}
+
+// One sketch: grid (column blocks, K splits, row slices).
+template <int MT, class TA>
+__global__ __launch_bounds__(256) void sketch_f64_kernel(
+    int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
+    const double2 *__restrict__ G, int64_t ldg, double *__restrict__ out, int64_t ldo,
+    int64_t split_stride, int64_t pchunk) {
+  sketch_f64_body<MT, TA>(m, n, l, A, lda, G, ldg, out, ldo, split_stride, pchunk, blockIdx.x,
+                          blockIdx.y, blockIdx.z);
+}
+
+// A batch: block b runs (job, column block, split) = tab[b] of that job.
+template <int MT, class TA>
+__global__ __launch_bounds__(256) void sketch_f64_kernel_grouped(const SketchJob *__restrict__ jobs,
+                                                     const int4 *__restrict__ tab) {
+  const int4 e = tab[blockIdx.x];
+  const SketchJob &j = jobs[e.x];
+  sketch_f64_body<MT, TA>(j.m, j.n, j.l, static_cast<const TA *>(j.A), j.lda, j.G, j.ldg,
+                   static_cast<double *>(j.part), 2 * j.l, 2 * j.l * j.n, j.pchunk, e.y, e.z, 0);
 }
 
 // Y(mu, j) = sum over splits s = 0..S-1 (in order) of part[s](mu, j).
@@ -146,6 +166,22 @@ __global__ __launch_bounds__(256) void sketch_reduce_kernel(int64_t rows, int64_
     double s = 0.0;
     for (int sp = 0; sp < S; ++sp) s += part[sp * stride + e];
     Y[j * ldy2 + mu] = s;
+  }
+}
+
+// A batch of reduces: entry (job, block, blocks of the job).
+__global__ __launch_bounds__(256) void sketch_reduce_kernel_grouped(const SketchJob *__restrict__ jobs,
+                                                     const int4 *__restrict__ tab) {
+  const int4 en = tab[blockIdx.x];
+  const SketchJob &jb = jobs[en.x];
+  const int64_t rows = 2 * jb.l;
+  const int64_t total = rows * jb.n;
+  const double *part = static_cast<const double *>(jb.part);
+  double *Y = reinterpret_cast<double *>(jb.Y);
+  for (int64_t e = int64_t(en.y) * 256 + threadIdx.x; e < total; e += int64_t(en.z) * 256) {
+    double s = 0.0;
+    for (int64_t sp = 0; sp < jb.S; ++sp) s += static_cast<double>(part[sp * total + e]);
+    Y[e] = s;
   }
 }
 
@@ -245,6 +281,41 @@ hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l, co
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(sketch_reduce_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
                      st, 2 * l, n, p.S, part, reinterpret_cast<double *>(Y), 2 * ldy);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_batch_f64(hipStream_t st, rid_dtype dtype, const SketchJob *djobs,
+                                     const int4 *dtab, const int *mts, const int64_t *off,
+                                     const int64_t *cnt, int nbuckets, int64_t red_off,
+                                     int64_t red_cnt, RidProf *prof) {
+  ProfScope ps(prof, st, RID_KERNEL_SKETCH);
+  for (int b = 0; b < nbuckets; ++b) {
+    if (cnt[b] == 0) continue;
+    const dim3 grid(static_cast<unsigned>(cnt[b]));
+    const int4 *tb = dtab + off[b];
+    switch (mts[b]) {
+#define RID_MT_CASE(X)                                                                    \
+  case X:                                                                                 \
+    if (dtype == RID_C64)                                                                 \
+      hipLaunchKernelGGL((sketch_f64_kernel_grouped<X, float2>), grid, dim3(256), 0, st, djobs, tb);  \
+    else                                                                                  \
+      hipLaunchKernelGGL((sketch_f64_kernel_grouped<X, double2>), grid, dim3(256), 0, st, djobs, tb); \
+    break;
+      RID_MT_CASE(1) RID_MT_CASE(2) RID_MT_CASE(3) RID_MT_CASE(4) RID_MT_CASE(5)
+      RID_MT_CASE(6) RID_MT_CASE(7) RID_MT_CASE(8) RID_MT_CASE(9) RID_MT_CASE(10)
+      RID_MT_CASE(11) RID_MT_CASE(12) RID_MT_CASE(13) RID_MT_CASE(14) RID_MT_CASE(15)
+      RID_MT_CASE(16) RID_MT_CASE(18) RID_MT_CASE(20) RID_MT_CASE(22) RID_MT_CASE(24)
+      RID_MT_CASE(26) RID_MT_CASE(28)
+#undef RID_MT_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  ps.stop();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || red_cnt == 0) return e;
+  hipLaunchKernelGGL(sketch_reduce_kernel_grouped, dim3(static_cast<unsigned>(red_cnt)), dim3(256), 0, st, djobs,
+                     dtab + red_off);
   return hipGetLastError();
 }
 

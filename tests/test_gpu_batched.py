@@ -1,0 +1,134 @@
+"""GPU tests of the batched form: many IDs of uneven sizes in one call.
+
+Each job of a batch must give the result of the single-job path with the
+same inputs (and of the oracle): J exact beyond the pivot-gap tolerance,
+P within 1e-10 (FP64 products; the batch sums the sketch over different
+K splits, so Y differs in the last bits), sigma within the end-to-end bound.
+A rank-deficient job fails alone; the graph-captured and directly launched
+batches give bitwise the same results; repeated calls are bitwise equal.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+rid = pytest.importorskip("paper_1205_3830_amd")
+
+
+@pytest.fixture(scope="module")
+def h():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    hd = rid.rid_create(0)
+    yield hd
+    rid.rid_destroy(hd)
+
+
+def dev(A):
+    return torch.from_numpy(np.ascontiguousarray(np.asarray(A).T)).to("cuda").t()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+def make_jobs(count, seed, dtype=np.complex128, noise=1e-9, mmax=1500, nmax=700):
+    rng = np.random.default_rng(seed)
+    jobs = []
+    for i in range(count):
+        m = int(np.exp(rng.uniform(np.log(100), np.log(mmax))))
+        n = int(np.exp(rng.uniform(np.log(40), np.log(nmax))))
+        k = int(rng.integers(4, min(40, n, m - 8) + 1))
+        l = k + 8
+        A = synth.lowrank(m, n, k, noise, seed=1000 + i).astype(dtype)
+        jobs.append((A, k, l, 17 + i))
+    return jobs
+
+
+def test_batch_matches_single_and_oracle_fp64(h):
+    jobs = make_jobs(12, 1)
+    As = [dev(A) for A, _, _, _ in jobs]
+    Js, Ps, sig, status, used = rid.rid_decompose_batched(
+        h, As, [j[1] for j in jobs], [j[2] for j in jobs], [j[3] for j in jobs], q=6)
+    assert status == [0] * len(jobs)
+    for i, (A, k, l, s) in enumerate(jobs):
+        J1, P1, s1, u1 = rid.rid_decompose(h, As[i], k, l, seed=s, q=6)
+        assert used[i] == u1
+        Jb, Pb, sb = host(Js[i]), host(Ps[i]), float(host(sig[i])[0])
+        r = oracle.decompose(A, k, l, seed=s, q=6)
+        gaps = r["gaps"]
+        for t in range(k):
+            if gaps[t] <= 1e-10:
+                break
+            assert Jb[t] == r["J"][t] == host(J1)[t], (i, t)
+        assert np.array_equal(Pb[:, Jb], np.eye(k))
+        assert np.abs(Pb - host(P1)).max() <= 1e-10 * max(1.0, np.abs(host(P1)).max())
+        dP = Pb - r["P"]
+        assert np.abs(dP).max() <= 1e-10 * max(1.0, np.abs(r["P"]).max())
+        tol = 1e-10 * r["sigma"] + 2 * np.linalg.norm(A[:, Jb]) * np.linalg.norm(dP)
+        assert abs(sb - r["sigma"]) <= tol, i
+
+
+def test_batch_complex64_fp32(h):
+    jobs = make_jobs(10, 2, dtype=np.complex64, noise=1e-2)
+    As = [dev(A) for A, _, _, _ in jobs]
+    Js, Ps, sig, status, _ = rid.rid_decompose_batched(
+        h, As, [j[1] for j in jobs], [j[2] for j in jobs], [j[3] for j in jobs], q=6,
+        prec=rid.RID_FP32, rank_tol=1e-5)
+    assert status == [0] * len(jobs)
+    for i, (A, k, l, s) in enumerate(jobs):
+        r = oracle.decompose(A.astype(np.complex128), k, l, seed=s, q=6)
+        Jb, Pb, sb = host(Js[i]), host(Ps[i]), float(host(sig[i])[0])
+        for t in range(k):
+            if r["gaps"][t] <= 1e-4:
+                break
+            assert Jb[t] == r["J"][t], (i, t)
+        assert np.array_equal(Pb[:, Jb], np.eye(k))
+        assert 0.5 * r["sigma"] <= sb <= 2.0 * r["sigma"], i
+
+
+def test_batch_rank_failure_is_per_job(h):
+    jobs = make_jobs(5, 3)
+    bad = synth.lowrank(300, 120, 3, 0.0, seed=9)       # rank 3 < k = 6
+    jobs.insert(2, (bad, 6, 10, 5))
+    As = [dev(A) for A, _, _, _ in jobs]
+    Js, Ps, sig, status, used = rid.rid_decompose_batched(
+        h, As, [j[1] for j in jobs], [j[2] for j in jobs], [j[3] for j in jobs], q=3,
+        max_retries=1, raise_on_rank=False)
+    assert status[2] == rid.RID_ERR_RANK and used[2] == 6
+    assert all(st == 0 for i, st in enumerate(status) if i != 2)
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_decompose_batched(h, As, [j[1] for j in jobs], [j[2] for j in jobs],
+                                  [j[3] for j in jobs], q=3, max_retries=0)
+    assert ei.value.status == rid.RID_ERR_RANK
+
+
+def test_batch_graph_and_direct_launch_agree_bitwise(h, monkeypatch):
+    jobs = make_jobs(7, 4)
+    As = [dev(A) for A, _, _, _ in jobs]
+    args = ([j[1] for j in jobs], [j[2] for j in jobs], [j[3] for j in jobs])
+    a = rid.rid_decompose_batched(h, As, *args, q=4)
+    b = rid.rid_decompose_batched(h, As, *args, q=4)
+    monkeypatch.setenv("RID_BATCH_GRAPH", "0")
+    c = rid.rid_decompose_batched(h, As, *args, q=4)
+    for i in range(len(jobs)):
+        for res in (b, c):
+            assert torch.equal(a[0][i], res[0][i])
+            assert torch.equal(a[1][i], res[1][i])
+            assert torch.equal(a[2][i], res[2][i])
+
+
+def test_batch_invalid_job_rejected(h):
+    A = dev(synth.lowrank(50, 20, 3, 0.0, seed=1))
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_decompose_batched(h, [A], [5], [4], [0])       # l < k
+    assert ei.value.status == rid.RID_ERR_INVALID_ARG
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_decompose_batched(h, [A], [3], [300], [0])     # l > m, and > 224
+    assert ei.value.status == rid.RID_ERR_INVALID_ARG
