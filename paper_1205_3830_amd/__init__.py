@@ -348,37 +348,71 @@ def rid_profile_read(h, kernel: int):
     return ms.value, cnt.value
 
 
+class _Slices:
+    """Per-job views into one output slab, made when indexed."""
+
+    def __init__(self, base, spans, shape_of):
+        self._base, self._spans, self._shape_of = base, spans, shape_of
+
+    def __len__(self):
+        return len(self._spans)
+
+    def __getitem__(self, i):
+        if isinstance(i, slice):
+            return [self[j] for j in range(*i.indices(len(self)))]
+        off, size, shape = self._spans[i]
+        return self._shape_of(self._base[off:off + size], shape)
+
+    def __iter__(self):
+        return (self[i] for i in range(len(self)))
+
+
 def rid_decompose_batched(h, As, ks, ls, seeds, q: int = 10, max_retries: int = 3,
                           rank_tol: float = 1e-12, prec: int = RID_FP64, stream=None,
                           raise_on_rank: bool = True):
     """Many IDs in one call.  As: list of column-major device tensors (one
     dtype); ks, ls, seeds: per-job ints.  Returns (Js, Ps, sigmas, status,
-    seeds_used) with per-job device tensors and host lists."""
+    seeds_used): per-job device views (J: k int64, P: k x n complex128
+    column-major, sigma: 1 float64) into three output slabs, and host lists."""
+    import numpy as np
     torch = _torch()
     count = len(As)
-    arr = (rid_job * max(count, 1))()
-    Js, Ps, sig = [], [], []
-    dt = None
-    for i, A in enumerate(As):
-        m, n = A.shape
-        k, l = int(ks[i]), int(ls[i])
-        c = _dtype_code(A)
-        if dt is None:
-            dt = c
-        elif c != dt:
-            raise ValueError("all matrices of a batch must share one dtype")
-        J = torch.empty(k, dtype=torch.int64, device="cuda")
-        P = _new_colmajor(k, n, torch.complex128)
-        s = torch.zeros(1, dtype=torch.float64, device="cuda")
-        Js.append(J)
-        Ps.append(P)
-        sig.append(s)
-        arr[i] = rid_job(m, n, k, l, A.data_ptr(), _ld_colmajor(A, "A"), int(seeds[i]),
-                         J.data_ptr(), P.data_ptr(), _ld_colmajor(P, "P"), s.data_ptr())
+    dts = {A.dtype for A in As}
+    if len(dts) > 1:
+        raise ValueError("all matrices of a batch must share one dtype")
+    dt = _dtype_code(As[0]) if count else RID_C128
+    ks = [int(x) for x in ks]
+    ls = [int(x) for x in ls]
+    ns = [int(A.shape[1]) for A in As]
+    tab = np.zeros((max(count, 1), 11), dtype=np.int64)
+    if count:
+        tab[:count, 0] = [int(A.shape[0]) for A in As]
+        tab[:count, 1] = ns
+        tab[:count, 2] = ks
+        tab[:count, 3] = ls
+        tab[:count, 4] = [A.data_ptr() for A in As]
+        tab[:count, 5] = [_ld_colmajor(A, "A") for A in As]
+        tab[:count, 6] = np.array([int(x) for x in seeds], dtype=np.uint64).view(np.int64)
+    koff = np.concatenate([[0], np.cumsum(ks)]).astype(np.int64)
+    poff = np.concatenate([[0], np.cumsum(np.array(ks, dtype=np.int64) *
+                                          np.array(ns, dtype=np.int64))]).astype(np.int64)
+    Jall = torch.empty(max(int(koff[-1]), 1), dtype=torch.int64, device="cuda")
+    Pall = torch.empty(max(int(poff[-1]), 1), dtype=torch.complex128, device="cuda")
+    sall = torch.zeros(max(count, 1), dtype=torch.float64, device="cuda")
+    if count:
+        tab[:count, 7] = Jall.data_ptr() + 8 * koff[:-1]
+        tab[:count, 8] = Pall.data_ptr() + 16 * poff[:-1]
+        tab[:count, 9] = ks
+        tab[:count, 10] = sall.data_ptr() + 8 * np.arange(count, dtype=np.int64)
     status = (_I * max(count, 1))()
     used = (_U64 * max(count, 1))()
-    st = _L.rid_decompose_batched(h, _stream(stream), RID_C128 if dt is None else dt, prec, arr,
+    st = _L.rid_decompose_batched(h, _stream(stream), dt, prec,
+                                  ctypes.cast(tab.ctypes.data, ctypes.POINTER(rid_job)),
                                   count, q, max_retries, rank_tol, status, used)
     if st != RID_OK and not (st == RID_ERR_RANK and not raise_on_rank):
         raise RidError(st, "rid_decompose_batched")
+    Js = _Slices(Jall, [(int(koff[i]), ks[i], None) for i in range(count)], lambda v, s: v)
+    Ps = _Slices(Pall, [(int(poff[i]), ks[i] * ns[i], (ns[i], ks[i])) for i in range(count)],
+                 lambda v, s: v.view(s).t())
+    sig = _Slices(sall, [(i, 1, None) for i in range(count)], lambda v, s: v)
     return Js, Ps, sig, [status[i] for i in range(count)], [int(used[i]) for i in range(count)]

@@ -4,11 +4,11 @@
 // costs the same number of launches as one ID.  The launch sequence is
 // captured into a HIP graph and replayed on the caller's stream.
 //
-// The pivoted QR of a job's sketch (l x n, small) runs in one workgroup per
-// job that loops over the k steps with block barriers only -- no
-// cross-workgroup waits.  Jobs are ordered largest first so the long QRs
-// start early.  A job whose sketch has rank < k is redrawn with seed + 1
-// (Sec. 2), up to max_retries times, in a follow-up batch of the failures.
+// The pivoted QR takes one grouped launch per step: every job's sketch is
+// split into 64-column workgroups as in the single-ID QR, and a job whose
+// k steps are done leaves the later launches at once.  A job whose sketch
+// has rank < k is redrawn with seed + 1 (Sec. 2), up to max_retries times,
+// in a follow-up batch of the failures.
 #include <algorithm>
 #include <climits>
 #include <cstdlib>
@@ -18,17 +18,6 @@
 #include "rid_internal.hpp"
 
 namespace {
-
-constexpr int QR_NMAX = 4096;  // columns per job held in LDS by the batch QR
-
-struct QrJob {
-  int64_t l, n, k, ldy;
-  double2 *Y;
-  int64_t *J;    // caller's J (k entries)
-  int *mark;     // n: step at which the column was picked, -1 otherwise
-  int *status;   // per-job status word
-  double rank_tol;
-};
 
 struct OpJob {
   int64_t rows, cols, ld;
@@ -66,198 +55,6 @@ __global__ __launch_bounds__(256) void operator_grouped_kernel(const OpJob *__re
   }
 }
 
-// ---------------------------------------------------------------- QR, one block per job
-template <int LPC>
-RID_DEV double group_sum(double v) {
-#pragma unroll
-  for (int off = LPC / 2; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
-// Householder QR with exact column pivoting of one job's Y (as rid_pivqr,
-// Sec. 2), all k steps in this workgroup.  Columns are processed LPC lanes
-// per column (RPL rows per lane, l <= LPC RPL), 64 / LPC columns per wave.
-template <int LPC, int RPL>
-__global__ __launch_bounds__(256) void pivqr_job_kernel(const QrJob *__restrict__ jobs,
-                                                        const int4 *__restrict__ order) {
-  constexpr int CPW = 64 / LPC;
-  constexpr int CPB = 4 * CPW;
-  __shared__ double nrm[QR_NMAX];
-  __shared__ int picked[QR_NMAX];
-  __shared__ double2 v_s[LPC * RPL];
-  __shared__ double rv1[256], rv2[256];
-  __shared__ int64_t ri[256];
-  __shared__ double2 tau_s;
-  __shared__ double beta_s;
-  __shared__ int64_t jstar_s;
-  __shared__ int fail_s;
-  __shared__ double nu0_s;
-
-  const QrJob jb = jobs[order[blockIdx.x].x];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int grp = lane / LPC;
-  const int gl = lane % LPC;
-  const int64_t l = jb.l, n = jb.n, k = jb.k;
-  for (int64_t j = tid; j < n; j += 256) picked[j] = -1;
-  if (tid == 0) *jb.status = RID_OK;
-  __syncthreads();
-
-  double2 tau = make_double2(0.0, 0.0);
-  for (int64_t t = 0; t <= k; ++t) {
-    const int64_t r0 = t > 0 ? t - 1 : 0;
-    // 1. apply the reflector of step t-1; trailing norms for step t
-    for (int64_t c0 = 0; c0 < n; c0 += CPB) {
-      const int64_t j = c0 + wave * CPW + grp;
-      const bool act = j < n && picked[j] < 0;
-      double2 *col = jb.Y + (act ? j : 0) * jb.ldy;
-      double2 y[RPL];
-#pragma unroll
-      for (int h = 0; h < RPL; ++h) {
-        const int64_t row = r0 + gl + LPC * h;
-        y[h] = (act && row < l) ? col[row] : make_double2(0.0, 0.0);
-      }
-      if (t > 0) {
-        double dr = 0.0, di = 0.0;
-#pragma unroll
-        for (int h = 0; h < RPL; ++h) {
-          const double2 v = v_s[gl + LPC * h];
-          dr += v.x * y[h].x + v.y * y[h].y;
-          di += v.x * y[h].y - v.y * y[h].x;
-        }
-        dr = group_sum<LPC>(dr);
-        di = group_sum<LPC>(di);
-        const double cr = tau.x * dr + tau.y * di;
-        const double ci = tau.x * di - tau.y * dr;
-#pragma unroll
-        for (int h = 0; h < RPL; ++h) {
-          const double2 v = v_s[gl + LPC * h];
-          y[h].x -= v.x * cr - v.y * ci;
-          y[h].y -= v.x * ci + v.y * cr;
-          const int64_t row = r0 + gl + LPC * h;
-          if (act && row < l) col[row] = y[h];
-        }
-      }
-      if (t < k) {
-        double ss = 0.0;
-#pragma unroll
-        for (int h = 0; h < RPL; ++h) {
-          const int64_t row = r0 + gl + LPC * h;
-          if (row >= t && row < l) ss += y[h].x * y[h].x + y[h].y * y[h].y;
-        }
-        ss = group_sum<LPC>(ss);
-        if (gl == 0 && j < n) nrm[j] = act ? sqrt(ss) : -1.0;
-      }
-    }
-    if (t == k) break;
-    __syncthreads();
-
-    // 2. pivot: largest trailing norm, lowest index on exact ties
-    double b1 = -1.0, b2 = -1.0;
-    int64_t bi = INT64_MAX;
-    for (int64_t j = tid; j < n; j += 256) {
-      const double v = nrm[j];
-      if (v < 0.0) continue;
-      if (v > b1 || (v == b1 && j < bi)) {
-        b2 = fmax(b2, b1);
-        b1 = v;
-        bi = j;
-      } else {
-        b2 = fmax(b2, v);
-      }
-    }
-    rv1[tid] = b1;
-    rv2[tid] = b2;
-    ri[tid] = bi;
-    __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-      if (tid < s) {
-        const double a1 = rv1[tid], c1 = rv1[tid + s];
-        const int64_t ai = ri[tid], ci = ri[tid + s];
-        const bool other = (c1 > a1) || (c1 == a1 && ci < ai);
-        const double lose = other ? a1 : c1;
-        rv2[tid] = fmax(fmax(rv2[tid], rv2[tid + s]), lose);
-        if (other) {
-          rv1[tid] = c1;
-          ri[tid] = ci;
-        }
-      }
-      __syncthreads();
-    }
-    if (tid == 0) {
-      const double nu1 = rv1[0];
-      if (t == 0) nu0_s = nu1;
-      const bool fail = !(nu1 > 0.0) || nu1 <= jb.rank_tol * nu0_s;
-      fail_s = fail ? 1 : 0;
-      jstar_s = ri[0];
-      if (fail) {
-        *jb.status = RID_ERR_RANK;
-      } else {
-        jb.J[t] = ri[0];
-      }
-    }
-    __syncthreads();
-    if (fail_s) return;
-    const int64_t js = jstar_s;
-
-    // 3. reflector of step t from column js, built by the lanes that own it
-    const int owner_wave = static_cast<int>((js % CPB) / CPW);
-    const int owner_grp = static_cast<int>(js % CPW);
-    if (wave == owner_wave && grp == owner_grp) {
-      double2 *col = jb.Y + js * jb.ldy;
-      double2 x[RPL];
-      double ss = 0.0;
-#pragma unroll
-      for (int h = 0; h < RPL; ++h) {
-        const int64_t row = t + gl + LPC * h;
-        x[h] = row < l ? col[row] : make_double2(0.0, 0.0);
-        if (gl + LPC * h >= 1) ss += x[h].x * x[h].x + x[h].y * x[h].y;
-      }
-      const double xnorm2 = group_sum<LPC>(ss);
-      const double ar = __shfl(x[0].x, grp * LPC, 64);
-      const double ai = __shfl(x[0].y, grp * LPC, 64);
-      double2 tv;
-      double beta;
-      double2 scale;
-      if (xnorm2 == 0.0 && ai == 0.0) {
-        tv = make_double2(0.0, 0.0);
-        beta = ar;
-        scale = make_double2(0.0, 0.0);
-      } else {
-        const double mag = sqrt(ar * ar + ai * ai + xnorm2);
-        beta = (ar >= 0.0) ? -mag : mag;
-        tv = make_double2((beta - ar) / beta, -ai / beta);
-        const double dr = ar - beta, di = ai;
-        const double den = dr * dr + di * di;
-        scale = make_double2(dr / den, -di / den);
-      }
-#pragma unroll
-      for (int h = 0; h < RPL; ++h) {
-        const int idx = gl + LPC * h;
-        const int64_t row = t + idx;
-        double2 v;
-        if (idx == 0)
-          v = make_double2(1.0, 0.0);
-        else
-          v = make_double2(x[h].x * scale.x - x[h].y * scale.y,
-                           x[h].x * scale.y + x[h].y * scale.x);
-        // v_s is indexed from row t - 1 + 1 = t in the next apply (r0 = t)
-        v_s[idx] = row < l ? v : make_double2(0.0, 0.0);
-        if (row < l) col[row] = (idx == 0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
-      }
-      if (gl == 0) {
-        tau_s = tv;
-        beta_s = beta;
-        picked[js] = static_cast<int>(t);
-      }
-    }
-    __syncthreads();
-    tau = tau_s;
-  }
-  for (int64_t j = tid; j < n; j += 256) jb.mark[j] = picked[j];
-}
-
 // ---------------------------------------------------------------- host side
 struct Buf {
   std::vector<char> bytes;
@@ -278,7 +75,7 @@ bool use_graph() {
 }  // namespace
 
 bool batch_job_supported(const RidBatchJob &j) {
-  return j.l <= 256 && j.n <= QR_NMAX && j.k <= 256 && sketch_pick_mt(j.l) > 0;
+  return j.l <= 256 && j.k <= 256 && sketch_pick_mt(j.l) > 0;
 }
 
 // Runs one batch (each job once, with the seeds in bj); writes per-job
@@ -288,7 +85,7 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   // ---- plans and workspace layout
   std::vector<SketchJob> sk(count);
   std::vector<OpJob> op(count);
-  std::vector<QrJob> qr(count);
+  std::vector<PivJob> qr(count);
   std::vector<InterpJob> in(count);
   std::vector<int> mt(count);
   int kmax = 1;
@@ -316,9 +113,14 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
     const size_t el = prec == RID_FP32 ? sizeof(float) : sizeof(double);
     offPart[i] = sc.take_off<char>(size_t(S) * size_t(2 * bj[i].l) * size_t(bj[i].n) * el);
   }
+  // the QR workspace reuses the scratch region too (G is dead by then)
+  WsCarve qc(nullptr);
+  std::vector<size_t> offQr(count);
+  for (int i = 0; i < count; ++i)
+    offQr[i] = qc.take_off<char>(pivqr_job_ws_bytes(bj[i].l, bj[i].n));
   GroupedHost res;
   residual_batch_setup(bj, count, dtype, nullptr, &res);
-  const size_t scratch = std::max(sc.off, res.ws_bytes) + 256;
+  const size_t scratch = std::max(std::max(sc.off, qc.off), res.ws_bytes) + 256;
 
   // ---- descriptor + table upload region goes first
   // (sizes are known only after the tables are built; build them with a
@@ -350,14 +152,10 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
         t_sk[bucket].push_back(make_int4(i, static_cast<int>(x), static_cast<int>(s), 0));
     const int64_t nq = (bj[i].n + 3) / 4;
     for (int64_t x = 0; x < nq; ++x) t_in.push_back(make_int4(i, static_cast<int>(x), 0, 0));
+    const int64_t nbq = pivqr_blocks(bj[i].n);
+    for (int64_t x = 0; x < nbq; ++x)
+      t_qr.push_back(make_int4(i, static_cast<int>(x), static_cast<int>(nbq), 0));
   }
-  // QR: largest jobs first
-  std::vector<int> ord(count);
-  std::iota(ord.begin(), ord.end(), 0);
-  std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) {
-    return bj[a].l * bj[a].n * bj[a].k > bj[b].l * bj[b].n * bj[b].k;
-  });
-  for (int i : ord) t_qr.push_back(make_int4(i, 0, 0, 0));
 
   // descriptor region size
   const size_t nbuck = mts.size();
@@ -408,7 +206,9 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
     sk[i] = SketchJob{bj[i].m, bj[i].n, bj[i].l, bj[i].lda, bj[i].m, pchunk, bj[i].A, G,
                       sbase + offPart[i], Y, (bj[i].m + pchunk - 1) / pchunk, 0};
     op[i] = OpJob{bj[i].l, bj[i].m, bj[i].m, bj[i].seed, G, h->sketch_kind};
-    qr[i] = QrJob{bj[i].l, bj[i].n, bj[i].k, bj[i].l, Y, bj[i].J, mark, dstatus + i, rank_tol};
+    qr[i] = PivJob{bj[i].l, bj[i].n, bj[i].k, bj[i].l, Y, bj[i].J, mark, dstatus + i, rank_tol,
+                   nullptr, nullptr, nullptr, nullptr, nullptr};
+    pivqr_job_carve(sbase + offQr[i], qr[i]);
     in[i] = InterpJob{bj[i].n, bj[i].k, bj[i].l, bj[i].ldp, Y, bj[i].J, bj[i].P, mark};
   }
   const size_t o_sk = tabs.put(sk.data(), count);
@@ -436,7 +236,7 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   // ---- the launch sequence
   const SketchJob *d_sk = reinterpret_cast<const SketchJob *>(base + o_sk);
   const OpJob *d_op = reinterpret_cast<const OpJob *>(base + o_op);
-  const QrJob *d_qr = reinterpret_cast<const QrJob *>(base + o_qr);
+  const PivJob *d_qr = reinterpret_cast<const PivJob *>(base + o_qr);
   const InterpJob *d_in = reinterpret_cast<const InterpJob *>(base + o_in);
   const void *d_res = base + o_res;
   const int4 *d_top = reinterpret_cast<const int4 *>(base + o_top);
@@ -458,16 +258,8 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
                             static_cast<int>(nbuck), red_off, static_cast<int64_t>(t_red.size()),
                             nullptr);
     if (e != hipSuccess) return e;
-    if (lmax <= 80)
-      hipLaunchKernelGGL((pivqr_job_kernel<16, 5>), dim3(static_cast<unsigned>(count)), dim3(256),
-                         0, st, d_qr, d_tqr);
-    else if (lmax <= 128)
-      hipLaunchKernelGGL((pivqr_job_kernel<16, 8>), dim3(static_cast<unsigned>(count)), dim3(256),
-                         0, st, d_qr, d_tqr);
-    else
-      hipLaunchKernelGGL((pivqr_job_kernel<32, 8>), dim3(static_cast<unsigned>(count)), dim3(256),
-                         0, st, d_qr, d_tqr);
-    e = hipGetLastError();
+    e = launch_pivqr_batch(st, lmax, kmax, d_qr, d_tqr, static_cast<int64_t>(t_qr.size()),
+                           nullptr);
     if (e != hipSuccess) return e;
     e = launch_interp_batch(st, kmax, d_in, d_tin, static_cast<int64_t>(t_in.size()), nullptr);
     if (e != hipSuccess) return e;

@@ -84,31 +84,34 @@ __global__ void pivqr_init_kernel(int64_t n, int *pstep, int *status) {
   if (j == 0) *status = RID_OK;
 }
 
+// Step t of the QR for workgroup bx of nb (the column owner of [64 bx, 64 bx + 64)).
 template <int RR>
-__global__ __launch_bounds__(256) void pivqr_step_kernel(int t, int64_t l, int64_t n,
-                                                         int64_t k, double2 *Y, int64_t ldy,
-                                                         int64_t *perm, double *gaps,
-                                                         double rank_tol, PivWs w,
-                                                         int *status) {
+RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y, int64_t ldy,
+                             int64_t *perm, double *gaps, double rank_tol, const PivWs &w,
+                             int *status, int64_t bx, int64_t nb) {
   __shared__ double2 v_s[64 * RR];
   __shared__ double2 best_col[4][64 * RR];
   __shared__ Cand red[256];
   __shared__ double2 tau_s;
   __shared__ double beta_s;
+  __shared__ int status_s;
 
-  if (*status != RID_OK) return;
+  // workgroup 0 of this same launch may be writing the status word: one
+  // read, shared, so that the whole workgroup leaves or stays together
+  if (threadIdx.x == 0) status_s = *status;
+  __syncthreads();
+  if (status_s != RID_OK) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int nb = gridDim.x;
-  const int64_t cbeg = int64_t(blockIdx.x) * PQ_COLS;
+  const int64_t cbeg = bx * PQ_COLS;
   int64_t jstar = -1;
   const int64_t r0 = (t > 0) ? t - 1 : 0;  // first row touched by this kernel
 
   if (t > 0) {
     // ---- 1. pivot of step t-1
     Cand cd = cand_empty();
-    for (int b = tid; b < nb; b += 256) {
+    for (int64_t b = tid; b < nb; b += 256) {
       Cand x{w.cnorm[b], w.cidx[b], w.cnorm2[b], 0};
       if (x.v1 < 0.0) x = cand_empty();
       cd = cand_merge(cd, x);
@@ -123,7 +126,7 @@ __global__ __launch_bounds__(256) void pivqr_step_kernel(int t, int64_t l, int64
     const double nu1 = best.v1;
     const double nu0 = (t == 1) ? nu1 : *w.nu0;
     const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
-    if (blockIdx.x == 0 && tid == 0) {
+    if (bx == 0 && tid == 0) {
       perm[t - 1] = best.i1;
       if (gaps) gaps[t - 1] = (best.v2 < 0.0) ? 1.0 : (nu1 - best.v2) / nu1;
       if (t == 1) *w.nu0 = nu1;
@@ -255,17 +258,53 @@ __global__ __launch_bounds__(256) void pivqr_step_kernel(int t, int64_t l, int64
   Cand bc = cand_empty();
   for (int wv = 0; wv < 4; ++wv) bc = cand_merge(bc, red[wv]);
   if (tid == 0) {
-    w.cnorm[blockIdx.x] = bc.v1;
-    w.cnorm2[blockIdx.x] = bc.v2;
-    w.cidx[blockIdx.x] = bc.i1;
+    w.cnorm[bx] = bc.v1;
+    w.cnorm2[bx] = bc.v2;
+    w.cidx[bx] = bc.i1;
   }
   if (bc.src >= 0) {
-    double2 *dst = w.ccol + int64_t(blockIdx.x) * l;
+    double2 *dst = w.ccol + bx * l;
     for (int idx = tid; idx < 64 * RR; idx += 256) {
       const int64_t row = r0 + idx;
       if (row >= t && row < l) dst[row] = best_col[bc.src][idx];
     }
   }
+}
+
+template <int RR>
+__global__ __launch_bounds__(256) void pivqr_step_kernel(int t, int64_t l, int64_t n,
+                                                         int64_t k, double2 *Y, int64_t ldy,
+                                                         int64_t *perm, double *gaps,
+                                                         double rank_tol, PivWs w,
+                                                         int *status) {
+  pivqr_step_body<RR>(t, l, n, k, Y, ldy, perm, gaps, rank_tol, w, status, blockIdx.x,
+                      gridDim.x);
+}
+
+// A batch: block b is column block tab[b].y of job tab[b].x (tab[b].z blocks
+// in that job).  Jobs with k < t have finished and leave at once.
+template <int RR>
+__global__ __launch_bounds__(256) void pivqr_step_grouped(int t, const PivJob *__restrict__ jobs,
+                                                          const int4 *__restrict__ tab) {
+  const int4 e = tab[blockIdx.x];
+  const PivJob &jb = jobs[e.x];
+  if (t > jb.k) return;
+  const PivWs w{jb.cnorm, jb.cnorm2, jb.cidx, jb.ccol, jb.mark, jb.nu0};
+  pivqr_step_body<RR>(t, jb.l, jb.n, jb.k, jb.Y, jb.ldy, jb.J, nullptr, jb.rank_tol, w,
+                      jb.status, e.y, e.z);
+}
+
+// A batch: the picked-step marks of each job's own columns start at -1; the
+// first block of a job also clears its status word.
+__global__ __launch_bounds__(256) void pivqr_init_grouped(const PivJob *__restrict__ jobs,
+                                                          const int4 *__restrict__ tab) {
+  const int4 e = tab[blockIdx.x];
+  const PivJob &jb = jobs[e.x];
+  if (threadIdx.x < PQ_COLS) {
+    const int64_t j = int64_t(e.y) * PQ_COLS + threadIdx.x;
+    if (j < jb.n) jb.mark[j] = -1;
+  }
+  if (e.y == 0 && threadIdx.x == 0) *jb.status = RID_OK;
 }
 
 // perm[k + r] = r-th unpicked column in increasing order (one workgroup).
@@ -310,6 +349,49 @@ void launch_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y, i
 bool pivqr_supported(int64_t l) { return l >= 1 && l <= 256; }
 
 size_t pivqr_ws_bytes(int64_t l, int64_t n) { return piv_bytes(l, n); }
+
+int64_t pivqr_blocks(int64_t n) { return (n + PQ_COLS - 1) / PQ_COLS; }
+
+size_t pivqr_job_ws_bytes(int64_t l, int64_t n) {
+  WsCarve c(nullptr);
+  const int64_t nb = pivqr_blocks(n);
+  c.take<double>(nb);
+  c.take<double>(nb);
+  c.take<int64_t>(nb);
+  c.take<double2>(size_t(nb) * size_t(l));
+  c.take<double>(1);
+  return c.off;
+}
+
+void pivqr_job_carve(char *base, PivJob &jb) {
+  WsCarve c(base);
+  const int64_t nb = pivqr_blocks(jb.n);
+  jb.cnorm = c.take<double>(nb);
+  jb.cnorm2 = c.take<double>(nb);
+  jb.cidx = c.take<int64_t>(nb);
+  jb.ccol = c.take<double2>(size_t(nb) * size_t(jb.l));
+  jb.nu0 = c.take<double>(1);
+}
+
+hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const PivJob *djobs,
+                              const int4 *dtab, int64_t count, RidProf *prof) {
+  if (count == 0) return hipSuccess;
+  const dim3 grid(static_cast<unsigned>(count));
+  ProfScope ps(prof, st, RID_KERNEL_PIVQR);
+  hipLaunchKernelGGL(pivqr_init_grouped, grid, dim3(256), 0, st, djobs, dtab);
+  for (int t = 0; t <= kmax; ++t) {
+    if (lmax <= 64)
+      hipLaunchKernelGGL(pivqr_step_grouped<1>, grid, dim3(256), 0, st, t, djobs, dtab);
+    else if (lmax <= 128)
+      hipLaunchKernelGGL(pivqr_step_grouped<2>, grid, dim3(256), 0, st, t, djobs, dtab);
+    else if (lmax <= 192)
+      hipLaunchKernelGGL(pivqr_step_grouped<3>, grid, dim3(256), 0, st, t, djobs, dtab);
+    else
+      hipLaunchKernelGGL(pivqr_step_grouped<4>, grid, dim3(256), 0, st, t, djobs, dtab);
+  }
+  ps.stop();
+  return hipGetLastError();
+}
 
 hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y,
                         int64_t ldy, int64_t *perm, double *gaps, double rank_tol, void *ws,

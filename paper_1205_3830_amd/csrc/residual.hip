@@ -21,6 +21,8 @@
 // inside that job, so the same bodies serve one ID (one launch per step,
 // grid = the job's blocks) and a batch of IDs (one launch per step over all
 // jobs, each block looking up its (job, block) pair in a table).
+#include <algorithm>
+#include <cstdlib>
 #include <cstring>
 #include <type_traits>
 
@@ -681,6 +683,11 @@ hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n
 void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, void *ws,
                           GroupedHost *out) {
   WsCarve c(ws);
+  int64_t block_bytes = int64_t(256) << 10;
+  if (const char *e = getenv("RID_RES_BLOCK_KB")) {
+    const long v = strtol(e, nullptr, 10);
+    if (v >= 16 && v <= 65536) block_bytes = int64_t(v) << 10;
+  }
   std::vector<ResJob> jobs(count);
   for (int i = 0; i < count; ++i) {
     ResJob &r = jobs[i];
@@ -697,8 +704,11 @@ void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, voi
     r.sigma = bj[i].sigma;
     r.hist = nullptr;
     r.pair = pair_ok(dtype, bj[i].A, bj[i].lda) ? 1 : 0;
-    // a job's own passes need few workgroups: the batch fills the device
-    r.pl = plan_res(r.m, r.n, r.k, 64);
+    // a job's own passes need few workgroups (the batch fills the device):
+    // about one ax workgroup per block_bytes of A
+    const int64_t abytes = r.m * r.n * (dtype == RID_C64 ? 8 : 16);
+    r.pl = plan_res(r.m, r.n, r.k,
+                    std::min<int64_t>(2048, std::max<int64_t>(1, abytes / block_bytes)));
     carve_res(c, r);
   }
   out->ws_bytes = c.off + 256;

@@ -254,6 +254,22 @@ struct InterpJob {
   const int *mark;
 };
 
+// One pivoted QR of a batch: Y (l x n, ldy) is overwritten by R, J gets the
+// k pivots, mark[j] the step at which column j was picked (-1 otherwise);
+// the rest is per-job workspace (pivqr_job_ws_bytes).
+struct PivJob {
+  int64_t l, n, k, ldy;
+  double2 *Y;
+  int64_t *J;
+  int *mark;
+  int *status;
+  double rank_tol;
+  double *cnorm, *cnorm2;
+  int64_t *cidx;
+  double2 *ccol;
+  double *nu0;
+};
+
 // Host-side description of a grouped launch sequence: per-job descriptors
 // (opaque bytes, copied to the device as an array) and, per step, a table of
 // (job, block x, block y) entries, concatenated.
@@ -327,6 +343,15 @@ bool pivqr_supported(int64_t l);
 hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y,
                         int64_t ldy, int64_t *perm, double *gaps, double rank_tol,
                         void *ws, int *d_status, RidProf *prof);
+
+// Batched pivoted QR: one grouped launch per step over the (job, column
+// block, blocks of job) table; every job's table entries are its
+// pivqr_blocks(n) column blocks.
+int64_t pivqr_blocks(int64_t n);
+size_t pivqr_job_ws_bytes(int64_t l, int64_t n);
+void pivqr_job_carve(char *base, PivJob &jb);
+hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const PivJob *djobs,
+                              const int4 *dtab, int64_t count, RidProf *prof);
 
 size_t interp_ws_bytes(int64_t n);
 bool interp_supported(int64_t k);
