@@ -158,6 +158,144 @@ def bench_batched(args, torch, rid, synth) -> int:
     return 0
 
 
+def serving_trace(args, seed: int = 0):
+    """Arrival times (Poisson, args.rate per second over args.duration s)
+    and per-request shapes: with probability p_big a big complex128 job,
+    otherwise a job of the batched workload's distribution (complex64)."""
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    t, out = 0.0, []
+    small = iter(batch_shapes(1 << 16, seed + 1))
+    while True:
+        t += rng.exponential(1.0 / args.rate)
+        if t >= args.duration:
+            break
+        if rng.uniform() < args.p_big:
+            k = args.big_k
+            out.append((t, True, args.big_m, args.big_n, k, k + 8))
+        else:
+            m, n, k, l = next(small)
+            out.append((t, False, m, n, k, l))
+    return out
+
+
+def run_trace(rid, synth, torch, trace, q, big_lanes, batch_lanes, max_batch, prec):
+    """Submit `trace` at its arrival times; returns per-request records."""
+    import numpy as np
+    chunk = 1024
+
+    def fill(ticket, req):
+        dt = torch.complex128 if req["dtype"] == rid.RID_C128 else torch.complex64
+        noise = 1e-12 if req["big"] else 1e-7
+        return synth.lowrank_device(req["m"], req["n"], req["k"], noise, seed=req["gen_seed"],
+                                    dtype=dt, col_chunk=chunk).t()
+
+    srv = rid.RidServer(fill, big_bytes=1 << 30, big_lanes=big_lanes, batch_lanes=batch_lanes,
+                        max_batch=max_batch)
+    try:
+        def submit(i, big, m, n, k, l):
+            dt = rid.RID_C128 if big else rid.RID_C64
+            fb = 4 * m * chunk * 16 if big else 4 * m * n * 8
+            return srv.submit(m, n, k, l, dtype=dt, prec=prec, seed=i, q=q, rank_tol=1e-12,
+                              fill_bytes=fb, big=big, gen_seed=i)
+
+        # warm-up: small jobs, and one big job per big lane, grow the lanes'
+        # workspaces before the clock starts
+        big0 = next((r for r in trace if r[1]), None)
+        for i in range(8):
+            submit(10 ** 6 + i, False, 1024, 512, 16, 24)
+        if big0 is not None:
+            for i in range(max(1, big_lanes)):
+                submit(10 ** 6 + 99 + i, *big0[1:])
+        srv.drain()
+        t_base = time.perf_counter()
+        tick = []
+        for i, (ta, big, m, n, k, l) in enumerate(trace):
+            d = t_base + ta - time.perf_counter()
+            if d > 0:
+                time.sleep(d)
+            tick.append(submit(i, big, m, n, k, l))
+            if i % 200 == 0:
+                print("submitted %d/%d" % (i, len(trace)), file=sys.stderr, flush=True)
+        srv.drain()
+        recs = []
+        for i, t in enumerate(tick):
+            r = srv.result(t)
+            ta, big, m, n, k, l = trace[i]
+            recs.append(dict(big=big, status=r["status"], times=r["times"],
+                             bytes=m * n * (16 if big else 8)))
+        stats = srv.stats()
+    finally:
+        srv.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    T = np.array([r["times"] for r in recs])
+    lat = T[:, 3] - T[:, 0]
+    wall = T[:, 3].max() - T[:, 0].min()
+    big = np.array([r["big"] for r in recs])
+
+    def pct(x):
+        if len(x) == 0:
+            return None
+        return {"p50_ms": float(np.percentile(x, 50) * 1e3),
+                "p99_ms": float(np.percentile(x, 99) * 1e3), "count": int(len(x))}
+
+    return {
+        "ids_per_s": len(recs) / wall,
+        "gb_per_s": sum(2 * q * r["bytes"] for r in recs) / wall / 1e9,
+        "wall_s": float(wall),
+        "all": pct(lat), "small": pct(lat[~big]), "big": pct(lat[big]),
+        "fill_ms_p50": float(np.percentile(T[:, 2] - T[:, 1], 50) * 1e3),
+        "queue_ms_p99": float(np.percentile(T[:, 1] - T[:, 0], 99) * 1e3),
+        "small_service_ms_p99": (float(np.percentile((T[:, 3] - T[:, 2])[~big], 99) * 1e3)
+                                 if (~big).any() else None),
+        "big_fill_ms": [float(x) * 1e3 for x in (T[:, 2] - T[:, 1])[big]],
+        "big_service_ms": [float(x) * 1e3 for x in (T[:, 3] - T[:, 2])[big]],
+        "failed": int(sum(r["status"] != 0 for r in recs)),
+        "peak_admitted_GB": stats["peak_bytes"] / 1e9,
+        "runs": stats["batches"],
+    }
+
+
+def bench_serving(args, torch, rid, synth) -> int:
+    trace = serving_trace(args)
+    prec = rid.RID_FP64 if args.prec == "fp64" else rid.RID_FP32
+    n_big = sum(1 for r in trace if r[1])
+    print("serving trace: %d requests (%d big)" % (len(trace), n_big), file=sys.stderr, flush=True)
+    served = run_trace(rid, synth, torch, trace, args.q, big_lanes=args.big_lanes,
+                       batch_lanes=args.batch_lanes, max_batch=512, prec=prec)
+    print("served: %s" % json.dumps(served), file=sys.stderr, flush=True)
+    base = None
+    if not args.no_baseline:
+        base = run_trace(rid, synth, torch, trace, args.q, big_lanes=0, batch_lanes=1,
+                         max_batch=1, prec=rid.RID_FP64)
+    out = {
+        "metric": "A GB/s streamed & IDs/sec at <=1e-10 rel err; p50/p99 latency vs plain FP64",
+        "value": served["ids_per_s"],
+        "unit": "IDs/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.prec == "fp64" else "f32 sketch products, f64 QR/solve/residual",
+        "data": "synthetic",
+        "config": {"workload": "served ID requests: Poisson %.0f/s for %.1f s; small jobs m "
+                               "log-uniform [256, 4096], n log-uniform [128, 2048], k uniform "
+                               "[8, 64], l = k + 8, c64, 1e-7 noise; with probability %.3f a "
+                               "c128 %dx%d k=%d l=%d job, 1e-12 noise; q=%d" % (
+                                   args.rate, args.duration, args.p_big, args.big_m, args.big_n,
+                                   args.big_k, args.big_k + 8, args.q),
+                   "requests": len(trace), "big_requests": n_big,
+                   "server": "%d batch lanes (up to 512 jobs per batch) + %d big lanes, "
+                             "admission by device footprint" % (args.batch_lanes,
+                                                                args.big_lanes)},
+        "served": served,
+        "plain_fp64_one_at_a_time": base,
+    }
+    print(json.dumps(out))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -177,9 +315,23 @@ def main() -> int:
                     help="arithmetic of the sketch products (QR, solve, residual stay double)")
     ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["single", "batched"], default="single",
+    ap.add_argument("--form", choices=["single", "batched", "serving"], default="single",
                     help="single: one large ID per step (default); batched: many uneven IDs "
-                         "per call, compared with the single-ID FP64 path run one at a time")
+                         "per call, compared with the single-ID FP64 path run one at a time; "
+                         "serving: a Poisson request stream through the continuous-batching "
+                         "server, compared with the plain FP64 path one request at a time")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: requests per second")
+    ap.add_argument("--duration", type=float, default=4.0,
+                    help="serving: seconds of arrivals")
+    ap.add_argument("--p-big", type=float, default=0.01,
+                    help="serving: probability that a request is a big complex128 job")
+    ap.add_argument("--big-m", type=int, default=262144)
+    ap.add_argument("--big-n", type=int, default=16384)
+    ap.add_argument("--big-k", type=int, default=64)
+    ap.add_argument("--batch-lanes", type=int, default=2, help="serving: batch lanes")
+    ap.add_argument("--big-lanes", type=int, default=2, help="serving: big-job lanes")
+    ap.add_argument("--no-baseline", action="store_true",
+                    help="serving: skip the one-at-a-time replay")
     ap.add_argument("--jobs", type=int, default=512, help="IDs per batch (--form batched)")
     ap.add_argument("--no-single", action="store_true",
                     help="--form batched: skip the one-at-a-time comparison")
@@ -201,6 +353,8 @@ def main() -> int:
 
     if args.form == "batched":
         return bench_batched(args, torch, rid, synth)
+    if args.form == "serving":
+        return bench_serving(args, torch, rid, synth)
 
     m, n, k, l, q = args.m, args.n, args.k, args.l, args.q
     torch.cuda.set_device(0)

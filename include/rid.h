@@ -77,7 +77,10 @@ typedef enum { RID_FP64 = 0, RID_FP32 = 1, RID_BF16X3 = 2 } rid_prec;
 
 /* Create a handle bound to HIP device `device` (host out-pointer `h`).
  * Allocates a small device status word; workspace is allocated on first use
- * or by rid_reserve().  Errors: INVALID_ARG (null h, bad device), HIP.    */
+ * or by rid_reserve().  A call that needs more workspace allocates a larger
+ * buffer (at least 1.5x) without waiting for the device; the superseded
+ * buffers are kept until rid_destroy, as work in flight may still use them.
+ * Errors: INVALID_ARG (null h, bad device), HIP.                          */
 rid_status rid_create(rid_handle *h, int device);
 
 /* Free the handle and its workspace.  The caller must make sure no work
@@ -92,8 +95,8 @@ int rid_last_hip_error(rid_handle h);
 
 /* Pre-size the workspace for every call with m <= max_m, n <= max_n,
  * l <= max_l, k <= max_k, so that later calls allocate nothing (needed
- * before capturing calls into a HIP graph).  Synchronises the device.
- * Errors: INVALID_ARG (negative sizes), NOMEM.                            */
+ * before capturing calls into a HIP graph).  Errors: INVALID_ARG
+ * (negative sizes), NOMEM.                                               */
 rid_status rid_reserve(rid_handle h, int64_t max_m, int64_t max_n, int64_t max_l,
                        int64_t max_k);
 
@@ -267,7 +270,7 @@ typedef struct {
 
 /* Many independent IDs of uneven sizes (Sec. 2 for each), each with its own
  * seed: every step runs as one launch over all jobs (the pivoted QR as one
- * workgroup per job), captured into a HIP graph and replayed on `stream`
+ * launch per pivot step), captured into a HIP graph and replayed on `stream`
  * (set RID_BATCH_GRAPH=0 in the environment to launch directly).  A job
  * whose sketch has rank < k is redrawn with seed + 1, up to max_retries
  * times.  Results per job are those of rid_decompose with the same inputs
@@ -275,12 +278,82 @@ typedef struct {
  * jobs: host array of `count`; job_status (host, count, or null) receives
  * RID_OK / RID_ERR_RANK per job; seed_used (host, count, or null) the seed
  * of each job's last draw.  Limits per job: 1 <= k <= l <= m, k <= n,
- * k <= 256, l <= 224, n <= 4096.  SYNCHRONISES the stream.  Errors:
+ * k <= 256, l <= 224, n < 2^31.  A job's results do not depend on the
+ * other jobs of the batch (bitwise).  SYNCHRONISES the stream.  Errors:
  * INVALID_ARG, UNSUPPORTED, NOMEM, HIP, RANK (some job failed every draw;
  * the others hold their results).                                        */
 rid_status rid_decompose_batched(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
                                  const rid_job *jobs, int count, int q, int max_retries,
                                  double rank_tol, int *job_status, uint64_t *seed_used);
+
+/* ---------------------------------------------------------------- serving */
+
+/* A request loop on one device with continuous batching: requests arrive at
+ * any time (rid_server_submit); each is admitted as soon as its device
+ * footprint fits the memory budget beside the jobs already admitted, and
+ * admitted jobs run while others are still running.  Jobs whose A has fewer
+ * than big_bytes bytes are grouped, per (dtype, prec, q, max_retries,
+ * rank_tol), into batches of up to max_batch that run as one
+ * rid_decompose_batched call (one job alone: rid_decompose); larger jobs run
+ * one per big lane through rid_decompose.  Every lane owns a handle and a
+ * non-blocking stream of default priority, so batches and big jobs overlap
+ * on the device.  A job's results equal those of the same entry point
+ * called alone (the batched path's per-job results do not depend on the
+ * other jobs of its batch).                                               */
+typedef struct rid_server_ctx *rid_server;
+
+typedef struct {
+  int64_t hbm_budget; /* device bytes that admitted jobs may hold at once */
+  int64_t big_bytes;  /* A of at least this many bytes: a big job */
+  int big_lanes;      /* big jobs running at once (0: big jobs are batched too) */
+  int batch_lanes;    /* batches running at once (>= 1) */
+  int max_batch;      /* jobs per batch (>= 1) */
+} rid_server_config;
+
+typedef struct {
+  int64_t m, n, k, l;
+  rid_dtype dtype;
+  rid_prec prec;
+  uint64_t seed;
+  int q, max_retries;
+  double rank_tol;
+  int64_t fill_bytes; /* transient device bytes the admit callback uses */
+} rid_request;
+
+/* Called on a lane thread once the request `ticket` is admitted: place A on
+ * the device (enqueued on `stream`, or complete before returning) and set
+ * job->A, lda, J, P, ldp and sigma (device memory the caller owns; m, n, k,
+ * l and seed are already set).  Return 0, or non-zero to fail the job with
+ * RID_ERR_INVALID_ARG.  Callbacks of different lanes may run at once.     */
+typedef int (*rid_admit_fn)(void *ctx, uint64_t ticket, hipStream_t stream, rid_job *job);
+
+/* Called on a lane thread when the job's results are final: status (RID_OK,
+ * RID_ERR_RANK, ...), the seed of the last draw, and times[4] = seconds
+ * since rid_server_create at arrival, admission, A in place, and done.    */
+typedef void (*rid_done_fn)(void *ctx, uint64_t ticket, int status, uint64_t seed_used,
+                            const double *times);
+
+/* Start the lanes on `device`.  A job's footprint is bytes(A) + fill_bytes
+ * + its outputs + the workspace of rid_decompose for its shape.  Errors:
+ * INVALID_ARG, HIP, NOMEM.                                               */
+rid_status rid_server_create(rid_server *s, int device, const rid_server_config *cfg,
+                             rid_admit_fn admit, rid_done_fn done, void *ctx);
+
+/* Queue one request; *ticket (host) receives its id (> 0).  Does not block.
+ * Errors: INVALID_ARG (sizes as rid_decompose), UNSUPPORTED, NOMEM (the
+ * footprint alone exceeds the budget).                                   */
+rid_status rid_server_submit(rid_server s, const rid_request *req, uint64_t *ticket);
+
+/* Block until every submitted job is done.                               */
+rid_status rid_server_drain(rid_server s);
+
+/* Peak admitted footprint (bytes), jobs completed, and batches run so far
+ * (host out-pointers; any may be null).                                   */
+rid_status rid_server_stats(rid_server s, int64_t *peak_bytes, int64_t *completed,
+                            int64_t *batches);
+
+/* Drain, stop the lanes and release everything the server holds.         */
+rid_status rid_server_destroy(rid_server s);
 
 /* Synchronise `stream` and return the handle's status word: RID_OK, or
  * RID_ERR_RANK if the last rid_pivqr on this handle met rank(Y) < k.

@@ -38,7 +38,9 @@ RID_BF16X3 = 2
 EXPORTED = ["rid_create", "rid_destroy", "rid_status_string", "rid_last_hip_error",
             "rid_reserve", "rid_gaussian", "rid_sketch", "rid_sketch_explicit", "rid_pivqr",
             "rid_interp", "rid_residual", "rid_decompose", "rid_query_status", "rid_profile",
-            "rid_profile_read", "rid_set_sketch", "rid_srft_operator", "rid_decompose_batched"]
+            "rid_profile_read", "rid_set_sketch", "rid_srft_operator", "rid_decompose_batched",
+            "rid_server_create", "rid_server_submit", "rid_server_drain", "rid_server_stats",
+            "rid_server_destroy"]
 
 RID_SKETCH_GAUSSIAN = 0
 RID_SKETCH_SRFT = 1
@@ -69,6 +71,26 @@ class rid_job(ctypes.Structure):
                 ("ldp", ctypes.c_int64), ("sigma", ctypes.c_void_p)]
 
 
+class rid_server_config(ctypes.Structure):
+    """Mirror of the C struct rid_server_config."""
+    _fields_ = [("hbm_budget", ctypes.c_int64), ("big_bytes", ctypes.c_int64),
+                ("big_lanes", ctypes.c_int), ("batch_lanes", ctypes.c_int),
+                ("max_batch", ctypes.c_int)]
+
+
+class rid_request(ctypes.Structure):
+    """Mirror of the C struct rid_request (one served ID)."""
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("k", ctypes.c_int64),
+                ("l", ctypes.c_int64), ("dtype", ctypes.c_int), ("prec", ctypes.c_int),
+                ("seed", ctypes.c_uint64), ("q", ctypes.c_int), ("max_retries", ctypes.c_int),
+                ("rank_tol", ctypes.c_double), ("fill_bytes", ctypes.c_int64)]
+
+
+ADMIT_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                            ctypes.POINTER(rid_job))
+DONE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint64, ctypes.c_int, ctypes.c_uint64,
+                           ctypes.POINTER(ctypes.c_double))
+
 _sig = {
     "rid_create": ([ctypes.POINTER(_P), _I], _I),
     "rid_destroy": ([_P], _I),
@@ -91,6 +113,13 @@ _sig = {
     "rid_decompose_batched": ([_P, _P, _I, _I, ctypes.POINTER(rid_job), _I, _I, _I, _D,
                                ctypes.POINTER(_I), ctypes.POINTER(_U64)], _I),
     "rid_srft_operator": ([_P, _P, _I64, _I64, _U64, _P, _I64], _I),
+    "rid_server_create": ([ctypes.POINTER(_P), _I, ctypes.POINTER(rid_server_config), ADMIT_FN,
+                           DONE_FN, _P], _I),
+    "rid_server_submit": ([_P, ctypes.POINTER(rid_request), ctypes.POINTER(_U64)], _I),
+    "rid_server_drain": ([_P], _I),
+    "rid_server_stats": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
+                         _I),
+    "rid_server_destroy": ([_P], _I),
     "rid_profile_read": ([_P, _I, ctypes.POINTER(_D), ctypes.POINTER(_I64)], _I),
 }
 
@@ -416,3 +445,143 @@ def rid_decompose_batched(h, As, ks, ls, seeds, q: int = 10, max_retries: int = 
                  lambda v, s: v.view(s).t())
     sig = _Slices(sall, [(i, 1, None) for i in range(count)], lambda v, s: v)
     return Js, Ps, sig, [status[i] for i in range(count)], [int(used[i]) for i in range(count)]
+
+
+def rid_server_create(device: int, cfg: rid_server_config, admit_cb, done_cb):
+    """Start a server (admit_cb / done_cb: ADMIT_FN / DONE_FN objects the
+    caller keeps alive); returns its handle."""
+    h = _P()
+    _check(_L.rid_server_create(ctypes.byref(h), device, ctypes.byref(cfg), admit_cb, done_cb,
+                                None), "rid_server_create")
+    return h
+
+
+def rid_server_submit(s, req: rid_request) -> int:
+    t = _U64(0)
+    _check(_L.rid_server_submit(s, ctypes.byref(req), ctypes.byref(t)), "rid_server_submit")
+    return t.value
+
+
+def rid_server_drain(s) -> None:
+    _check(_L.rid_server_drain(s), "rid_server_drain")
+
+
+def rid_server_stats(s):
+    peak, done, batches = _I64(0), _I64(0), _I64(0)
+    _check(_L.rid_server_stats(s, ctypes.byref(peak), ctypes.byref(done), ctypes.byref(batches)),
+           "rid_server_stats")
+    return {"peak_bytes": peak.value, "completed": done.value, "batches": batches.value}
+
+
+def rid_server_destroy(s) -> None:
+    _check(_L.rid_server_destroy(s), "rid_server_destroy")
+
+
+class RidServer:
+    """Continuous-batching request loop on one device (rid_server_*).
+
+    fill(ticket, req) -> A is called on a server lane once request `ticket`
+    is admitted, with torch's current stream set to the lane's stream; it
+    returns A as a column-major device tensor of the request's dtype
+    (complex128 for RID_C128, complex64 for RID_C64).  The binding allocates
+    J, P and sigma per request; result(ticket) returns them with the status,
+    the seed of the last draw and the four times (arrival, admission, A in
+    place, done; seconds since the server started).  A is released when the
+    job is done.
+    """
+
+    def __init__(self, fill, device: int = 0, hbm_budget: int | None = None,
+                 big_bytes: int = 1 << 30, big_lanes: int = 2, batch_lanes: int = 2,
+                 max_batch: int = 512):
+        import threading
+        torch = _torch()
+        if hbm_budget is None:
+            free, total = torch.cuda.mem_get_info(device)
+            hbm_budget = int(0.8 * free)
+        self._fill = fill
+        self._device = device
+        self._lock = threading.Lock()
+        self._reqs = {}
+        self._live = {}
+        self._results = {}
+        self._errors = {}
+        cfg = rid_server_config(hbm_budget, big_bytes, big_lanes, batch_lanes, max_batch)
+        self._admit_cb = ADMIT_FN(self._admit)
+        self._done_cb = DONE_FN(self._done)
+        self._s = rid_server_create(device, cfg, self._admit_cb, self._done_cb)
+
+    def _admit(self, ctx, ticket, stream, job_p):
+        try:
+            torch = _torch()
+            with self._lock:
+                req = self._reqs[ticket]
+            with torch.cuda.device(self._device), \
+                    torch.cuda.stream(torch.cuda.ExternalStream(stream)):
+                A = self._fill(ticket, req)
+                k, n = req["k"], req["n"]
+                J = torch.empty(k, dtype=torch.int64, device="cuda")
+                P = _new_colmajor(k, n, torch.complex128)
+                sig = torch.zeros(1, dtype=torch.float64, device="cuda")
+            want = torch.complex128 if req["dtype"] == RID_C128 else torch.complex64
+            if tuple(A.shape) != (req["m"], n) or A.dtype != want:
+                raise ValueError("fill returned %s %s for request %s" % (tuple(A.shape), A.dtype, req))
+            job = job_p.contents
+            job.A = A.data_ptr()
+            job.lda = _ld_colmajor(A, "A")
+            job.J = J.data_ptr()
+            job.P = P.data_ptr()
+            job.ldp = _ld_colmajor(P, "P")
+            job.sigma = sig.data_ptr()
+            with self._lock:
+                self._live[ticket] = (A, J, P, sig)
+            return 0
+        except Exception as e:  # reported through result(ticket)
+            with self._lock:
+                self._errors[ticket] = repr(e)
+            return 1
+
+    def _done(self, ctx, ticket, status, seed_used, times):
+        with self._lock:
+            out = self._live.pop(ticket, None)
+            self._results[ticket] = {
+                "status": status, "seed_used": seed_used,
+                "times": [times[i] for i in range(4)],
+                "J": out[1] if out else None, "P": out[2] if out else None,
+                "sigma": out[3] if out else None, "error": self._errors.pop(ticket, None)}
+
+    def submit(self, m: int, n: int, k: int, l: int, dtype: int = RID_C128,
+               prec: int = RID_FP64, seed: int = 0, q: int = 10, max_retries: int = 3,
+               rank_tol: float = 1e-12, fill_bytes: int = 0, **meta) -> int:
+        """Queue one ID; returns its ticket.  meta is handed to fill()."""
+        req = rid_request(m, n, k, l, dtype, prec, seed, q, max_retries, rank_tol, fill_bytes)
+        with self._lock:
+            t = rid_server_submit(self._s, req)
+            d = dict(m=m, n=n, k=k, l=l, dtype=dtype, prec=prec, seed=seed, q=q)
+            d.update(meta)
+            self._reqs[t] = d
+        return t
+
+    def drain(self) -> None:
+        rid_server_drain(self._s)
+
+    def result(self, ticket: int):
+        with self._lock:
+            return self._results.get(ticket)
+
+    def request(self, ticket: int):
+        with self._lock:
+            return self._reqs.get(ticket)
+
+    def stats(self):
+        return rid_server_stats(self._s)
+
+    def close(self) -> None:
+        if getattr(self, "_s", None):
+            rid_server_destroy(self._s)
+            self._s = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

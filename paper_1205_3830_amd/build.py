@@ -19,12 +19,12 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librid.so")
 
 SOURCES = ["gaussian.hip", "sketch_f64.hip", "sketch_f32.hip", "pivqr.hip", "interp.hip", "residual.hip",
-           "batched.hip", "api.hip"]
+           "batched.hip", "api.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-         "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
+         "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function", "-pthread"]
 
 
 def _compile(src: str) -> str:
@@ -41,7 +41,7 @@ def build(jobs: int = 8, verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s%s" % (r.stdout, r.stderr))

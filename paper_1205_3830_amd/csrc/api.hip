@@ -31,26 +31,12 @@ rid_status fail_hip(rid_handle h, hipError_t e) {
 }
 
 rid_status ensure_ws(rid_handle h, size_t bytes) {
-  if (bytes <= h->ws_bytes) return RID_OK;
-  if (h->ws) {
-    hipError_t e = hipDeviceSynchronize();
-    if (e != hipSuccess) return fail_hip(h, e);
-    e = hipFree(h->ws);
-    h->ws = nullptr;
-    h->ws_bytes = 0;
-    if (e != hipSuccess) return fail_hip(h, e);
-  }
-  void *p = nullptr;
-  const size_t want = (bytes + 4095) & ~size_t(4095);
-  hipError_t e = hipMalloc(&p, want);
-  if (e != hipSuccess) {
+  const hipError_t e = grow_ws(h, bytes);
+  if (e == hipErrorOutOfMemory) {
     h->last_hip_error = static_cast<int>(e);
-    (void)hipGetLastError();
     return RID_ERR_NOMEM;
   }
-  h->ws = p;
-  h->ws_bytes = want;
-  return RID_OK;
+  return e == hipSuccess ? RID_OK : fail_hip(h, e);
 }
 
 bool aligned(const void *p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
@@ -109,6 +95,35 @@ size_t bytes_decomp(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, 
 
 }  // namespace
 
+thread_local bool rid_tl_short_blocks = false;
+
+hipError_t grow_ws(rid_handle h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return hipSuccess;
+  const size_t exact = (bytes + 4095) & ~size_t(4095);
+  size_t want = h->ws_bytes + h->ws_bytes / 2;
+  want = (want < exact) ? exact : ((want + 4095) & ~size_t(4095));
+  void *p = nullptr;
+  hipError_t e = hipMalloc(&p, want);
+  if (e != hipSuccess && want > exact) {
+    (void)hipGetLastError();
+    e = hipMalloc(&p, exact);
+    want = exact;
+  }
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return e;
+  }
+  if (h->ws) h->retired.push_back(h->ws);
+  h->ws = p;
+  h->ws_bytes = want;
+  return hipSuccess;
+}
+
+size_t decomp_ws_bytes(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, int64_t l,
+                       int q) {
+  return bytes_decomp(dt, pr, m, n, k, l, q);
+}
+
 extern "C" {
 
 const char *rid_status_string(int status) {
@@ -159,6 +174,7 @@ rid_status rid_destroy(rid_handle h) {
   for (hipEvent_t e : h->prof.pool) (void)hipEventDestroy(e);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->ws) (void)hipFree(h->ws);
+  for (void *p : h->retired) (void)hipFree(p);
   if (h->d_status) (void)hipFree(h->d_status);
   delete h;
   return RID_OK;

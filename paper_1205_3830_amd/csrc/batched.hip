@@ -179,20 +179,8 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   // the residual descriptors need the final scratch base: set it up now
   hipError_t err = hipSuccess;
   {
-    // ensure the workspace (may reallocate; callers synchronise around it)
-    if (total > h->ws_bytes) {
-      hipError_t e = hipDeviceSynchronize();
-      if (e != hipSuccess) return e;
-      if (h->ws) (void)hipFree(h->ws);
-      h->ws = nullptr;
-      h->ws_bytes = 0;
-      e = hipMalloc(&h->ws, total);
-      if (e != hipSuccess) {
-        h->ws = nullptr;
-        return e;
-      }
-      h->ws_bytes = total;
-    }
+    const hipError_t e = grow_ws(h, total);
+    if (e != hipSuccess) return e;
   }
   char *base = static_cast<char *>(h->ws);
   char *pbase = base + tabbytes;
@@ -266,7 +254,7 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
     return launch_residual_batch(st, dtype, d_res, d_tres, res, q, nullptr);
   };
 
-  if (use_graph()) {
+  if (h->batch_graph && use_graph()) {
     if (!h->cap_stream) {
       err = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
       if (err != hipSuccess) return err;
@@ -290,7 +278,8 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
     if (err == hipSuccess) err = hipStreamSynchronize(stream);
     if (err != hipSuccess) return err;
   }
-  err = hipMemcpy(status, dstatus, sizeof(int) * count, hipMemcpyDeviceToHost);
+  err = hipMemcpyAsync(status, dstatus, sizeof(int) * count, hipMemcpyDeviceToHost, stream);
+  if (err == hipSuccess) err = hipStreamSynchronize(stream);
   return err;
 }
 

@@ -60,6 +60,8 @@ ResPlan plan_res(int64_t m, int64_t n, int64_t k, int64_t target_blocks) {
   if (S < 1) S = 1;
   p.cpz = (n + S - 1) / S;
   if (p.cpz < 1) p.cpz = 1;
+  if (rid_tl_short_blocks && p.cpz > RID_AX_COLS_MAX) p.cpz = RID_AX_COLS_MAX;
+  if ((n + p.cpz - 1) / p.cpz > 65535) p.cpz = (n + 65534) / 65535;  // grid y
   p.S_z = (n + p.cpz - 1) / p.cpz;
   if (p.S_z < 1) p.S_z = 1;
   p.rpu = AHZ_RS;

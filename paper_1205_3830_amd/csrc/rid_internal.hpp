@@ -62,9 +62,11 @@ struct rid_ctx {
   int *d_status = nullptr;  // device status word (RID_OK / RID_ERR_RANK)
   void *ws = nullptr;       // grow-only workspace
   size_t ws_bytes = 0;
+  std::vector<void *> retired;  // superseded workspaces, freed by rid_destroy
   RidProf prof;
   int sketch_kind = RID_SKETCH_GAUSSIAN;  // operator drawn by rid_sketch / rid_decompose
   hipStream_t cap_stream = nullptr;       // stream used to capture batch graphs
+  bool batch_graph = true;                // capture batches into a graph (else launch directly)
 };
 
 // Bump allocator over the handle workspace (256-byte aligned pieces).
@@ -221,6 +223,20 @@ RID_DEV void wave_sum_dd(double &s, double &c) {
   c = __shfl(c, 0, 64);
 }
 
+// ------------------------------------------------------------------ plans
+// Short-workgroup plans for a shared device.  When the calling thread has
+// rid_tl_short_blocks set (the serving lanes set it for themselves), the
+// A-streaming kernels bound the work of one workgroup (rows of a sketch K
+// split; columns of an ax split) so that a workgroup lives about a
+// millisecond and the dispatcher can hand freed CU slots to kernels of other
+// streams (a served batch beside a big ID) instead of making them wait out a
+// whole pass.  It costs a few percent more partial sums, so a plain call
+// keeps the long-workgroup plans.  Workspace sizing and launches read the
+// flag on the same thread within one call, so they always agree.
+constexpr int64_t RID_SPLIT_ROWS_MAX = 4096;
+constexpr int64_t RID_AX_COLS_MAX = 512;
+extern thread_local bool rid_tl_short_blocks;
+
 // ------------------------------------------------------------------ batches
 // One job of a batch as the library sees it (device pointers for data).
 struct RidBatchJob {
@@ -318,6 +334,14 @@ hipError_t launch_sketch_batch(hipStream_t st, rid_dtype dtype, rid_prec prec,
 int sketch_pick_mt(int64_t l);  // tiles per block for one batch job (0: unsupported)
 
 bool batch_job_supported(const RidBatchJob &j);
+// Make the handle's workspace at least `bytes` long.  A larger buffer
+// (>= 1.5x the old one) replaces the old, which is kept until rid_destroy:
+// work still in flight may use it, and growing never waits for the device
+// (hipFree would wait for every stream, other callers' included).
+hipError_t grow_ws(rid_handle h, size_t bytes);
+// Device workspace rid_decompose needs for one ID of this shape.
+size_t decomp_ws_bytes(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, int64_t l,
+                       int q);
 hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
                      const RidBatchJob *bj, int count, int q, double rank_tol, int *status);
 

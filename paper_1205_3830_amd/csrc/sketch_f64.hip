@@ -215,6 +215,8 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t l) {
   int64_t pchunk = (m + S - 1) / S;
   pchunk = (pchunk + 15) / 16 * 16;
   if (pchunk < 16) pchunk = 16;
+  if (rid_tl_short_blocks && pchunk > RID_SPLIT_ROWS_MAX) pchunk = RID_SPLIT_ROWS_MAX;
+  if ((m + pchunk - 1) / pchunk > 65535) pchunk = ((m + 65534) / 65535 + 15) / 16 * 16;  // grid y
   S = (m + pchunk - 1) / pchunk;
   if (S < 1) S = 1;
   p.S = static_cast<int>(S);

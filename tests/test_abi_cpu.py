@@ -49,6 +49,26 @@ def test_null_handle_and_bad_args_rejected_without_gpu():
         rid.RID_ERR_INVALID_ARG
     assert lib.rid_reserve(None, 1, 1, 1, 1) == rid.RID_ERR_INVALID_ARG
     assert lib.rid_last_hip_error(None) == 0
+    # the serving entry points check their arguments before touching a device
+    cfg = rid.rid_server_config(1 << 30, 1 << 20, 1, 1, 8)
+    admit = rid.ADMIT_FN(lambda *a: 1)
+    done = rid.DONE_FN(lambda *a: None)
+    h = rid._P()
+    assert lib.rid_server_create(None, 0, ctypes.byref(cfg), admit, done, None) == \
+        rid.RID_ERR_INVALID_ARG
+    assert lib.rid_server_create(ctypes.byref(h), 0, None, admit, done, None) == \
+        rid.RID_ERR_INVALID_ARG
+    for bad in (rid.rid_server_config(0, 1, 1, 1, 8), rid.rid_server_config(1, 1, 1, 0, 8),
+                rid.rid_server_config(1, 1, -1, 1, 8), rid.rid_server_config(1, 1, 1, 1, 0)):
+        assert lib.rid_server_create(ctypes.byref(h), 0, ctypes.byref(bad), admit, done,
+                                     None) == rid.RID_ERR_INVALID_ARG
+    req = rid.rid_request(100, 50, 5, 10, rid.RID_C128, rid.RID_FP64, 0, 4, 1, 1e-12, 0)
+    t = rid._U64(0)
+    assert lib.rid_server_submit(None, ctypes.byref(req), ctypes.byref(t)) == \
+        rid.RID_ERR_INVALID_ARG
+    assert lib.rid_server_drain(None) == rid.RID_ERR_INVALID_ARG
+    assert lib.rid_server_stats(None, None, None, None) == rid.RID_ERR_INVALID_ARG
+    assert lib.rid_server_destroy(None) == rid.RID_ERR_INVALID_ARG
 
 
 def test_binding_functions_carry_the_c_names():
