@@ -103,14 +103,24 @@ def bench_batched(args, torch, rid, synth) -> int:
     def batch(p):
         return rid.rid_decompose_batched(h, As, ks, ls, seeds, q=q, prec=p, rank_tol=tol)
 
-    batch(prec)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        Js, Ps, sig, status, _ = batch(prec)
-    torch.cuda.synchronize()
-    t_batch = (time.perf_counter() - t0) / args.steps
-    assert all(s == 0 for s in status)
+    def timed():
+        batch(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            Js, Ps, sig, status, _ = batch(prec)
+        torch.cuda.synchronize()
+        assert all(s == 0 for s in status)
+        return (time.perf_counter() - t0) / args.steps
+
+    plan_default = rid.rid_get_batch_plan(h)
+    t_default = timed()
+    plan = plan_default
+    t_batch = t_default
+    if not args.no_tune:
+        print("autotuning the batch plan", file=sys.stderr, flush=True)
+        plan = rid.rid_tune_batched(h, As, ks, ls, seeds, q=q, prec=prec)
+        t_batch = timed()
     if args.no_single:
         As = []
     # the plain FP64 single-ID path, one ID at a time, same matrices
@@ -151,6 +161,12 @@ def bench_batched(args, torch, rid, synth) -> int:
                                "A = X W + 1e-7 N %s, q=%d" % (len(shapes), args.dtype, q),
                    "jobs": len(shapes), "bytes_A": bytes_a, "storage": args.dtype,
                    "sketch_products": args.prec},
+        "plan": {"sketch_split_rows": plan[0], "ax_block_bytes": plan[1],
+                 "ahz_cols_per_wave": plan[2], "tuned": not args.no_tune,
+                 "default_plan": {"sketch_split_rows": plan_default[0],
+                                  "ax_block_bytes": plan_default[1],
+                                  "ahz_cols_per_wave": plan_default[2],
+                                  "ms_per_step": t_default * 1e3}},
         "single_fp64_one_at_a_time": single,
         "speedup_vs_single": t_single / t_batch if lat else None,
     }
@@ -333,6 +349,8 @@ def main() -> int:
     ap.add_argument("--no-baseline", action="store_true",
                     help="serving: skip the one-at-a-time replay")
     ap.add_argument("--jobs", type=int, default=512, help="IDs per batch (--form batched)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="--form batched: time the default batch plan only (no autotuning)")
     ap.add_argument("--no-single", action="store_true",
                     help="--form batched: skip the one-at-a-time comparison")
     ap.add_argument("--copy-calibration", action="store_true",

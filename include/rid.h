@@ -286,6 +286,32 @@ rid_status rid_decompose_batched(rid_handle h, hipStream_t stream, rid_dtype dty
                                  const rid_job *jobs, int count, int q, int max_retries,
                                  double rank_tol, int *job_status, uint64_t *seed_used);
 
+/* The plan of this handle's batches: rows of A per sketch K split
+ * (multiple of 16, 16 .. 2^20; default 1024), bytes of A per workgroup of
+ * the residual's A x pass (4 KiB .. 1 GiB; default 256 KiB) and columns per
+ * wave of its A^H z pass (4 or 8; default 8).  Per-job results depend on the
+ * plan only through summation order (within the FP64 tolerances of
+ * rid_decompose).  Errors: INVALID_ARG.                                  */
+rid_status rid_set_batch_plan(rid_handle h, int64_t sketch_rows, int64_t res_block_bytes,
+                              int ahz_cols);
+
+/* The current batch plan (host out-pointers; any may be null).            */
+rid_status rid_get_batch_plan(rid_handle h, int64_t *sketch_rows, int64_t *res_block_bytes,
+                              int *ahz_cols);
+
+/* Autotuner of the batch plan on the caller's own batch: times the batch
+ * (launched directly, HIP events around each kernel family) under six
+ * candidate plans -- sketch split rows {128, 256, 512, 1024, 2048, 4096},
+ * A-pass workgroup bytes {32, 64, 128, 256, 512, 1024} KiB and A^H z
+ * columns per wave {8, 4, 8, 4, 8, 4}, the i-th of each together -- keeps
+ * the fastest value of each parameter (each changes only its own kernel
+ * family) in the handle and returns it (host out-pointers, may be null).
+ * The jobs' outputs are overwritten (contents unspecified afterwards).
+ * SYNCHRONISES the stream.  Errors: INVALID_ARG, UNSUPPORTED, NOMEM, HIP. */
+rid_status rid_tune_batched(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                            const rid_job *jobs, int count, int q, int64_t *sketch_rows,
+                            int64_t *res_block_bytes, int *ahz_cols);
+
 /* ---------------------------------------------------------------- serving */
 
 /* A request loop on one device with continuous batching: requests arrive at

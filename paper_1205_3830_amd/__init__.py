@@ -40,7 +40,7 @@ EXPORTED = ["rid_create", "rid_destroy", "rid_status_string", "rid_last_hip_erro
             "rid_interp", "rid_residual", "rid_decompose", "rid_query_status", "rid_profile",
             "rid_profile_read", "rid_set_sketch", "rid_srft_operator", "rid_decompose_batched",
             "rid_server_create", "rid_server_submit", "rid_server_drain", "rid_server_stats",
-            "rid_server_destroy"]
+            "rid_server_destroy", "rid_set_batch_plan", "rid_get_batch_plan", "rid_tune_batched"]
 
 RID_SKETCH_GAUSSIAN = 0
 RID_SKETCH_SRFT = 1
@@ -117,6 +117,11 @@ _sig = {
                            DONE_FN, _P], _I),
     "rid_server_submit": ([_P, ctypes.POINTER(rid_request), ctypes.POINTER(_U64)], _I),
     "rid_server_drain": ([_P], _I),
+    "rid_set_batch_plan": ([_P, _I64, _I64, _I], _I),
+    "rid_get_batch_plan": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I)],
+                           _I),
+    "rid_tune_batched": ([_P, _P, _I, _I, ctypes.POINTER(rid_job), _I, _I,
+                          ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I)], _I),
     "rid_server_stats": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I64)],
                          _I),
     "rid_server_destroy": ([_P], _I),
@@ -403,6 +408,25 @@ def rid_decompose_batched(h, As, ks, ls, seeds, q: int = 10, max_retries: int = 
     dtype); ks, ls, seeds: per-job ints.  Returns (Js, Ps, sigmas, status,
     seeds_used): per-job device views (J: k int64, P: k x n complex128
     column-major, sigma: 1 float64) into three output slabs, and host lists."""
+    tab, dt, Jall, Pall, sall, koff, poff, ks, ns = _batch_table(As, ks, ls, seeds)
+    count = len(As)
+    status = (_I * max(count, 1))()
+    used = (_U64 * max(count, 1))()
+    st = _L.rid_decompose_batched(h, _stream(stream), dt, prec,
+                                  ctypes.cast(tab.ctypes.data, ctypes.POINTER(rid_job)),
+                                  count, q, max_retries, rank_tol, status, used)
+    if st != RID_OK and not (st == RID_ERR_RANK and not raise_on_rank):
+        raise RidError(st, "rid_decompose_batched")
+    Js = _Slices(Jall, [(int(koff[i]), ks[i], None) for i in range(count)], lambda v, s: v)
+    Ps = _Slices(Pall, [(int(poff[i]), ks[i] * ns[i], (ns[i], ks[i])) for i in range(count)],
+                 lambda v, s: v.view(s).t())
+    sig = _Slices(sall, [(i, 1, None) for i in range(count)], lambda v, s: v)
+    return Js, Ps, sig, [status[i] for i in range(count)], [int(used[i]) for i in range(count)]
+
+
+def _batch_table(As, ks, ls, seeds):
+    """The rid_job array of a batch (numpy, one row of 11 int64 per job) and
+    the output slabs it points into."""
     import numpy as np
     torch = _torch()
     count = len(As)
@@ -433,18 +457,33 @@ def rid_decompose_batched(h, As, ks, ls, seeds, q: int = 10, max_retries: int = 
         tab[:count, 8] = Pall.data_ptr() + 16 * poff[:-1]
         tab[:count, 9] = ks
         tab[:count, 10] = sall.data_ptr() + 8 * np.arange(count, dtype=np.int64)
-    status = (_I * max(count, 1))()
-    used = (_U64 * max(count, 1))()
-    st = _L.rid_decompose_batched(h, _stream(stream), dt, prec,
-                                  ctypes.cast(tab.ctypes.data, ctypes.POINTER(rid_job)),
-                                  count, q, max_retries, rank_tol, status, used)
-    if st != RID_OK and not (st == RID_ERR_RANK and not raise_on_rank):
-        raise RidError(st, "rid_decompose_batched")
-    Js = _Slices(Jall, [(int(koff[i]), ks[i], None) for i in range(count)], lambda v, s: v)
-    Ps = _Slices(Pall, [(int(poff[i]), ks[i] * ns[i], (ns[i], ks[i])) for i in range(count)],
-                 lambda v, s: v.view(s).t())
-    sig = _Slices(sall, [(i, 1, None) for i in range(count)], lambda v, s: v)
-    return Js, Ps, sig, [status[i] for i in range(count)], [int(used[i]) for i in range(count)]
+    return tab, dt, Jall, Pall, sall, koff, poff, ks, ns
+
+
+def rid_set_batch_plan(h, sketch_rows: int, res_block_bytes: int, ahz_cols: int = 8) -> None:
+    _check(_L.rid_set_batch_plan(h, sketch_rows, res_block_bytes, ahz_cols),
+           "rid_set_batch_plan")
+
+
+def rid_get_batch_plan(h):
+    """(sketch split rows, A-pass workgroup bytes, A^H z columns per wave) of
+    the handle's batches."""
+    a, b, c = _I64(0), _I64(0), _I(0)
+    _check(_L.rid_get_batch_plan(h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "rid_get_batch_plan")
+    return a.value, b.value, c.value
+
+
+def rid_tune_batched(h, As, ks, ls, seeds, q: int = 10, prec: int = RID_FP64, stream=None):
+    """Autotune the handle's batch plan on this batch; returns the chosen
+    (sketch split rows, A-pass workgroup bytes, A^H z columns per wave)."""
+    tab, dt, Jall, Pall, sall, _, _, _, _ = _batch_table(As, ks, ls, seeds)
+    a, b, c = _I64(0), _I64(0), _I(0)
+    _check(_L.rid_tune_batched(h, _stream(stream), dt, prec,
+                               ctypes.cast(tab.ctypes.data, ctypes.POINTER(rid_job)), len(As), q,
+                               ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)),
+           "rid_tune_batched")
+    return a.value, b.value, c.value
 
 
 def rid_server_create(device: int, cfg: rid_server_config, admit_cb, done_cb):

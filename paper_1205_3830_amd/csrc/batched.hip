@@ -81,7 +81,8 @@ bool batch_job_supported(const RidBatchJob &j) {
 // Runs one batch (each job once, with the seeds in bj); writes per-job
 // status (host).  ws: device workspace of batch_ws_bytes(...) bytes.
 hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
-                     const RidBatchJob *bj, int count, int q, double rank_tol, int *status) {
+                     const RidBatchJob *bj, int count, int q, double rank_tol, int *status,
+                     RidProf *prof) {
   // ---- plans and workspace layout
   std::vector<SketchJob> sk(count);
   std::vector<OpJob> op(count);
@@ -106,7 +107,7 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   const size_t persist = (pc.off + 255) & ~size_t(255);
   WsCarve sc(nullptr);
   std::vector<size_t> offG(count), offPart(count);
-  const int64_t pchunk = 1024;
+  const int64_t pchunk = h->batch_sketch_rows;
   for (int i = 0; i < count; ++i) {
     const int64_t S = (bj[i].m + pchunk - 1) / pchunk;
     offG[i] = sc.take_off<double2>(size_t(bj[i].l) * size_t(bj[i].m));
@@ -119,7 +120,8 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   for (int i = 0; i < count; ++i)
     offQr[i] = qc.take_off<char>(pivqr_job_ws_bytes(bj[i].l, bj[i].n));
   GroupedHost res;
-  residual_batch_setup(bj, count, dtype, nullptr, &res);
+  residual_batch_setup(bj, count, dtype, h->batch_res_block_bytes, h->batch_ahz_cpw, nullptr,
+                       &res);
   const size_t scratch = std::max(std::max(sc.off, qc.off), res.ws_bytes) + 256;
 
   // ---- descriptor + table upload region goes first
@@ -185,7 +187,8 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   char *base = static_cast<char *>(h->ws);
   char *pbase = base + tabbytes;
   char *sbase = pbase + persist;
-  residual_batch_setup(bj, count, dtype, sbase, &res);
+  residual_batch_setup(bj, count, dtype, h->batch_res_block_bytes, h->batch_ahz_cpw, sbase,
+                       &res);
   int *dstatus = reinterpret_cast<int *>(pbase + offStatus);
   for (int i = 0; i < count; ++i) {
     double2 *Y = reinterpret_cast<double2 *>(pbase + offY[i]);
@@ -244,17 +247,17 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
                             static_cast<int64_t>(sizeof(int4));
     e = launch_sketch_batch(st, dtype, prec, d_sk, d_tsk, mts.data(), skoff.data(), skcnt.data(),
                             static_cast<int>(nbuck), red_off, static_cast<int64_t>(t_red.size()),
-                            nullptr);
+                            prof);
     if (e != hipSuccess) return e;
     e = launch_pivqr_batch(st, lmax, kmax, d_qr, d_tqr, static_cast<int64_t>(t_qr.size()),
-                           nullptr);
+                           prof);
     if (e != hipSuccess) return e;
-    e = launch_interp_batch(st, kmax, d_in, d_tin, static_cast<int64_t>(t_in.size()), nullptr);
+    e = launch_interp_batch(st, kmax, d_in, d_tin, static_cast<int64_t>(t_in.size()), prof);
     if (e != hipSuccess) return e;
-    return launch_residual_batch(st, dtype, d_res, d_tres, res, q, nullptr);
+    return launch_residual_batch(st, dtype, d_res, d_tres, res, q, prof);
   };
 
-  if (h->batch_graph && use_graph()) {
+  if (!prof && h->batch_graph && use_graph()) {
     if (!h->cap_stream) {
       err = hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking);
       if (err != hipSuccess) return err;
@@ -345,6 +348,113 @@ extern "C" rid_status rid_decompose_batched(rid_handle h, hipStream_t stream, ri
     for (int i = 0; i < count; ++i) job_status[i] = st[i];
   if (seed_used)
     for (int i = 0; i < count; ++i) seed_used[i] = used[i];
+  if (prev != h->device) (void)hipSetDevice(prev);
+  return out;
+}
+
+extern "C" rid_status rid_set_batch_plan(rid_handle h, int64_t sketch_rows,
+                                         int64_t res_block_bytes, int ahz_cols) {
+  if (!h || sketch_rows < 16 || sketch_rows > (int64_t(1) << 20) || sketch_rows % 16 != 0 ||
+      res_block_bytes < (int64_t(4) << 10) || res_block_bytes > (int64_t(1) << 30) ||
+      (ahz_cols != 4 && ahz_cols != 8))
+    return RID_ERR_INVALID_ARG;
+  h->batch_sketch_rows = sketch_rows;
+  h->batch_res_block_bytes = res_block_bytes;
+  h->batch_ahz_cpw = ahz_cols;
+  return RID_OK;
+}
+
+extern "C" rid_status rid_get_batch_plan(rid_handle h, int64_t *sketch_rows,
+                                         int64_t *res_block_bytes, int *ahz_cols) {
+  if (!h) return RID_ERR_INVALID_ARG;
+  if (sketch_rows) *sketch_rows = h->batch_sketch_rows;
+  if (res_block_bytes) *res_block_bytes = h->batch_res_block_bytes;
+  if (ahz_cols) *ahz_cols = h->batch_ahz_cpw;
+  return RID_OK;
+}
+
+// Autotuner of the batched plan: candidate i pairs sketch split rows
+// kRows[i] with ax block bytes kBlock[i] and ahz columns per wave kCols[i];
+// one directly launched, event-timed run per candidate gives the sketch,
+// ax and ahz family times of its three values (each parameter changes only
+// its own family), and the fastest value of each is kept in the handle.
+extern "C" rid_status rid_tune_batched(rid_handle h, hipStream_t stream, rid_dtype dtype,
+                                       rid_prec prec, const rid_job *jobs, int count, int q,
+                                       int64_t *sketch_rows, int64_t *res_block_bytes,
+                                       int *ahz_cols) {
+  static const int64_t kRows[] = {128, 256, 512, 1024, 2048, 4096};
+  static const int64_t kBlock[] = {int64_t(32) << 10,  int64_t(64) << 10,  int64_t(128) << 10,
+                                   int64_t(256) << 10, int64_t(512) << 10, int64_t(1024) << 10};
+  static const int kCols[] = {8, 4, 8, 4, 8, 4};
+  constexpr int kCand = 6;
+  if (!h || count < 1 || !jobs || q < 1) return RID_ERR_INVALID_ARG;
+  if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
+  if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
+  if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
+  const size_t align = dtype == RID_C128 ? 16 : 8;
+  std::vector<RidBatchJob> bj(count);
+  for (int i = 0; i < count; ++i) {
+    const rid_job &j = jobs[i];
+    if (j.k < 1 || j.k > j.l || j.k > j.n || j.l > j.m || j.lda < j.m || j.ldp < j.k || !j.A ||
+        !j.J || !j.P || !j.sigma || reinterpret_cast<uintptr_t>(j.A) % align != 0 ||
+        reinterpret_cast<uintptr_t>(j.P) % 16 != 0 || j.n > 0x7FFFFFFFll)
+      return RID_ERR_INVALID_ARG;
+    bj[i] = RidBatchJob{j.m, j.n, j.k, j.l, j.lda, j.ldp, j.A, j.seed, j.J,
+                        static_cast<double2 *>(j.P), j.sigma};
+    if (!batch_job_supported(bj[i])) return RID_ERR_UNSUPPORTED;
+  }
+  int prev = -1;
+  if (hipGetDevice(&prev) != hipSuccess) return RID_ERR_HIP;
+  if (prev != h->device && hipSetDevice(h->device) != hipSuccess) return RID_ERR_HIP;
+  const int64_t keep_rows = h->batch_sketch_rows, keep_block = h->batch_res_block_bytes;
+  const int keep_cols = h->batch_ahz_cpw;
+  std::vector<int> st(count);
+  double best_sk = 1e300, best_ax = 1e300, best_ahz = 1e300;
+  int64_t pick_rows = keep_rows, pick_block = keep_block;
+  int pick_cols = keep_cols;
+  rid_status out = RID_OK;
+  RidProf prof;
+  for (int c = -1; c < kCand && out == RID_OK; ++c) {  // c = -1: warm-up, untimed
+    h->batch_sketch_rows = c < 0 ? keep_rows : kRows[c];
+    h->batch_res_block_bytes = c < 0 ? keep_block : kBlock[c];
+    h->batch_ahz_cpw = c < 0 ? keep_cols : kCols[c];
+    prof.on = true;
+    prof.used = 0;
+    prof.recs.clear();
+    hipError_t e = run_batch(h, stream, dtype, prec, bj.data(), count, q, 0.0, st.data(), &prof);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    double fam[RID_KERNEL_COUNT] = {0.0};
+    for (const auto &r : prof.recs) {
+      float ms = 0.0f;
+      if (e == hipSuccess) e = hipEventElapsedTime(&ms, prof.pool[r.second], prof.pool[r.second + 1]);
+      fam[r.first] += ms;
+    }
+    if (e != hipSuccess) {
+      h->last_hip_error = static_cast<int>(e);
+      out = RID_ERR_HIP;
+      break;
+    }
+    if (c < 0) continue;
+    if (fam[RID_KERNEL_SKETCH] < best_sk) {
+      best_sk = fam[RID_KERNEL_SKETCH];
+      pick_rows = kRows[c];
+    }
+    if (fam[RID_KERNEL_AX] < best_ax) {
+      best_ax = fam[RID_KERNEL_AX];
+      pick_block = kBlock[c];
+    }
+    if (fam[RID_KERNEL_AHZ] < best_ahz) {
+      best_ahz = fam[RID_KERNEL_AHZ];
+      pick_cols = kCols[c];
+    }
+  }
+  for (hipEvent_t ev : prof.pool) (void)hipEventDestroy(ev);
+  h->batch_sketch_rows = out == RID_OK ? pick_rows : keep_rows;
+  h->batch_res_block_bytes = out == RID_OK ? pick_block : keep_block;
+  h->batch_ahz_cpw = out == RID_OK ? pick_cols : keep_cols;
+  if (sketch_rows) *sketch_rows = h->batch_sketch_rows;
+  if (res_block_bytes) *res_block_bytes = h->batch_res_block_bytes;
+  if (ahz_cols) *ahz_cols = h->batch_ahz_cpw;
   if (prev != h->device) (void)hipSetDevice(prev);
   return out;
 }

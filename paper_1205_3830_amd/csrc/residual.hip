@@ -12,8 +12,9 @@
 //   ax  : z = A x~ ; a workgroup streams a 512-row slab of a range of
 //         columns (each column slab is one contiguous 8 KB read).
 //   ahz : u = A^H z ; a workgroup stages a 2048-row chunk of z in LDS and
-//         each wave streams 8 columns of that chunk (32 KB contiguous reads
-//         each), reducing in registers then across lanes.
+//         each wave streams AHZ_CPW columns of that chunk (32 KB contiguous
+//         reads each for complex128), reducing in registers then across
+//         lanes by one reduce-scatter.
 // Partial sums over column splits (resp. row splits) are reduced in a fixed
 // order by separate kernels, so results are bitwise reproducible.
 //
@@ -32,8 +33,9 @@ namespace {
 
 constexpr int AX_ROWS = 512;   // rows per ax workgroup (2 per thread)
 constexpr int AHZ_RS = 2048;   // rows per ahz split (z chunk in LDS, 32 KB)
-constexpr int AHZ_CPW = 8;     // columns per ahz wave
-constexpr int AHZ_COLS = 4 * AHZ_CPW;  // columns per ahz workgroup
+// columns per ahz wave: a plan choice, 8 (fewer z reads per byte of A) or 4
+// (fewer registers: 5 waves per SIMD instead of 3 for complex64)
+
 constexpr int PX_JC = 256;     // columns per workgroup of the P x partials
 constexpr int RES_KMAX = 1024; // LDS holds u_J for k <= RES_KMAX
 
@@ -44,6 +46,7 @@ struct ResPlan {
   int64_t S_u;     // ahz row splits
   int64_t rpu;     // rows per ahz split
   int64_t nb_ahz;  // ahz column blocks
+  int ahz_cpw;     // ahz columns per wave (4 or 8)
   int64_t nb_px;   // P x partial blocks
   int64_t nb_k;    // 256-blocks over k
   int64_t nb_n;    // 256-blocks over n
@@ -51,8 +54,9 @@ struct ResPlan {
 };
 
 // target_blocks: workgroups wanted for the ax pass of this job alone
-ResPlan plan_res(int64_t m, int64_t n, int64_t k, int64_t target_blocks) {
+ResPlan plan_res(int64_t m, int64_t n, int64_t k, int64_t target_blocks, int ahz_cpw) {
   ResPlan p;
+  p.ahz_cpw = ahz_cpw == 4 ? 4 : 8;
   p.nb_ax = (m + AX_ROWS - 1) / AX_ROWS;
   int64_t S = (target_blocks + p.nb_ax - 1) / p.nb_ax;
   const int64_t maxS = (n + 31) / 32;
@@ -67,7 +71,7 @@ ResPlan plan_res(int64_t m, int64_t n, int64_t k, int64_t target_blocks) {
   p.rpu = AHZ_RS;
   p.S_u = (m + p.rpu - 1) / p.rpu;
   if (p.S_u < 1) p.S_u = 1;
-  p.nb_ahz = (n + AHZ_COLS - 1) / AHZ_COLS;
+  p.nb_ahz = (n + 4 * p.ahz_cpw - 1) / (4 * p.ahz_cpw);
   p.nb_px = (n + PX_JC - 1) / PX_JC;
   p.nb_k = (k + 255) / 256;
   p.nb_n = (n + 255) / 256;
@@ -357,8 +361,9 @@ RID_DEV void sigma_final_body(const ResJob &r, int t) {
 // u partials: columns [32 bx, +32) x rows of split by; z chunk staged in LDS.
 // A lane takes one row per step for complex128 and two adjacent rows (one
 // 16-byte load when aligned) for complex64.
-template <class TA>
+template <class TA, int AHZ_CPW>
 RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
+  constexpr int AHZ_COLS = 4 * AHZ_CPW;  // columns per workgroup
   constexpr bool C64 = sizeof(TA) == 8;
   __shared__ double2 zs[AHZ_RS];
   if (stopped(r.scal)) return;
@@ -423,17 +428,22 @@ RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
       }
     }
   }
+  // value 2u + p of the reduction: column jb + u, real (p = 0) or imaginary part
+  double vs[2 * AHZ_CPW], vc[2 * AHZ_CPW];
 #pragma unroll
   for (int u = 0; u < AHZ_CPW; ++u) {
-    wave_sum_dd(sr[u], cr[u]);
-    wave_sum_dd(si[u], ci[u]);
-    if (lane == 0 && cok[u]) {
-      double *o = r.upart + (by * n + jb + u) * 4;
-      o[0] = sr[u];
-      o[1] = cr[u];
-      o[2] = si[u];
-      o[3] = ci[u];
-    }
+    vs[2 * u] = sr[u];
+    vc[2 * u] = cr[u];
+    vs[2 * u + 1] = si[u];
+    vc[2 * u + 1] = ci[u];
+  }
+  wave_reduce_dd<2 * AHZ_CPW>(vs, vc);
+  constexpr int GROUP = 64 / (2 * AHZ_CPW);
+  const int v = lane / GROUP;
+  if (lane % GROUP == 0 && jb + (v >> 1) < n) {
+    double *o = r.upart + (by * n + jb + (v >> 1)) * 4 + 2 * (v & 1);
+    o[0] = vs[0];
+    o[1] = vc[0];
   }
 }
 
@@ -501,7 +511,7 @@ RID_DEV void w_body(const ResJob &r, int64_t bx) {
 // (job, bx, by) of the step's table.
 enum Step : int {
   ST_X0, ST_WNORM, ST_XSCALE, ST_XTINIT, ST_PXP, ST_PXF, ST_AX, ST_ZF, ST_SIGMA, ST_AHZ, ST_UF,
-  ST_W, ST_COUNT
+  ST_W, ST_AHZ4, ST_COUNT
 };
 
 template <class TA, int STEP>
@@ -515,7 +525,8 @@ RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
   if constexpr (STEP == ST_AX) ax_body<TA>(r, bx, by);
   if constexpr (STEP == ST_ZF) z_final_body(r, bx);
   if constexpr (STEP == ST_SIGMA) sigma_final_body(r, t);
-  if constexpr (STEP == ST_AHZ) ahz_body<TA>(r, bx, by);
+  if constexpr (STEP == ST_AHZ) ahz_body<TA, 8>(r, bx, by);
+  if constexpr (STEP == ST_AHZ4) ahz_body<TA, 4>(r, bx, by);
   if constexpr (STEP == ST_UF) u_final_body(r, bx);
   if constexpr (STEP == ST_W) w_body(r, bx);
 }
@@ -543,7 +554,8 @@ void step_grid(int step, const ResJob &r, int64_t &gx, int64_t &gy) {
     case ST_PXF: gx = r.k > 0 ? p.nb_k : 0; break;
     case ST_AX: gx = p.nb_ax; gy = p.S_z; break;
     case ST_ZF: gx = p.nb_m; break;
-    case ST_AHZ: gx = p.nb_ahz; gy = p.S_u; break;
+    case ST_AHZ: gx = p.ahz_cpw == 8 ? p.nb_ahz : 0; gy = p.S_u; break;
+    case ST_AHZ4: gx = p.ahz_cpw == 4 ? p.nb_ahz : 0; gy = p.S_u; break;
     default: gx = 0;
   }
 }
@@ -583,7 +595,8 @@ void power_iteration(L &&launch, int q) {
     launch(ST_ZF, t, -1);
     launch(ST_SIGMA, t, -1);
     if (t + 1 < q) {
-      launch(ST_AHZ, t, RID_KERNEL_AHZ);
+      launch(ST_AHZ, t, RID_KERNEL_AHZ);   // one of the two has blocks for a job
+      launch(ST_AHZ4, t, RID_KERNEL_AHZ);
       launch(ST_UF, t, -1);
       launch(ST_W, t, -1);
       launch(ST_WNORM, t, -1);
@@ -608,6 +621,7 @@ void by_step(int step, F &&f) {
     case ST_AHZ: f(std::integral_constant<int, ST_AHZ>()); break;
     case ST_UF: f(std::integral_constant<int, ST_UF>()); break;
     case ST_W: f(std::integral_constant<int, ST_W>()); break;
+    case ST_AHZ4: f(std::integral_constant<int, ST_AHZ4>()); break;
     default: break;
   }
 }
@@ -647,7 +661,7 @@ size_t residual_ws_bytes(int64_t m, int64_t n, int64_t k, int q) {
   r.m = m;
   r.n = n;
   r.k = k;
-  r.pl = plan_res(m, n, k, 2048);
+  r.pl = plan_res(m, n, k, 2048, 8);
   WsCarve c(nullptr);
   carve_res(c, r);
   return c.off + 256;
@@ -671,7 +685,7 @@ hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n
   r.sigma = sigma;
   r.hist = hist;
   r.pair = pair_ok(dtype, A, lda) ? 1 : 0;
-  r.pl = plan_res(m, n, k, 2048);
+  r.pl = plan_res(m, n, k, 2048, dtype == RID_C64 ? 4 : 8);
   WsCarve c(ws);
   carve_res(c, r);
   if (dtype == RID_C64)
@@ -682,14 +696,10 @@ hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n
 }
 
 // ------------------------------------------------------------------ a batch of IDs
-void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, void *ws,
-                          GroupedHost *out) {
+void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, int64_t block_bytes,
+                          int ahz_cpw, void *ws, GroupedHost *out) {
   WsCarve c(ws);
-  int64_t block_bytes = int64_t(256) << 10;
-  if (const char *e = getenv("RID_RES_BLOCK_KB")) {
-    const long v = strtol(e, nullptr, 10);
-    if (v >= 16 && v <= 65536) block_bytes = int64_t(v) << 10;
-  }
+  if (block_bytes < 1) block_bytes = 1;
   std::vector<ResJob> jobs(count);
   for (int i = 0; i < count; ++i) {
     ResJob &r = jobs[i];
@@ -710,7 +720,7 @@ void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, voi
     // about one ax workgroup per block_bytes of A
     const int64_t abytes = r.m * r.n * (dtype == RID_C64 ? 8 : 16);
     r.pl = plan_res(r.m, r.n, r.k,
-                    std::min<int64_t>(2048, std::max<int64_t>(1, abytes / block_bytes)));
+                    std::min<int64_t>(2048, std::max<int64_t>(1, abytes / block_bytes)), ahz_cpw);
     carve_res(c, r);
   }
   out->ws_bytes = c.off + 256;

@@ -67,6 +67,10 @@ struct rid_ctx {
   int sketch_kind = RID_SKETCH_GAUSSIAN;  // operator drawn by rid_sketch / rid_decompose
   hipStream_t cap_stream = nullptr;       // stream used to capture batch graphs
   bool batch_graph = true;                // capture batches into a graph (else launch directly)
+  // plan of the batched path (rid_set_batch_plan / rid_tune_batched)
+  int64_t batch_sketch_rows = 1024;       // rows of A per sketch K split
+  int64_t batch_res_block_bytes = 256 << 10;  // bytes of A per ax workgroup
+  int batch_ahz_cpw = 8;                  // columns per wave of the ahz pass (4 or 8)
 };
 
 // Bump allocator over the handle workspace (256-byte aligned pieces).
@@ -223,6 +227,42 @@ RID_DEV void wave_sum_dd(double &s, double &c) {
   c = __shfl(c, 0, 64);
 }
 
+// Sums NV double-double values (s[v], c[v]) (NV a power of two, 2..64) over
+// the 64 lanes of a wave by reduce-scatter: at the level of lane bit b (from
+// bit 5 down) each lane keeps the half of its values that the bit selects
+// and adds the partner's copy of that half, so after log2(NV) levels a lane
+// holds one value, v = lane >> (6 - log2(NV)); the remaining lane bits
+// finish it with a plain butterfly.  For NV = 16 that is 34 double shuffles
+// and 17 compensated adds, against 192 and 96 for 16 separate wave sums.  On
+// return (s[0], c[0]) of every lane is the total of its value v (dd_add is
+// symmetric, so all lanes of a group hold the same bits).
+template <int NV>
+RID_DEV void wave_reduce_dd(double (&s)[NV], double (&c)[NV]) {
+  static_assert(NV >= 2 && NV <= 64 && (NV & (NV - 1)) == 0, "NV: power of two in 2..64");
+  const int lane = threadIdx.x & 63;
+  constexpr int GROUP = 64 / NV;  // lanes that end up holding the same value
+#pragma unroll
+  for (int half = NV / 2; half >= 1; half >>= 1) {
+    const int off = half * GROUP;
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int j = 0; j < half; ++j) {
+      double ks = up ? s[half + j] : s[j], kc = up ? c[half + j] : c[j];
+      const double gs = __shfl_xor(up ? s[j] : s[half + j], off, 64);
+      const double gc = __shfl_xor(up ? c[j] : c[half + j], off, 64);
+      dd_add(ks, kc, gs, gc);
+      s[j] = ks;
+      c[j] = kc;
+    }
+  }
+#pragma unroll
+  for (int off = GROUP / 2; off >= 1; off >>= 1) {
+    const double gs = __shfl_xor(s[0], off, 64);
+    const double gc = __shfl_xor(c[0], off, 64);
+    dd_add(s[0], c[0], gs, gc);
+  }
+}
+
 // ------------------------------------------------------------------ plans
 // Short-workgroup plans for a shared device.  When the calling thread has
 // rid_tl_short_blocks set (the serving lanes set it for themselves), the
@@ -342,8 +382,10 @@ hipError_t grow_ws(rid_handle h, size_t bytes);
 // Device workspace rid_decompose needs for one ID of this shape.
 size_t decomp_ws_bytes(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, int64_t l,
                        int q);
+// prof non-null: launch directly (no graph) and time the kernel families into prof.
 hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
-                     const RidBatchJob *bj, int count, int q, double rank_tol, int *status);
+                     const RidBatchJob *bj, int count, int q, double rank_tol, int *status,
+                     RidProf *prof = nullptr);
 
 // Grouped interpolation (k <= 256): tab entries (job, column quad).
 hipError_t launch_interp_batch(hipStream_t st, int kmax, const InterpJob *djobs,
@@ -385,7 +427,8 @@ hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R,
 
 // Grouped power iteration over a batch: setup on the host (ws == nullptr
 // only sizes the workspace), then one launch per step for all jobs.
-void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, void *ws,
+void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, int64_t block_bytes,
+                          int ahz_cpw, void *ws,
                           GroupedHost *out);
 hipError_t launch_residual_batch(hipStream_t st, rid_dtype dtype, const void *djobs,
                                  const int4 *dtab, const GroupedHost &gh, int q, RidProf *prof);

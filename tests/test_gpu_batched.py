@@ -132,3 +132,39 @@ def test_batch_invalid_job_rejected(h):
     with pytest.raises(rid.RidError) as ei:
         rid.rid_decompose_batched(h, [A], [3], [300], [0])     # l > m, and > 224
     assert ei.value.status == rid.RID_ERR_INVALID_ARG
+
+
+def test_autotuner_picks_candidates_and_keeps_parity(h):
+    jobs = make_jobs(10, 6)
+    As = [dev(A) for A, _, _, _ in jobs]
+    ks, ls, seeds = [j[1] for j in jobs], [j[2] for j in jobs], [j[3] for j in jobs]
+    keep = rid.rid_get_batch_plan(h)
+    try:
+        rows, blk, cols = rid.rid_tune_batched(h, As, ks, ls, seeds, q=4)
+        assert rows in (128, 256, 512, 1024, 2048, 4096)
+        assert blk in tuple(x << 10 for x in (32, 64, 128, 256, 512, 1024))
+        assert cols in (4, 8)
+        assert rid.rid_get_batch_plan(h) == (rows, blk, cols)
+        # every plan gives results within the FP64 tolerances of the single path
+        for plan in ((rows, blk, cols), (128, 32 << 10, 4), (4096, 1 << 20, 8)):
+            rid.rid_set_batch_plan(h, *plan)
+            Js, Ps, sig, status, _ = rid.rid_decompose_batched(h, As, ks, ls, seeds, q=4)
+            assert status == [0] * len(jobs)
+            for i, (A, k, l, s) in enumerate(jobs):
+                J1, P1, s1, _ = rid.rid_decompose(h, As[i], k, l, seed=s, q=4)
+                gaps = host(rid.rid_pivqr(h, rid.rid_sketch(h, As[i], l, seed=s), k)[1])
+                jb, j1 = host(Js[i]), host(J1)
+                for t in range(k):
+                    if gaps[t] <= 1e-10:
+                        break
+                    assert jb[t] == j1[t], (plan, i, t)
+                p1 = host(P1)
+                assert np.abs(host(Ps[i]) - p1).max() <= 1e-10 * max(1.0, np.abs(p1).max())
+        with pytest.raises(rid.RidError):
+            rid.rid_set_batch_plan(h, 100, 1 << 20)        # not a multiple of 16
+        with pytest.raises(rid.RidError):
+            rid.rid_set_batch_plan(h, 1024, 100)           # below 4 KiB
+        with pytest.raises(rid.RidError):
+            rid.rid_set_batch_plan(h, 1024, 1 << 18, 6)    # 4 or 8 columns per wave
+    finally:
+        rid.rid_set_batch_plan(h, *keep)
