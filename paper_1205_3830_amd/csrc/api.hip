@@ -86,7 +86,7 @@ size_t bytes_decomp(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, 
   c2.take<double>(k);
   const size_t base = (c2.off + 255) & ~size_t(255);
   size_t need = c.off;
-  const size_t others[] = {pivqr_ws_bytes(l, n), interp_ws_bytes(n),
+  const size_t others[] = {pivqr_ws_bytes(l, n), interp_ws_bytes(n, k),
                            residual_ws_bytes(m, n, k, q)};
   for (size_t o : others)
     if (base + o > need) need = base + o;
@@ -311,7 +311,7 @@ rid_status rid_interp(rid_handle h, hipStream_t stream, int64_t n, int64_t k, co
   if (!interp_supported(k)) return RID_ERR_UNSUPPORTED;
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
-  rid_status s = ensure_ws(h, interp_ws_bytes(n));
+  rid_status s = ensure_ws(h, interp_ws_bytes(n, k));
   if (s != RID_OK) return s;
   hipError_t e = launch_interp(stream, n, k, static_cast<const double2 *>(R), ldr, J,
                                static_cast<double2 *>(P), ldp, h->ws, &h->prof);

@@ -4,7 +4,7 @@
 //
 // One kernel per step.  Workgroup b (4 waves) owns columns [64b, 64b + 64),
 // each wave 16 of them, one column at a time with the rows spread over the
-// 64 lanes (RR rows per lane, l <= 64 RR).  Kernel t
+// 64 lanes (RR rows per lane, l <= 64 RR <= 2048).  Kernel t
 //   1. merges the per-workgroup candidates of step t-1 into the pivot j* of
 //      step t-1 (max trailing norm, lowest index on exact ties) -- every
 //      workgroup does the same merge in the same order, so all agree;
@@ -18,6 +18,7 @@
 // Columns stay in place: after the last kernel, Y(0:k, :) is R in original
 // column order.  No floating-point atomics; every reduction has a fixed order.
 #include <climits>
+#include <type_traits>
 
 #include "rid_internal.hpp"
 
@@ -25,11 +26,17 @@ namespace {
 
 constexpr int PQ_COLS = 64;
 
+// The per-workgroup candidates are double-buffered by step parity: launch t
+// reads the candidates of step t-1 (buffer (t-1) & 1) to rebuild the
+// reflector and writes those of step t (buffer t & 1).  With one buffer, a
+// workgroup that finishes early would overwrite the pivot column's copy
+// while workgroups that start later (when there are more than fit on the
+// device at once) still have to read it.
 struct PivWs {
-  double *cnorm;   // [nb] best trailing norm of the block (-1: none)
-  double *cnorm2;  // [nb] its second-best norm (-1: none)
-  int64_t *cidx;   // [nb] column index of the best
-  double2 *ccol;   // [nb][l] copy of the best column (rows t..l-1 valid)
+  double *cnorm;   // [2][nb] best trailing norm of the block (-1: none)
+  double *cnorm2;  // [2][nb] its second-best norm (-1: none)
+  int64_t *cidx;   // [2][nb] column index of the best
+  double2 *ccol;   // [2][nb][l] copy of the best column (rows t..l-1 valid)
   int *pstep;      // [n] step at which the column was picked, -1 if not
   double *nu0;     // best norm of step 0
 };
@@ -38,10 +45,10 @@ PivWs carve_piv(void *ws, int64_t l, int64_t n) {
   WsCarve c(ws);
   const int64_t nb = (n + PQ_COLS - 1) / PQ_COLS;
   PivWs w;
-  w.cnorm = c.take<double>(nb);
-  w.cnorm2 = c.take<double>(nb);
-  w.cidx = c.take<int64_t>(nb);
-  w.ccol = c.take<double2>(size_t(nb) * size_t(l));
+  w.cnorm = c.take<double>(2 * nb);
+  w.cnorm2 = c.take<double>(2 * nb);
+  w.cidx = c.take<int64_t>(2 * nb);
+  w.ccol = c.take<double2>(2 * size_t(nb) * size_t(l));
   w.pstep = c.take<int>(n);
   w.nu0 = c.take<double>(1);
   return w;
@@ -50,10 +57,10 @@ PivWs carve_piv(void *ws, int64_t l, int64_t n) {
 size_t piv_bytes(int64_t l, int64_t n) {
   WsCarve c(nullptr);
   const int64_t nb = (n + PQ_COLS - 1) / PQ_COLS;
-  c.take<double>(nb);
-  c.take<double>(nb);
-  c.take<int64_t>(nb);
-  c.take<double2>(size_t(nb) * size_t(l));
+  c.take<double>(2 * nb);
+  c.take<double>(2 * nb);
+  c.take<int64_t>(2 * nb);
+  c.take<double2>(2 * size_t(nb) * size_t(l));
   c.take<int>(n);
   c.take<double>(1);
   return c.off + 256;
@@ -90,7 +97,6 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
                              int64_t *perm, double *gaps, double rank_tol, const PivWs &w,
                              int *status, int64_t bx, int64_t nb) {
   __shared__ double2 v_s[64 * RR];
-  __shared__ double2 best_col[4][64 * RR];
   __shared__ Cand red[256];
   __shared__ double2 tau_s;
   __shared__ double beta_s;
@@ -108,11 +114,13 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
   int64_t jstar = -1;
   const int64_t r0 = (t > 0) ? t - 1 : 0;  // first row touched by this kernel
 
+  const int64_t rd = ((t - 1) & 1) * nb;  // candidates of step t-1
+  const int64_t wr = (t & 1) * nb;        // candidates of step t
   if (t > 0) {
     // ---- 1. pivot of step t-1
     Cand cd = cand_empty();
     for (int64_t b = tid; b < nb; b += 256) {
-      Cand x{w.cnorm[b], w.cidx[b], w.cnorm2[b], 0};
+      Cand x{w.cnorm[rd + b], w.cidx[rd + b], w.cnorm2[rd + b], 0};
       if (x.v1 < 0.0) x = cand_empty();
       cd = cand_merge(cd, x);
     }
@@ -138,7 +146,7 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
 
     // ---- 2. reflector of step t-1 from the candidate copy (wave 0)
     if (wave == 0) {
-      const double2 *x = w.ccol + bstar * l;
+      const double2 *x = w.ccol + (rd + bstar) * l;
       double2 xv[RR];
       double ss = 0.0;
 #pragma unroll
@@ -241,13 +249,7 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
         if (row >= t && row < l) ss += y[h].x * y[h].x + y[h].y * y[h].y;
       }
       const double nrm = sqrt(wave_sum(ss));
-      const Cand x{nrm, j, -1.0, wave};
-      const bool better = (nrm > wc.v1) || (nrm == wc.v1 && j < wc.i1);
-      wc = cand_merge(wc, x);
-      if (better) {
-#pragma unroll
-        for (int h = 0; h < RR; ++h) best_col[wave][lane + 64 * h] = y[h];
-      }
+      wc = cand_merge(wc, Cand{nrm, j, -1.0, wave});
     }
   }
   if (t >= k) return;
@@ -258,16 +260,16 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
   Cand bc = cand_empty();
   for (int wv = 0; wv < 4; ++wv) bc = cand_merge(bc, red[wv]);
   if (tid == 0) {
-    w.cnorm[bx] = bc.v1;
-    w.cnorm2[bx] = bc.v2;
-    w.cidx[bx] = bc.i1;
+    w.cnorm[wr + bx] = bc.v1;
+    w.cnorm2[wr + bx] = bc.v2;
+    w.cidx[wr + bx] = bc.i1;
   }
+  // publish a copy of the block's best column, re-read from Y: its owning
+  // wave stored it (updated) before the barrier above
   if (bc.src >= 0) {
-    double2 *dst = w.ccol + bx * l;
-    for (int idx = tid; idx < 64 * RR; idx += 256) {
-      const int64_t row = r0 + idx;
-      if (row >= t && row < l) dst[row] = best_col[bc.src][idx];
-    }
+    const double2 *src = Y + bc.i1 * ldy;
+    double2 *dst = w.ccol + (wr + bx) * l;
+    for (int64_t row = t + tid; row < l; row += 256) dst[row] = src[row];
   }
 }
 
@@ -335,6 +337,29 @@ __global__ __launch_bounds__(1024) void pivqr_tail_kernel(int64_t n, int64_t k,
   }
 }
 
+// rows per lane for a sketch of l rows: the smallest of 1, 2, 3, 4, 8, 16, 32
+// with 64 RR >= l (0 when l > 2048)
+int pick_rr(int64_t l) {
+  static const int opts[] = {1, 2, 3, 4, 8, 16, 32};
+  for (int o : opts)
+    if (64 * o >= l) return o;
+  return 0;
+}
+
+template <class F>
+void with_rr(int rr, F &&f) {
+  switch (rr) {
+    case 1: f(std::integral_constant<int, 1>()); break;
+    case 2: f(std::integral_constant<int, 2>()); break;
+    case 3: f(std::integral_constant<int, 3>()); break;
+    case 4: f(std::integral_constant<int, 4>()); break;
+    case 8: f(std::integral_constant<int, 8>()); break;
+    case 16: f(std::integral_constant<int, 16>()); break;
+    case 32: f(std::integral_constant<int, 32>()); break;
+    default: break;
+  }
+}
+
 template <int RR>
 void launch_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y, int64_t ldy,
                   int64_t *perm, double *gaps, double rank_tol, const PivWs &w, int *status) {
@@ -346,7 +371,7 @@ void launch_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y, i
 
 }  // namespace
 
-bool pivqr_supported(int64_t l) { return l >= 1 && l <= 256; }
+bool pivqr_supported(int64_t l) { return l >= 1 && pick_rr(l) > 0; }
 
 size_t pivqr_ws_bytes(int64_t l, int64_t n) { return piv_bytes(l, n); }
 
@@ -355,10 +380,10 @@ int64_t pivqr_blocks(int64_t n) { return (n + PQ_COLS - 1) / PQ_COLS; }
 size_t pivqr_job_ws_bytes(int64_t l, int64_t n) {
   WsCarve c(nullptr);
   const int64_t nb = pivqr_blocks(n);
-  c.take<double>(nb);
-  c.take<double>(nb);
-  c.take<int64_t>(nb);
-  c.take<double2>(size_t(nb) * size_t(l));
+  c.take<double>(2 * nb);
+  c.take<double>(2 * nb);
+  c.take<int64_t>(2 * nb);
+  c.take<double2>(2 * size_t(nb) * size_t(l));
   c.take<double>(1);
   return c.off;
 }
@@ -366,10 +391,10 @@ size_t pivqr_job_ws_bytes(int64_t l, int64_t n) {
 void pivqr_job_carve(char *base, PivJob &jb) {
   WsCarve c(base);
   const int64_t nb = pivqr_blocks(jb.n);
-  jb.cnorm = c.take<double>(nb);
-  jb.cnorm2 = c.take<double>(nb);
-  jb.cidx = c.take<int64_t>(nb);
-  jb.ccol = c.take<double2>(size_t(nb) * size_t(jb.l));
+  jb.cnorm = c.take<double>(2 * nb);
+  jb.cnorm2 = c.take<double>(2 * nb);
+  jb.cidx = c.take<int64_t>(2 * nb);
+  jb.ccol = c.take<double2>(2 * size_t(nb) * size_t(jb.l));
   jb.nu0 = c.take<double>(1);
 }
 
@@ -380,14 +405,10 @@ hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const 
   ProfScope ps(prof, st, RID_KERNEL_PIVQR);
   hipLaunchKernelGGL(pivqr_init_grouped, grid, dim3(256), 0, st, djobs, dtab);
   for (int t = 0; t <= kmax; ++t) {
-    if (lmax <= 64)
-      hipLaunchKernelGGL(pivqr_step_grouped<1>, grid, dim3(256), 0, st, t, djobs, dtab);
-    else if (lmax <= 128)
-      hipLaunchKernelGGL(pivqr_step_grouped<2>, grid, dim3(256), 0, st, t, djobs, dtab);
-    else if (lmax <= 192)
-      hipLaunchKernelGGL(pivqr_step_grouped<3>, grid, dim3(256), 0, st, t, djobs, dtab);
-    else
-      hipLaunchKernelGGL(pivqr_step_grouped<4>, grid, dim3(256), 0, st, t, djobs, dtab);
+    with_rr(pick_rr(lmax), [&](auto R) {
+      hipLaunchKernelGGL(pivqr_step_grouped<decltype(R)::value>, grid, dim3(256), 0, st, t,
+                         djobs, dtab);
+    });
   }
   ps.stop();
   return hipGetLastError();
@@ -400,14 +421,9 @@ hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2
   ProfScope ps(prof, st, RID_KERNEL_PIVQR);
   hipLaunchKernelGGL(pivqr_init_kernel, dim3(static_cast<unsigned>((n + 255) / 256)),
                      dim3(256), 0, st, n, w.pstep, d_status);
-  if (l <= 64)
-    launch_steps<1>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
-  else if (l <= 128)
-    launch_steps<2>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
-  else if (l <= 192)
-    launch_steps<3>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
-  else
-    launch_steps<4>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
+  with_rr(pick_rr(l), [&](auto R) {
+    launch_steps<decltype(R)::value>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
+  });
   hipLaunchKernelGGL(pivqr_tail_kernel, dim3(1), dim3(1024), 0, st, n, k, w.pstep, perm,
                      d_status);
   ps.stop();

@@ -419,7 +419,7 @@ void pivqr_job_carve(char *base, PivJob &jb);
 hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const PivJob *djobs,
                               const int4 *dtab, int64_t count, RidProf *prof);
 
-size_t interp_ws_bytes(int64_t n);
+size_t interp_ws_bytes(int64_t n, int64_t k);
 bool interp_supported(int64_t k);
 hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R, int64_t ldr,
                          const int64_t *J, double2 *P, int64_t ldp, void *ws,

@@ -118,7 +118,9 @@ def _compare_J(Jg, Jo, gaps):
 
 
 PIVQR_CASES = [(30, 500, 20), (108, 2000, 100), (12, 12, 12), (40, 9, 9), (8, 300, 1),
-               (200, 700, 150), (65, 100, 64)]
+               (200, 700, 150), (65, 100, 64),
+               # large l (16 and 32 rows per lane) and k > 256 (R1^-1 then one GEMM)
+               (600, 700, 300), (2000, 400, 100), (1024, 1100, 1000)]
 
 
 @pytest.mark.parametrize("l,n,k", PIVQR_CASES)
@@ -148,15 +150,33 @@ def test_pivqr_and_interp_match_oracle(h, l, n, k):
     assert np.abs(P - Po).max() <= 1e-10 * max(1.0, np.abs(Po).max())
 
 
-@pytest.mark.parametrize("l,n,k", [(30, 500, 20), (108, 1000, 100), (250, 300, 250)])
-def test_interp_same_R_matches_oracle(h, l, n, k):
+@pytest.mark.parametrize("l,n,k", [(64, 1 << 18, 48), (800, 1 << 17, 40)])
+def test_pivqr_with_more_workgroups_than_fit_at_once(h, l, n, k):
+    # 4096 (2048) column workgroups per step launch: many start after others
+    # finished, so a step must not overwrite what the same launch still reads
+    Y = synth.lowrank(l, n, k, 1e-9, seed=n + l)
+    st, Jo, Ro, gaps_o = oracle.select(Y, k)
+    assert st == oracle.OK
+    Po = oracle.interp(Ro, Jo)
+    Yd = dev(Y)
+    perm, gaps = rid.rid_pivqr(h, Yd, k)
+    assert rid.rid_query_status(h) == rid.RID_OK
+    perm = host(perm)
+    assert _compare_J(perm[:k], Jo, gaps_o) == k
+    P = host(rid.rid_interp(h, Yd[:k], torch.from_numpy(perm[:k]).cuda()))
+    assert np.abs(P - Po).max() <= 1e-10 * max(1.0, np.abs(Po).max())
+
+
+@pytest.mark.parametrize("l,n,k,tol", [(30, 500, 20, 1e-12), (108, 1000, 100, 1e-12),
+                                       (250, 300, 250, 1e-12), (400, 900, 300, 1e-11)])
+def test_interp_same_R_matches_oracle(h, l, n, k, tol):
     A = _lowrank(max(l, 300), n, k, 1e-8, seed=n)
     Y = oracle.sketch(A, oracle.sketch_operator(l, A.shape[0], seed=4))
     st, Jo, Ro, _ = oracle.select(Y, k)
     Po = oracle.interp(Ro, Jo)
     P = host(rid.rid_interp(h, dev(Ro), torch.from_numpy(Jo).cuda()))
     assert np.array_equal(P[:, Jo], np.eye(k))
-    assert np.abs(P - Po).max() <= 1e-12 * max(1.0, np.abs(Po).max())
+    assert np.abs(P - Po).max() <= tol * max(1.0, np.abs(Po).max())
 
 
 def test_pivqr_rank_failure_sets_status(h):
@@ -210,6 +230,7 @@ DECOMP_CASES = [
     (513, 257, 1, 1, 1e-10, 5),       # k = 1, l = k
     (300, 40, 40, 40, 1e-10, 4),      # k = n: no T at all
     (2048, 700, 100, 108, 1e-12, 6),  # l, k of the large workload
+    (2500, 900, 300, 600, 1e-10, 3),  # l = 2k with k > 256 (the paper's l)
 ]
 
 
