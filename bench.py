@@ -29,6 +29,13 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0        # MI355X HBM3E
 FP64_PEAK_TFS = 78.6         # MI355X FP64 matrix (dense)
 FP32_PEAK_TFS = 157.3        # MI355X FP32 matrix (dense)
+BF16_PEAK_TFS = 2500.0       # MI355X BF16 matrix (dense)
+
+# sketch product arithmetic by command-line name
+PRECS = {"fp64": lambda rid: rid.RID_FP64, "fp32": lambda rid: rid.RID_FP32,
+         "bf16x3": lambda rid: rid.RID_BF16X3}
+DTYPE_TEXT = {"fp64": "f64", "fp32": "f32 sketch products, f64 QR/solve/residual",
+              "bf16x3": "bf16x3-split sketch products (f32 accumulate), f64 QR/solve/residual"}
 
 
 def _traffic(kernel_name: str, src_file: str, measured_config: bool = True):
@@ -88,7 +95,7 @@ def bench_batched(args, torch, rid, synth) -> int:
     shapes = batch_shapes(args.jobs)
     dt = torch.complex64 if args.dtype == "c64" else torch.complex128
     esize = 8 if args.dtype == "c64" else 16
-    prec = rid.RID_FP64 if args.prec == "fp64" else rid.RID_FP32
+    prec = PRECS[args.prec](rid)
     tol = 1e-12 if prec == rid.RID_FP64 else 1e-5
     print("generating %d matrices" % len(shapes), file=sys.stderr, flush=True)
     As = [synth.lowrank_device(m, n, k, 1e-7, seed=i, dtype=dt).t()
@@ -154,7 +161,7 @@ def bench_batched(args, torch, rid, synth) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32 sketch products, f64 QR/solve/residual",
+        "dtype": DTYPE_TEXT[args.prec],
         "data": "synthetic",
         "config": {"workload": "batched randomized IDs: %d jobs, m log-uniform [256, 4096], "
                                "n log-uniform [128, 2048], k uniform [8, 64], l = k + 8, "
@@ -275,7 +282,7 @@ def run_trace(rid, synth, torch, trace, q, big_lanes, batch_lanes, max_batch, pr
 
 def bench_serving(args, torch, rid, synth) -> int:
     trace = serving_trace(args)
-    prec = rid.RID_FP64 if args.prec == "fp64" else rid.RID_FP32
+    prec = PRECS[args.prec](rid)
     n_big = sum(1 for r in trace if r[1])
     print("serving trace: %d requests (%d big)" % (len(trace), n_big), file=sys.stderr, flush=True)
     served = run_trace(rid, synth, torch, trace, args.q, big_lanes=args.big_lanes,
@@ -293,7 +300,7 @@ def bench_serving(args, torch, rid, synth) -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32 sketch products, f64 QR/solve/residual",
+        "dtype": DTYPE_TEXT[args.prec],
         "data": "synthetic",
         "config": {"workload": "served ID requests: Poisson %.0f/s for %.1f s; small jobs m "
                                "log-uniform [256, 4096], n log-uniform [128, 2048], k uniform "
@@ -399,7 +406,7 @@ def main() -> int:
                     help="set the noise so that sigma_{k+1} ~ rho ||A||_2 (overrides --noise)")
     ap.add_argument("--dtype", choices=["c128", "c64"], default="c128",
                     help="storage of A")
-    ap.add_argument("--prec", choices=["fp64", "fp32"], default="fp64",
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16x3"], default="fp64",
                     help="arithmetic of the sketch products (QR, solve, residual stay double)")
     ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -456,7 +463,7 @@ def main() -> int:
     torch.cuda.set_device(0)
     tdt = torch.complex128 if args.dtype == "c128" else torch.complex64
     esize = 16 if args.dtype == "c128" else 8
-    prec = rid.RID_FP64 if args.prec == "fp64" else rid.RID_FP32
+    prec = PRECS[args.prec](rid)
     noise = args.noise
     if args.rho is not None:
         # ||X W||_2 ~ (sqrt(m) + sqrt(k)) (sqrt(n) + sqrt(k)) for Gaussian factors
@@ -516,12 +523,14 @@ def main() -> int:
                                "avg_launch_ms": kern[name]["avg_ms"]}
     if "sketch" in kern:
         avg = kern["sketch"]["avg_ms"] * 1e-3
-        ach = 8.0 * l * m * n / avg / 1e12
-        peak = FP64_PEAK_TFS if args.prec == "fp64" else FP32_PEAK_TFS
+        # the bf16 split form does six bf16 products per real product
+        flops = 8.0 * l * m * n * (6 if args.prec == "bf16x3" else 1)
+        ach = flops / avg / 1e12
+        peak = {"fp64": FP64_PEAK_TFS, "fp32": FP32_PEAK_TFS, "bf16x3": BF16_PEAK_TFS}[args.prec]
         rooflines["sketch"] = {"bound": "mfma", "achieved": ach, "peak": peak,
                                "unit": "TFLOP/s", "frac": ach / peak,
                                "traffic": _traffic("sketch", "sketch_f64.hip", default_cfg),
-                               "algorithmic_flops_per_launch": 8.0 * l * m * n,
+                               "algorithmic_flops_per_launch": flops,
                                "avg_launch_ms": kern["sketch"]["avg_ms"]}
     dominant = max(kern, key=lambda x: kern[x]["total_ms"]) if kern else None
     roof = dict(rooflines.get(dominant, {}))
@@ -543,7 +552,7 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.prec == "fp64" else "f32 sketch products, f64 QR/solve/residual",
+        "dtype": DTYPE_TEXT[args.prec],
         "data": "synthetic",
         "config": {"workload": "%s randomized ID, A = X W + %g N %s, "
                                "%d x %d, k=%d, l=%d, q=%d power steps (%d passes over A)"

@@ -67,10 +67,12 @@ typedef enum {
 typedef enum { RID_C128 = 0, RID_C64 = 1 } rid_dtype;
 
 /* Arithmetic of the sketch product Y = G A (Y itself is always complex128).
- *   RID_FP64   double FMA (A must be RID_C128);
+ *   RID_FP64   double products and accumulation (either storage type);
  *   RID_FP32   single-precision products, single accumulation;
- *   RID_BF16X3 each operand split into three bfloat16 terms, six bf16
- *              products per real product, single accumulation.         */
+ *   RID_BF16X3 each operand split into three bfloat16 terms, the six
+ *              leading bf16 products per real product on the bf16 matrix
+ *              cores, single accumulation (FP32-level error).  Single IDs
+ *              only: batches take RID_FP64 or RID_FP32.                 */
 typedef enum { RID_FP64 = 0, RID_FP32 = 1, RID_BF16X3 = 2 } rid_prec;
 
 /* ---------------------------------------------------------------- handle */

@@ -74,6 +74,9 @@ bool use_graph() {
 
 }  // namespace
 
+// The grouped sketch is built for FP64 and FP32 products.
+bool batch_prec_supported(rid_prec prec) { return prec == RID_FP64 || prec == RID_FP32; }
+
 bool batch_job_supported(const RidBatchJob &j) {
   return j.l <= 256 && j.k <= 256 && sketch_pick_mt(j.l) > 0;
 }
@@ -295,7 +298,7 @@ extern "C" rid_status rid_decompose_batched(rid_handle h, hipStream_t stream, ri
     return RID_ERR_INVALID_ARG;
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
   if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
-  if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
+  if (!sketch_supported(dtype, prec) || !batch_prec_supported(prec)) return RID_ERR_UNSUPPORTED;
   const size_t align = dtype == RID_C128 ? 16 : 8;
   std::vector<RidBatchJob> bj(count);
   for (int i = 0; i < count; ++i) {
@@ -390,7 +393,7 @@ extern "C" rid_status rid_tune_batched(rid_handle h, hipStream_t stream, rid_dty
   if (!h || count < 1 || !jobs || q < 1) return RID_ERR_INVALID_ARG;
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
   if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
-  if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
+  if (!sketch_supported(dtype, prec) || !batch_prec_supported(prec)) return RID_ERR_UNSUPPORTED;
   const size_t align = dtype == RID_C128 ? 16 : 8;
   std::vector<RidBatchJob> bj(count);
   for (int i = 0; i < count; ++i) {

@@ -374,6 +374,7 @@ hipError_t launch_sketch_batch(hipStream_t st, rid_dtype dtype, rid_prec prec,
 int sketch_pick_mt(int64_t l);  // tiles per block for one batch job (0: unsupported)
 
 bool batch_job_supported(const RidBatchJob &j);
+bool batch_prec_supported(rid_prec prec);
 // Make the handle's workspace at least `bytes` long.  A larger buffer
 // (>= 1.5x the old one) replaces the old, which is kept until rid_destroy:
 // work still in flight may use it, and growing never waits for the device
@@ -397,6 +398,11 @@ template <class TA>
 hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
                              int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
                              int64_t ldy, void *part, RidProf *prof);
+size_t sketch_bf16_ws_bytes(int64_t m, int64_t n, int64_t l);
+template <class TA>
+hipError_t launch_sketch_bf16(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
+                              int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
+                              int64_t ldy, void *ws, RidProf *prof);
 size_t sketch_f32_ws_bytes(int64_t m, int64_t n, int64_t l);
 template <class TA>
 hipError_t launch_sketch_f32(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,

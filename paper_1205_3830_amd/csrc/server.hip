@@ -254,7 +254,7 @@ rid_status rid_server_submit(rid_server s, const rid_request *req, uint64_t *tic
   const bool big = s->cfg.big_lanes > 0 && r.m * r.n * es >= s->cfg.big_bytes;
   if (!big) {
     RidBatchJob bj{r.m, r.n, r.k, r.l, r.m, r.k, nullptr, r.seed, nullptr, nullptr, nullptr};
-    if (!batch_job_supported(bj)) return RID_ERR_UNSUPPORTED;
+    if (!batch_job_supported(bj) || !batch_prec_supported(r.prec)) return RID_ERR_UNSUPPORTED;
   }
   SrvJob j{};
   j.req = r;

@@ -1,0 +1,361 @@
+// sketch_bf16.hip -- randomization step Y = G A (Sec. 2) with products on the
+// bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16), each operand split into
+// three bfloat16 terms x = x_h + x_m + x_l (round to nearest at each step,
+// 24 significant bits in all) and the six leading cross products
+//   a_h b_h + a_h b_m + a_m b_h + a_h b_l + a_m b_m + a_l b_h
+// accumulated in FP32 within a K split; the K splits are summed in double
+// into the complex128 Y.  The dropped products are below 2^-24 relative, so
+// the result carries FP32-level error at three times the bf16 MFMA work, not
+// the FP32 MFMA rate.  The pivoted QR, the solve and the residual that
+// follow stay in double.
+//
+// Real embedding as in the other sketches: Yr (2l x n) = Ge (2l x 2m) Ar
+// (2m x n), Ge built from 2 x 2 blocks [[Re g, -Im g], [Im g, Re g]].
+// Operand layouts of the bf16 16x16x32 MFMA (measured on gfx950): lane l
+// supplies row l % 16 of the A operand (and column l % 16 of the B operand)
+// at k = 8 (l / 16) .. 8 (l / 16) + 7; D lane l, register r is row
+// 4 (l / 16) + r, column l % 16.  So one MFMA covers 16 complex rows of A: a
+// lane's four consecutive complex entries of its column are exactly its eight
+// k-slots (re, im interleaved), and row mu of Ge over those k-slots is 16
+// contiguous bytes of a pre-split plane.
+//
+// G is split once per call into three bf16 planes of Ge (row-major, 2m_pad
+// columns, zero padding), reused by every column block.  A workgroup (4
+// waves) owns 128 columns of A -- 2 groups of 16 per wave, so each G operand
+// read from LDS feeds two MFMA sets -- and MT 16-row tiles of Yr.  Per K step
+// of 16 complex rows the workgroup stages the three planes' slab in LDS (one
+// buffer, two barriers; the next slab and the next A entries are loaded into
+// registers while the current step computes).
+#include "rid_internal.hpp"
+
+namespace {
+
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int BF_MT_MAX = 14;  // tiles per workgroup (LDS: 3 KB per tile)
+
+RID_DEV void split3(double v, __bf16 &h, __bf16 &m, __bf16 &l) {
+  h = static_cast<__bf16>(static_cast<float>(v));
+  const double r1 = v - static_cast<double>(static_cast<float>(h));
+  m = static_cast<__bf16>(static_cast<float>(r1));
+  const double r2 = r1 - static_cast<double>(static_cast<float>(m));
+  l = static_cast<__bf16>(static_cast<float>(r2));
+}
+
+// Gs plane p (p = 0, 1, 2 at p * pstride), entry (mu, kappa) at mu * ldk + kappa:
+// the three bf16 terms of Ge(mu, kappa) for mu < 2 * rows_pad, kappa < ldk
+// (zero outside 2l x 2m).  One thread per complex entry (i, p).
+__global__ __launch_bounds__(256) void bf16_split_kernel(int64_t l, int64_t m, int64_t rows_pad,
+                                                         int64_t mpad,
+                                                         const double2 *__restrict__ G,
+                                                         int64_t ldg, __bf16 *__restrict__ Gs,
+                                                         int64_t ldk, int64_t pstride) {
+  const int64_t total = rows_pad * mpad;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t i = e / mpad;
+    const int64_t p = e - i * mpad;
+    const double2 g = (i < l && p < m) ? G[i * ldg + p] : make_double2(0.0, 0.0);
+    const double v[2][2] = {{g.x, -g.y}, {g.y, g.x}};  // Ge(2i + c, 2p + part)
+#pragma unroll
+    for (int c = 0; c < 2; ++c)
+#pragma unroll
+      for (int part = 0; part < 2; ++part) {
+        __bf16 h, mi, lo;
+        split3(v[c][part], h, mi, lo);
+        const int64_t at = (2 * i + c) * ldk + 2 * p + part;
+        Gs[at] = h;
+        Gs[pstride + at] = mi;
+        Gs[2 * pstride + at] = lo;
+      }
+  }
+}
+
+template <class TA>
+RID_DEV void load_a(const TA *Acol, int64_t pb, int64_t pend, bool ok, float (&v)[8]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    double2 a = make_double2(0.0, 0.0);
+    if (ok && pb + u < pend) a = to_d2(Acol[pb + u]);
+    v[2 * u] = static_cast<float>(a.x);
+    v[2 * u + 1] = static_cast<float>(a.y);
+  }
+}
+
+RID_DEV void split_vec(const float (&v)[8], bf8 &h, bf8 &m, bf8 &l) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const __bf16 vh = static_cast<__bf16>(v[e]);
+    const float r1 = v[e] - static_cast<float>(vh);
+    const __bf16 vm = static_cast<__bf16>(r1);
+    const float r2 = r1 - static_cast<float>(vm);
+    h[e] = vh;
+    m[e] = vm;
+    l[e] = static_cast<__bf16>(r2);
+  }
+}
+
+// Block (bx, by, bz): columns [128 bx, 128 bx + 128), K split by (rows
+// [by pchunk, ...) of A), tiles [MT bz, MT bz + MT) of Yr.
+template <int MT, class TA>
+RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restrict__ A,
+                              int64_t lda, const __bf16 *__restrict__ Gs, int64_t ldk,
+                              int64_t pstride, float *__restrict__ out, int64_t ldo,
+                              int64_t split_stride, int64_t pchunk, int64_t bx, int64_t by,
+                              int64_t bz) {
+  constexpr int ROWS = 16 * MT;                 // Yr rows of the slab
+  constexpr int CHUNKS = 3 * ROWS * 4;          // 16-byte pieces of the slab (3 planes)
+  constexpr int PER = (CHUNKS + 255) / 256;     // pieces staged per thread
+  __shared__ uint4 gsl[3][ROWS][4];             // [plane][row][k-group of 8]
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int q = lane >> 4;
+  const int r16 = lane & 15;
+  const int64_t mu0 = bz * ROWS;                // first Yr row of the slab
+  const int64_t pbeg = by * pchunk;
+  const int64_t pend = min(m, pbeg + pchunk);
+  int64_t jcol[2];
+  bool ok[2];
+  const TA *Acol[2];
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    jcol[g] = bx * 128 + wave * 32 + g * 16 + r16;
+    ok[g] = jcol[g] < n;
+    Acol[g] = A + (ok[g] ? jcol[g] : 0) * lda;
+  }
+  f4 acc[2][MT];
+#pragma unroll
+  for (int g = 0; g < 2; ++g)
+#pragma unroll
+    for (int t = 0; t < MT; ++t) acc[g][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  const int64_t rows_all = ((2 * l + ROWS - 1) / ROWS) * ROWS;  // rows of the planes
+  uint4 stg[PER];
+  auto load_slab = [&](int64_t p0) {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 256 * r;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (e < CHUNKS && p0 < pend) {
+        const int plane = e / (ROWS * 4);
+        const int rem = e - plane * ROWS * 4;
+        const int row = rem >> 2, kg = rem & 3;
+        const int64_t mu = mu0 + row;
+        if (mu < rows_all) {
+          const __bf16 *src = Gs + plane * pstride + mu * ldk + 2 * p0 + 8 * kg;
+          v = *reinterpret_cast<const uint4 *>(src);
+        }
+      }
+      stg[r] = v;
+    }
+  };
+  auto store_slab = [&]() {
+#pragma unroll
+    for (int r = 0; r < PER; ++r) {
+      const int e = tid + 256 * r;
+      if (e < CHUNKS) {
+        const int plane = e / (ROWS * 4);
+        const int rem = e - plane * ROWS * 4;
+        gsl[plane][rem >> 2][rem & 3] = stg[r];
+      }
+    }
+  };
+
+  float av[2][8], an[2][8];
+  load_slab(pbeg);
+#pragma unroll
+  for (int g = 0; g < 2; ++g) load_a(Acol[g], pbeg + 4 * q, pend, ok[g], av[g]);
+  for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
+    const bool more = p0 + 16 < pend;
+    __syncthreads();  // the previous step has finished reading the slab
+    store_slab();
+    __syncthreads();
+    if (more) {
+      load_slab(p0 + 16);
+#pragma unroll
+      for (int g = 0; g < 2; ++g) load_a(Acol[g], p0 + 16 + 4 * q, pend, ok[g], an[g]);
+    }
+    bf8 bh[2], bm[2], bl[2];
+#pragma unroll
+    for (int g = 0; g < 2; ++g) split_vec(av[g], bh[g], bm[g], bl[g]);
+    // tiles in groups of TG: each of the six products sweeps TG tiles x 2
+    // column groups, so consecutive MFMAs use 2 TG different accumulators
+    // (no back-to-back dependence); smallest products first
+    constexpr int TG = 4;
+#pragma unroll
+    for (int t0 = 0; t0 < MT; t0 += TG) {
+      bf8 ah[TG], am[TG], al[TG];
+#pragma unroll
+      for (int u = 0; u < TG; ++u) {
+        if (t0 + u < MT) {
+          ah[u] = __builtin_bit_cast(bf8, gsl[0][16 * (t0 + u) + r16][q]);
+          am[u] = __builtin_bit_cast(bf8, gsl[1][16 * (t0 + u) + r16][q]);
+          al[u] = __builtin_bit_cast(bf8, gsl[2][16 * (t0 + u) + r16][q]);
+        }
+      }
+#define RID_BF_PRODUCT(AX, BX)                                                        \
+  _Pragma("unroll") for (int u = 0; u < TG; ++u) {                                   \
+    if (t0 + u < MT) {                                                               \
+      _Pragma("unroll") for (int g = 0; g < 2; ++g) acc[g][t0 + u] =                 \
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(AX[u], BX[g], acc[g][t0 + u], 0, 0, 0); \
+    }                                                                                \
+  }
+      RID_BF_PRODUCT(al, bh)
+      RID_BF_PRODUCT(am, bm)
+      RID_BF_PRODUCT(ah, bl)
+      RID_BF_PRODUCT(am, bh)
+      RID_BF_PRODUCT(ah, bm)
+      RID_BF_PRODUCT(ah, bh)
+#undef RID_BF_PRODUCT
+    }
+    if (more) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int e = 0; e < 8; ++e) av[g][e] = an[g][e];
+    }
+  }
+  const int64_t rows = 2 * l;
+#pragma unroll
+  for (int g = 0; g < 2; ++g) {
+    if (!ok[g]) continue;
+    float *o = out + by * split_stride + jcol[g] * ldo;
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t mu = mu0 + int64_t(t) * 16 + 4 * q + r;
+        if (mu < rows) o[mu] = acc[g][t][r];
+      }
+  }
+}
+
+template <int MT, class TA>
+__global__ __launch_bounds__(256) void sketch_bf16_kernel(
+    int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
+    const __bf16 *__restrict__ Gs, int64_t ldk, int64_t pstride, float *__restrict__ out,
+    int64_t ldo, int64_t split_stride, int64_t pchunk) {
+  sketch_bf16_body<MT, TA>(m, n, l, A, lda, Gs, ldk, pstride, out, ldo, split_stride, pchunk,
+                           blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// Y(mu, j) = sum over splits (in order, in double) of part[s](mu, j).
+__global__ __launch_bounds__(256) void bf16_reduce_kernel(int64_t rows, int64_t n, int S,
+                                                          const float *__restrict__ part,
+                                                          double *__restrict__ Y, int64_t ldy2) {
+  const int64_t total = rows * n;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = e / rows;
+    const int64_t mu = e - j * rows;
+    double s = 0.0;
+    for (int sp = 0; sp < S; ++sp) s += static_cast<double>(part[sp * total + e]);
+    Y[j * ldy2 + mu] = s;
+  }
+}
+
+struct BfPlan {
+  int MT;          // tiles per workgroup
+  int nbz;         // workgroups along the Yr rows
+  int64_t nbx;     // workgroups along the columns (128 each)
+  int S;           // K splits
+  int64_t pchunk;  // rows of A per split (multiple of 16)
+  int64_t mpad;    // complex columns of the planes (multiple of 16)
+  int64_t rows_pad;  // complex rows of the planes
+  int64_t ldk, pstride;
+};
+
+BfPlan plan_bf16(int64_t m, int64_t n, int64_t l) {
+  BfPlan p;
+  const int64_t tiles = (2 * l + 15) / 16;
+  p.nbz = static_cast<int>((tiles + BF_MT_MAX - 1) / BF_MT_MAX);
+  p.MT = static_cast<int>((tiles + p.nbz - 1) / p.nbz);
+  p.nbx = (n + 127) / 128;
+  const int64_t base = p.nbx * p.nbz;
+  int64_t S = (2048 + base - 1) / base;
+  const int64_t maxS = (m + 255) / 256;
+  if (S > maxS) S = maxS;
+  if (S < 1) S = 1;
+  int64_t pchunk = (m + S - 1) / S;
+  pchunk = (pchunk + 15) / 16 * 16;
+  if (pchunk < 16) pchunk = 16;
+  if (rid_tl_short_blocks && pchunk > RID_SPLIT_ROWS_MAX) pchunk = RID_SPLIT_ROWS_MAX;
+  if ((m + pchunk - 1) / pchunk > 65535) pchunk = ((m + 65534) / 65535 + 15) / 16 * 16;
+  p.S = static_cast<int>((m + pchunk - 1) / pchunk);
+  if (p.S < 1) p.S = 1;
+  p.pchunk = pchunk;
+  p.mpad = ((m + 15) / 16) * 16;
+  p.rows_pad = int64_t(p.nbz) * p.MT * 8;  // complex rows: every slab row exists
+  p.ldk = 2 * p.mpad;
+  p.pstride = 2 * p.rows_pad * p.ldk;
+  return p;
+}
+
+template <int MT, class TA>
+void launch_bf16_mt(hipStream_t st, const BfPlan &p, int64_t m, int64_t n, int64_t l,
+                    const TA *A, int64_t lda, const __bf16 *Gs, float *part) {
+  dim3 grid(static_cast<unsigned>(p.nbx), static_cast<unsigned>(p.S),
+            static_cast<unsigned>(p.nbz));
+  hipLaunchKernelGGL((sketch_bf16_kernel<MT, TA>), grid, dim3(256), 0, st, m, n, l, A, lda, Gs,
+                     p.ldk, p.pstride, part, 2 * l, 2 * l * n, p.pchunk);
+}
+
+}  // namespace
+
+size_t sketch_bf16_ws_bytes(int64_t m, int64_t n, int64_t l) {
+  const BfPlan p = plan_bf16(m, n, l);
+  WsCarve c(nullptr);
+  c.take<__bf16>(3 * size_t(p.pstride));
+  c.take<float>(size_t(p.S) * size_t(2 * l) * size_t(n));
+  return c.off;
+}
+
+template <class TA>
+hipError_t launch_sketch_bf16(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
+                              int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
+                              int64_t ldy, void *ws, RidProf *prof) {
+  if (n == 0 || l == 0) return hipSuccess;
+  if (m == 0) return launch_zero(st, l, n, Y, ldy);
+  const BfPlan p = plan_bf16(m, n, l);
+  WsCarve c(ws);
+  __bf16 *Gs = c.take<__bf16>(3 * size_t(p.pstride));
+  float *part = c.take<float>(size_t(p.S) * size_t(2 * l) * size_t(n));
+  {
+    const int64_t total = p.rows_pad * p.mpad;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(bf16_split_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                       l, m, p.rows_pad, p.mpad, G, ldg, Gs, p.ldk, p.pstride);
+  }
+  ProfScope ps(prof, st, RID_KERNEL_SKETCH);
+  switch (p.MT) {
+#define RID_BF_CASE(X)                                               \
+  case X:                                                            \
+    launch_bf16_mt<X, TA>(st, p, m, n, l, A, lda, Gs, part);         \
+    break;
+    RID_BF_CASE(1) RID_BF_CASE(2) RID_BF_CASE(3) RID_BF_CASE(4) RID_BF_CASE(5) RID_BF_CASE(6)
+    RID_BF_CASE(7) RID_BF_CASE(8) RID_BF_CASE(9) RID_BF_CASE(10) RID_BF_CASE(11)
+    RID_BF_CASE(12) RID_BF_CASE(13) RID_BF_CASE(14)
+#undef RID_BF_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  ps.stop();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = 2 * l * n;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(bf16_reduce_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
+                     2 * l, n, p.S, part, reinterpret_cast<double *>(Y), 2 * ldy);
+  return hipGetLastError();
+}
+
+template hipError_t launch_sketch_bf16<double2>(hipStream_t, int64_t, int64_t, int64_t,
+                                                const double2 *, int64_t, const double2 *,
+                                                int64_t, double2 *, int64_t, void *, RidProf *);
+template hipError_t launch_sketch_bf16<float2>(hipStream_t, int64_t, int64_t, int64_t,
+                                               const float2 *, int64_t, const double2 *,
+                                               int64_t, double2 *, int64_t, void *, RidProf *);

@@ -1,9 +1,10 @@
 """GPU parity of the reduced-precision form: A stored complex64, sketch
-products in FP32 (single-precision accumulation within a K split), QR,
-triangular solve and residual sums in double.  The oracle runs in double on
+products in FP32 or as three-term bfloat16 splits (single-precision
+accumulation within a K split either way), QR, triangular solve and residual
+sums in double.  The oracle runs in double on
 exactly the same complex64 values (converted to complex128, which is exact).
 
-Stated accuracy of the FP32 sketch, against the double oracle:
+Stated accuracy of the FP32 and BF16x3 sketches, against the double oracle:
   Y      : ||dY||_F <= 2e-5 ||Y||_F  (u32 sqrt(K) per split, splits summed in double)
   J      : equal at every step whose relative pivot gap exceeds 1e-4
   P      : max|dP| <= 1e-3 max(1, max|P|)   (kappa(R1) times the Y error)
@@ -60,16 +61,19 @@ def test_sketch_fp64_products_on_complex64(h, m, n, l):
     assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("prec", ["RID_FP32", "RID_BF16X3"])
 @pytest.mark.parametrize("dt", [np.complex64, np.complex128])
-@pytest.mark.parametrize("m,n,l", [(1000, 500, 30), (4096, 300, 108), (333, 65, 208)])
-def test_sketch_fp32_products(h, dt, m, n, l):
+@pytest.mark.parametrize("m,n,l", [(1000, 500, 30), (4096, 300, 108), (333, 65, 208),
+                                   (9, 40, 12), (2053, 129, 113)])
+def test_sketch_reduced_precision_products(h, prec, dt, m, n, l):
     A = lowrank64(m, n, 8, 1e-3, seed=n).astype(dt)
     G = oracle.sketch_operator(l, m, seed=2)
-    Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda(), prec=rid.RID_FP32))
+    Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda(),
+                                     prec=getattr(rid, prec)))
     ref = oracle.sketch(A.astype(np.complex128), G)
     err = np.linalg.norm(Y - ref) / np.linalg.norm(ref)
     assert err <= 2e-5, err
-    assert err > 0.0          # the products really are single precision
+    assert err > 0.0          # the products really are of reduced precision
 
 
 @pytest.mark.parametrize("m,n,k,l,q", [(1000, 500, 20, 30, 8), (777, 333, 9, 17, 6)])
@@ -82,13 +86,14 @@ def test_residual_complex64_call_for_call(h, m, n, k, l, q):
     assert np.all(np.abs(host(hist) - r["hist"]) <= 1e-10 * r["hist"])
 
 
+@pytest.mark.parametrize("prec", ["RID_FP32", "RID_BF16X3"])
 @pytest.mark.parametrize("m,n,k,l", [(1000, 500, 20, 30), (2048, 700, 64, 72)])
-def test_decompose_complex64_fp32(h, m, n, k, l):
+def test_decompose_complex64_reduced_precision(h, prec, m, n, k, l):
     A = lowrank64(m, n, k, 1e-3, seed=m + k)
     A128 = A.astype(np.complex128)
     ref = oracle.decompose(A128, k, l, seed=0, q=8)
-    J, P, sigma, used = rid.rid_decompose(h, dev(A), k, l, seed=0, q=8, prec=rid.RID_FP32,
-                                          rank_tol=1e-5)
+    J, P, sigma, used = rid.rid_decompose(h, dev(A), k, l, seed=0, q=8,
+                                          prec=getattr(rid, prec), rank_tol=1e-5)
     J, P, s = host(J), host(P), float(host(sigma)[0])
     assert used == ref["seed_used"]
     for t in range(k):
@@ -115,8 +120,8 @@ def test_decompose_complex64_fp64_matches_double_oracle(h):
     assert abs(s - ref["sigma"]) <= tol
 
 
-def test_bf16x3_not_built_yet_is_reported(h):
+def test_bf16x3_batches_are_reported_unsupported(h):
     A = dev(lowrank64(100, 40, 4, 1e-3, seed=1))
     with pytest.raises(rid.RidError) as ei:
-        rid.rid_sketch(h, A, 8, 0, prec=rid.RID_BF16X3)
+        rid.rid_decompose_batched(h, [A], [4], [8], [0], q=2, prec=rid.RID_BF16X3)
     assert ei.value.status == rid.RID_ERR_UNSUPPORTED
