@@ -391,6 +391,43 @@ def bench_sweep(args, torch, rid, synth) -> int:
     return 0
 
 
+def bench_qr(args, torch, rid, synth) -> int:
+    """The two pivoted-QR methods on the same sketches (l x n, first k
+    pivots): Householder against CGS2, Sec. 3.2's comparison."""
+    shapes = [(108, 16384, 100), (200, 16384, 100), (800, 16384, 400), (2000, 65536, 1000)]
+    h = rid.rid_create(0)
+    rows = []
+    for l, n, k in shapes:
+        Y0 = synth.lowrank_device(l, n, k, 1e-10, seed=l).t()   # l x n, column-major
+        res = {}
+        for name, kind in (("householder", rid.RID_QR_HOUSEHOLDER), ("cgs2", rid.RID_QR_CGS2)):
+            rid.rid_set_qr(h, kind)
+            Y = Y0.clone()
+            rid.rid_pivqr(h, Y, k)                                 # warm-up
+            torch.cuda.synchronize()
+            best = None
+            for _ in range(3):
+                Y = Y0.clone()
+                torch.cuda.synchronize()
+                rid.rid_profile(h, True)
+                perm, _ = rid.rid_pivqr(h, Y, k)
+                torch.cuda.synchronize()
+                rid.rid_profile(h, False)
+                ms, _ = rid.rid_profile_read(h, rid.RID_KERNEL_PIVQR)
+                best = ms if best is None else min(best, ms)
+            res[name] = {"ms": best, "J": perm[:k].cpu()}
+        same = bool(torch.equal(res["householder"]["J"], res["cgs2"]["J"]))
+        rows.append({"l": l, "n": n, "k": k, "householder_ms": res["householder"]["ms"],
+                     "cgs2_ms": res["cgs2"]["ms"],
+                     "cgs2_over_householder": res["cgs2"]["ms"] / res["householder"]["ms"],
+                     "same_J": same})
+        print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
+    rid.rid_set_qr(h, rid.RID_QR_HOUSEHOLDER)
+    rid.rid_destroy(h)
+    print(json.dumps({"metric": "pivoted QR time, Householder vs CGS2", "rows": rows}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -410,7 +447,8 @@ def main() -> int:
                     help="arithmetic of the sketch products (QR, solve, residual stay double)")
     ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["single", "batched", "serving", "sweep"], default="single",
+    ap.add_argument("--form", choices=["single", "batched", "serving", "sweep", "qr"],
+                    default="single",
                     help="single: one large ID per step (default); batched: many uneven IDs "
                          "per call, compared with the single-ID FP64 path run one at a time; "
                          "serving: a Poisson request stream through the continuous-batching "
@@ -458,6 +496,8 @@ def main() -> int:
         return bench_serving(args, torch, rid, synth)
     if args.form == "sweep":
         return bench_sweep(args, torch, rid, synth)
+    if args.form == "qr":
+        return bench_qr(args, torch, rid, synth)
 
     m, n, k, l, q = args.m, args.n, args.k, args.l, args.q
     torch.cuda.set_device(0)

@@ -102,6 +102,18 @@ int rid_last_hip_error(rid_handle h);
 rid_status rid_reserve(rid_handle h, int64_t max_m, int64_t max_n, int64_t max_l,
                        int64_t max_k);
 
+/* Method of the column-pivoted QR of rid_pivqr and rid_decompose (batches
+ * always use Householder).  Both pivot on exact trailing norms, so they pick
+ * the same J away from near-ties and give the same T = R1^-1 R2 up to
+ * rounding.                                                              */
+typedef enum {
+  RID_QR_HOUSEHOLDER = 0, /* Householder reflections (default)                 */
+  RID_QR_CGS2 = 1         /* Gram-Schmidt with reorthogonalisation (Sec. 3.2); k <= 1024 */
+} rid_qr_kind;
+
+/* Select the QR method of this handle's later calls.  Errors: INVALID_ARG. */
+rid_status rid_set_qr(rid_handle h, int kind);
+
 /* ---------------------------------------------------------------- step 1 */
 
 /* The Gaussian sketch operator of the randomization step (Sec. 2), or any

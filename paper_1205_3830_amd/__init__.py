@@ -40,10 +40,13 @@ EXPORTED = ["rid_create", "rid_destroy", "rid_status_string", "rid_last_hip_erro
             "rid_interp", "rid_residual", "rid_decompose", "rid_query_status", "rid_profile",
             "rid_profile_read", "rid_set_sketch", "rid_srft_operator", "rid_decompose_batched",
             "rid_server_create", "rid_server_submit", "rid_server_drain", "rid_server_stats",
-            "rid_server_destroy", "rid_set_batch_plan", "rid_get_batch_plan", "rid_tune_batched"]
+            "rid_server_destroy", "rid_set_batch_plan", "rid_get_batch_plan", "rid_tune_batched",
+            "rid_set_qr"]
 
 RID_SKETCH_GAUSSIAN = 0
 RID_SKETCH_SRFT = 1
+RID_QR_HOUSEHOLDER = 0
+RID_QR_CGS2 = 1
 
 RID_KERNEL_SKETCH = 0
 RID_KERNEL_AX = 1
@@ -118,6 +121,7 @@ _sig = {
     "rid_server_submit": ([_P, ctypes.POINTER(rid_request), ctypes.POINTER(_U64)], _I),
     "rid_server_drain": ([_P], _I),
     "rid_set_batch_plan": ([_P, _I64, _I64, _I], _I),
+    "rid_set_qr": ([_P, _I], _I),
     "rid_get_batch_plan": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I)],
                            _I),
     "rid_tune_batched": ([_P, _P, _I, _I, ctypes.POINTER(rid_job), _I, _I,
@@ -239,6 +243,12 @@ def rid_gaussian(h, rows: int, cols: int, seed: int, stream_id: int, out=None, s
     _check(_L.rid_gaussian(h, _stream(stream), rows, cols, seed, stream_id, _ptr(out), ld),
            "rid_gaussian")
     return out
+
+
+def rid_set_qr(h, kind: int) -> None:
+    """Choose the pivoted-QR method (RID_QR_HOUSEHOLDER or RID_QR_CGS2) of
+    later rid_pivqr / rid_decompose calls."""
+    _check(_L.rid_set_qr(h, kind), "rid_set_qr")
 
 
 def rid_set_sketch(h, kind: int) -> None:

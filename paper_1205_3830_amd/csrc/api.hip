@@ -1,6 +1,7 @@
 // api.hip -- the extern "C" entry points of librid (declared in rid.h):
 // argument validation, device selection, workspace, and the order of the
 // steps of the randomized ID (Sec. 2), including the redraw on rank(Y) < k.
+#include <algorithm>
 #include <cmath>
 #include <new>
 
@@ -76,7 +77,7 @@ DecompWs carve_decomp(C &c, rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int
 }
 
 size_t bytes_decomp(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, int64_t l,
-                    int q) {
+                    int q, int qr_kind) {
   WsCarve c(nullptr);
   carve_decomp(c, dt, pr, m, n, k, l);
   // the region after `scratch` must also hold each later step's workspace
@@ -86,7 +87,7 @@ size_t bytes_decomp(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, 
   c2.take<double>(k);
   const size_t base = (c2.off + 255) & ~size_t(255);
   size_t need = c.off;
-  const size_t others[] = {pivqr_ws_bytes(l, n), interp_ws_bytes(n, k),
+  const size_t others[] = {pivqr_ws_bytes(l, n, k, qr_kind), interp_ws_bytes(n, k),
                            residual_ws_bytes(m, n, k, q)};
   for (size_t o : others)
     if (base + o > need) need = base + o;
@@ -121,7 +122,8 @@ hipError_t grow_ws(rid_handle h, size_t bytes) {
 
 size_t decomp_ws_bytes(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, int64_t l,
                        int q) {
-  return bytes_decomp(dt, pr, m, n, k, l, q);
+  return std::max(bytes_decomp(dt, pr, m, n, k, l, q, RID_QR_HOUSEHOLDER),
+                  bytes_decomp(dt, pr, m, n, k, l, q, RID_QR_CGS2));
 }
 
 extern "C" {
@@ -190,7 +192,10 @@ rid_status rid_reserve(rid_handle h, int64_t max_m, int64_t max_n, int64_t max_l
   size_t need = 0;
   for (rid_prec pr : {RID_FP64, RID_FP32}) {
     const size_t sk = bytes_sketch(RID_C128, pr, max_m, max_n, max_l, true);
-    const size_t d = bytes_decomp(RID_C128, pr, max_m, max_n, max_k, max_l, 1);
+    const size_t d = std::max(bytes_decomp(RID_C128, pr, max_m, max_n, max_k, max_l, 1,
+                                           RID_QR_HOUSEHOLDER),
+                              bytes_decomp(RID_C128, pr, max_m, max_n, max_k, max_l, 1,
+                                           RID_QR_CGS2));
     if (sk > need) need = sk;
     if (d > need) need = d;
   }
@@ -296,10 +301,11 @@ rid_status rid_pivqr(rid_handle h, hipStream_t stream, int64_t l, int64_t n, int
   if (!pivqr_supported(l)) return RID_ERR_UNSUPPORTED;
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
-  rid_status s = ensure_ws(h, pivqr_ws_bytes(l, n));
+  if (h->qr_kind == RID_QR_CGS2 && k > 1024) return RID_ERR_UNSUPPORTED;
+  rid_status s = ensure_ws(h, pivqr_ws_bytes(l, n, k, h->qr_kind));
   if (s != RID_OK) return s;
   hipError_t e = launch_pivqr(stream, l, n, k, static_cast<double2 *>(Y), ldy, perm, gaps,
-                              rank_tol, h->ws, h->d_status, &h->prof);
+                              rank_tol, h->ws, h->d_status, &h->prof, h->qr_kind);
   return e == hipSuccess ? RID_OK : fail_hip(h, e);
 }
 
@@ -337,6 +343,12 @@ rid_status rid_residual(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_p
                                  static_cast<const double2 *>(P), k > 0 ? ldp : 1, q, seed,
                                  sigma, hist, h->ws, &h->prof);
   return e == hipSuccess ? RID_OK : fail_hip(h, e);
+}
+
+rid_status rid_set_qr(rid_handle h, int kind) {
+  if (!h || (kind != RID_QR_HOUSEHOLDER && kind != RID_QR_CGS2)) return RID_ERR_INVALID_ARG;
+  h->qr_kind = kind;
+  return RID_OK;
 }
 
 rid_status rid_profile(rid_handle h, int enable) {
@@ -398,7 +410,8 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
   if (h->sketch_kind == RID_SKETCH_SRFT && m > 0x7FFFFFFFll) return RID_ERR_UNSUPPORTED;
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
-  rid_status s = ensure_ws(h, bytes_decomp(dtype, prec, m, n, k, l, q));
+  if (h->qr_kind == RID_QR_CGS2 && k > 1024) return RID_ERR_UNSUPPORTED;
+  rid_status s = ensure_ws(h, bytes_decomp(dtype, prec, m, n, k, l, q, h->qr_kind));
   if (s != RID_OK) return s;
   WsCarve c(h->ws);
   const DecompWs d = carve_decomp(c, dtype, prec, m, n, k, l);
@@ -409,7 +422,7 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
       e = launch_sketch(stream, dtype, prec, m, n, l, A, lda, d.G, m, d.Y, l, d.part, &h->prof);
     if (e == hipSuccess)
       e = launch_pivqr(stream, l, n, k, d.Y, l, d.perm, d.gaps, rank_tol, d.scratch,
-                       h->d_status, &h->prof);
+                       h->d_status, &h->prof, h->qr_kind);
     if (e != hipSuccess) return fail_hip(h, e);
     int st = 0;
     e = hipMemcpyAsync(&st, h->d_status, sizeof(int), hipMemcpyDeviceToHost, stream);

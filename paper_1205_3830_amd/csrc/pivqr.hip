@@ -17,6 +17,7 @@
 //      trailing rows) and second-best norm for step t.
 // Columns stay in place: after the last kernel, Y(0:k, :) is R in original
 // column order.  No floating-point atomics; every reduction has a fixed order.
+#include <algorithm>
 #include <climits>
 #include <type_traits>
 
@@ -309,6 +310,225 @@ __global__ __launch_bounds__(256) void pivqr_init_grouped(const PivJob *__restri
   if (e.y == 0 && threadIdx.x == 0) *jb.status = RID_OK;
 }
 
+// ---------------------------------------------------------------- CGS2
+// The paper's QR method (Sec. 3.2): Gram-Schmidt with reorthogonalisation,
+// here right-looking with the same exact pivoting as the Householder steps.
+// Y holds the residual columns r_j = (I - Q Q^H) y_j of the unpicked
+// columns, updated in place (r_j -= q_t (q_t^H r_j), R(t, j) = q_t^H r_j),
+// so the trailing norms |r_j| are exact.  The new direction q_t comes from
+// the pivot's residual column reorthogonalised once more against q_0 ..
+// q_{t-1} (the second pass of CGS2) and normalised; R(t, j*) = its norm.
+// R (k x n, zero below the picked rows) is kept in the workspace and copied
+// into Y(0:k, :) after the last step.  Step t is two launches: the pick
+// kernel (one workgroup) merges the candidates of step t-1, forms q_{t-1}
+// once and stores it with the pivot; the apply kernel (one workgroup per
+// 64 columns) applies it and publishes the candidates of step t (parity
+// buffers, full residual columns).
+
+template <int RR>
+__global__ __launch_bounds__(256) void cgs2_pick_kernel(int t, int64_t l, int64_t n, int64_t k,
+                                                        int64_t *perm, double *gaps,
+                                                        double rank_tol, PivWs w, double2 *Q,
+                                                        double2 *Rk, int *status, int64_t nb) {
+  constexpr int QU = 4;                    // directions per wave in flight
+  __shared__ double2 vs[64 * RR];          // the pivot's residual column, then v
+  __shared__ double2 c_s[1024];            // c_i = q_i^H v
+  __shared__ Cand red[256];
+  __shared__ double part[256];
+  __shared__ int status_s;
+  if (threadIdx.x == 0) status_s = *status;
+  __syncthreads();
+  if (status_s != RID_OK) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t rd = ((t - 1) & 1) * nb;
+  Cand cd = cand_empty();
+  for (int64_t b = tid; b < nb; b += 256) {
+    Cand x{w.cnorm[rd + b], w.cidx[rd + b], w.cnorm2[rd + b], 0};
+    if (x.v1 < 0.0) x = cand_empty();
+    cd = cand_merge(cd, x);
+  }
+  red[tid] = cd;
+  __syncthreads();
+  for (int st = 128; st >= 1; st >>= 1) {
+    if (tid < st) red[tid] = cand_merge(red[tid], red[tid + st]);
+    __syncthreads();
+  }
+  const Cand best = red[0];
+  const double nu1 = best.v1;
+  const double nu0 = (t == 1) ? nu1 : *w.nu0;
+  const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
+  if (tid == 0) {
+    perm[t - 1] = best.i1;
+    if (gaps) gaps[t - 1] = (best.v2 < 0.0) ? 1.0 : (nu1 - best.v2) / nu1;
+    if (t == 1) *w.nu0 = nu1;
+    if (fail) *status = RID_ERR_RANK;
+  }
+  if (fail) return;
+  const int64_t jstar = best.i1;
+  const double2 *x = w.ccol + (rd + jstar / PQ_COLS) * l;
+  for (int idx = tid; idx < 64 * RR; idx += 256)
+    vs[idx] = (idx < l) ? x[idx] : make_double2(0.0, 0.0);
+  __syncthreads();
+  // second Gram-Schmidt pass, coefficients: wave w takes directions
+  // i = w QU + 4 QU u + e (e < QU), QU dot products at a time
+  const int64_t nq = t - 1;
+  for (int64_t i0 = int64_t(wave) * QU; i0 < nq; i0 += 4 * QU) {
+    double dr[QU], di[QU];
+#pragma unroll
+    for (int e = 0; e < QU; ++e) dr[e] = di[e] = 0.0;
+#pragma unroll
+    for (int h = 0; h < RR; ++h) {
+      const int64_t row = lane + 64 * h;
+      if (row >= l) break;
+      const double2 vv = vs[row];
+#pragma unroll
+      for (int e = 0; e < QU; ++e) {
+        if (i0 + e < nq) {
+          const double2 qv = Q[(i0 + e) * l + row];
+          dr[e] += qv.x * vv.x + qv.y * vv.y;
+          di[e] += qv.x * vv.y - qv.y * vv.x;
+        }
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < QU; ++e) {
+      const double a = wave_sum(dr[e]), b = wave_sum(di[e]);
+      if (lane == 0 && i0 + e < nq) c_s[i0 + e] = make_double2(a, b);
+    }
+  }
+  __syncthreads();
+  // v -= sum_i c_i q_i: threads over rows, QU directions per iteration
+  double ss = 0.0;
+  for (int64_t row = tid; row < l; row += 256) {
+    double2 acc = vs[row];
+    for (int64_t i = 0; i < nq; i += QU) {
+#pragma unroll
+      for (int e = 0; e < QU; ++e) {
+        if (i + e < nq) {
+          const double2 c = c_s[i + e];
+          const double2 qv = Q[(i + e) * l + row];
+          acc.x -= qv.x * c.x - qv.y * c.y;
+          acc.y -= qv.x * c.y + qv.y * c.x;
+        }
+      }
+    }
+    vs[row] = acc;
+    ss += acc.x * acc.x + acc.y * acc.y;
+  }
+  part[tid] = ss;
+  __syncthreads();
+  for (int st = 128; st >= 1; st >>= 1) {
+    if (tid < st) part[tid] += part[tid + st];
+    __syncthreads();
+  }
+  const double nrm = sqrt(part[0]);
+  for (int64_t row = tid; row < l; row += 256)
+    Q[(t - 1) * l + row] = make_double2(vs[row].x / nrm, vs[row].y / nrm);
+  if (tid == 0) {
+    Rk[jstar * k + (t - 1)] = make_double2(nrm, 0.0);
+    w.pstep[jstar] = t - 1;
+  }
+}
+
+template <int RR>
+__global__ __launch_bounds__(256) void cgs2_apply_kernel(int t, int64_t l, int64_t n, int64_t k,
+                                                         double2 *Y, int64_t ldy, PivWs w,
+                                                         const double2 *Q, double2 *Rk,
+                                                         int *status) {
+  __shared__ double2 q_s[64 * RR];
+  __shared__ Cand red[4];
+  __shared__ int status_s;
+  if (threadIdx.x == 0) status_s = *status;
+  __syncthreads();
+  if (status_s != RID_OK) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t bx = blockIdx.x;
+  const int64_t nb = gridDim.x;
+  const int64_t cbeg = bx * PQ_COLS;
+  const int64_t wr = (t & 1) * nb;
+  if (t > 0) {
+    for (int idx = tid; idx < 64 * RR; idx += 256)
+      q_s[idx] = (idx < l) ? Q[(t - 1) * l + idx] : make_double2(0.0, 0.0);
+    __syncthreads();
+  }
+  Cand wc = cand_empty();
+  for (int cc = 0; cc < 16; ++cc) {
+    const int64_t j = cbeg + wave * 16 + cc;
+    if (j >= n) break;
+    if (w.pstep[j] >= 0) continue;  // picked, the pivot of this step included
+    double2 *col = Y + j * ldy;
+    double2 y[RR];
+#pragma unroll
+    for (int h = 0; h < RR; ++h) {
+      const int64_t row = lane + 64 * h;
+      y[h] = (row < l) ? col[row] : make_double2(0.0, 0.0);
+    }
+    if (t > 0) {
+      double dr = 0.0, di = 0.0;
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const double2 qv = q_s[lane + 64 * h];
+        dr += qv.x * y[h].x + qv.y * y[h].y;
+        di += qv.x * y[h].y - qv.y * y[h].x;
+      }
+      dr = wave_sum(dr);
+      di = wave_sum(di);
+      if (lane == 0) Rk[j * k + (t - 1)] = make_double2(dr, di);
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const double2 qv = q_s[lane + 64 * h];
+        y[h].x -= qv.x * dr - qv.y * di;
+        y[h].y -= qv.x * di + qv.y * dr;
+        const int64_t row = lane + 64 * h;
+        if (row < l) col[row] = y[h];
+      }
+    }
+    if (t < k) {
+      double ss = 0.0;
+#pragma unroll
+      for (int h = 0; h < RR; ++h) ss += y[h].x * y[h].x + y[h].y * y[h].y;
+      wc = cand_merge(wc, Cand{sqrt(wave_sum(ss)), j, -1.0, wave});
+    }
+  }
+  if (t >= k) return;
+  if (lane == 0) red[wave] = wc;
+  __syncthreads();
+  Cand bc = cand_empty();
+  for (int wv = 0; wv < 4; ++wv) bc = cand_merge(bc, red[wv]);
+  if (tid == 0) {
+    w.cnorm[wr + bx] = bc.v1;
+    w.cnorm2[wr + bx] = bc.v2;
+    w.cidx[wr + bx] = bc.i1;
+  }
+  if (bc.src >= 0) {
+    const double2 *src = Y + bc.i1 * ldy;
+    double2 *dst = w.ccol + (wr + bx) * l;
+    for (int64_t row = tid; row < l; row += 256) dst[row] = src[row];
+  }
+}
+
+__global__ void cgs2_zero_kernel(int64_t count, double2 *p) {
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < count;
+       e += int64_t(gridDim.x) * blockDim.x)
+    p[e] = make_double2(0.0, 0.0);
+}
+
+// Y(0:k, j) = R(:, j) once every step is done.
+__global__ void cgs2_copy_r_kernel(int64_t n, int64_t k, const double2 *__restrict__ Rk,
+                                   double2 *__restrict__ Y, int64_t ldy, const int *status) {
+  if (*status != RID_OK) return;
+  const int64_t total = n * k;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = e / k;
+    Y[j * ldy + (e - j * k)] = Rk[e];
+  }
+}
+
 // perm[k + r] = r-th unpicked column in increasing order (one workgroup).
 __global__ __launch_bounds__(1024) void pivqr_tail_kernel(int64_t n, int64_t k,
                                                           const int *pstep, int64_t *perm,
@@ -373,7 +593,16 @@ void launch_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y, i
 
 bool pivqr_supported(int64_t l) { return l >= 1 && pick_rr(l) > 0; }
 
-size_t pivqr_ws_bytes(int64_t l, int64_t n) { return piv_bytes(l, n); }
+size_t pivqr_ws_bytes(int64_t l, int64_t n, int64_t k, int kind) {
+  size_t b = piv_bytes(l, n);
+  if (kind == RID_QR_CGS2) {
+    WsCarve c(nullptr);
+    c.take<double2>(size_t(l) * size_t(k));
+    c.take<double2>(size_t(k) * size_t(n));
+    b += c.off + 256;
+  }
+  return b;
+}
 
 int64_t pivqr_blocks(int64_t n) { return (n + PQ_COLS - 1) / PQ_COLS; }
 
@@ -416,14 +645,38 @@ hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const 
 
 hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y,
                         int64_t ldy, int64_t *perm, double *gaps, double rank_tol, void *ws,
-                        int *d_status, RidProf *prof) {
+                        int *d_status, RidProf *prof, int kind) {
   const PivWs w = carve_piv(ws, l, n);
   ProfScope ps(prof, st, RID_KERNEL_PIVQR);
   hipLaunchKernelGGL(pivqr_init_kernel, dim3(static_cast<unsigned>((n + 255) / 256)),
                      dim3(256), 0, st, n, w.pstep, d_status);
-  with_rr(pick_rr(l), [&](auto R) {
-    launch_steps<decltype(R)::value>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
-  });
+  if (kind == RID_QR_CGS2) {
+    WsCarve c(static_cast<char *>(ws) + piv_bytes(l, n));
+    double2 *Q = c.take<double2>(size_t(l) * size_t(k));
+    double2 *Rk = c.take<double2>(size_t(k) * size_t(n));
+    const int64_t rcount = k * n;
+    hipLaunchKernelGGL(cgs2_zero_kernel,
+                       dim3(static_cast<unsigned>(std::min<int64_t>((rcount + 255) / 256, 65536))),
+                       dim3(256), 0, st, rcount, Rk);
+    const unsigned nb = static_cast<unsigned>((n + PQ_COLS - 1) / PQ_COLS);
+    with_rr(pick_rr(l), [&](auto R) {
+      constexpr int RR = decltype(R)::value;
+      for (int t = 0; t <= k; ++t) {
+        if (t > 0)
+          hipLaunchKernelGGL(cgs2_pick_kernel<RR>, dim3(1), dim3(256), 0, st, t, l, n, k, perm,
+                             gaps, rank_tol, w, Q, Rk, d_status, int64_t(nb));
+        hipLaunchKernelGGL(cgs2_apply_kernel<RR>, dim3(nb), dim3(256), 0, st, t, l, n, k, Y, ldy,
+                           w, Q, Rk, d_status);
+      }
+    });
+    hipLaunchKernelGGL(cgs2_copy_r_kernel,
+                       dim3(static_cast<unsigned>(std::min<int64_t>((rcount + 255) / 256, 65536))),
+                       dim3(256), 0, st, n, k, Rk, Y, ldy, d_status);
+  } else {
+    with_rr(pick_rr(l), [&](auto R) {
+      launch_steps<decltype(R)::value>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
+    });
+  }
   hipLaunchKernelGGL(pivqr_tail_kernel, dim3(1), dim3(1024), 0, st, n, k, w.pstep, perm,
                      d_status);
   ps.stop();

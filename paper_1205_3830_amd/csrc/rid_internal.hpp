@@ -65,6 +65,7 @@ struct rid_ctx {
   std::vector<void *> retired;  // superseded workspaces, freed by rid_destroy
   RidProf prof;
   int sketch_kind = RID_SKETCH_GAUSSIAN;  // operator drawn by rid_sketch / rid_decompose
+  int qr_kind = RID_QR_HOUSEHOLDER;       // method of rid_pivqr / rid_decompose
   hipStream_t cap_stream = nullptr;       // stream used to capture batch graphs
   bool batch_graph = true;                // capture batches into a graph (else launch directly)
   // plan of the batched path (rid_set_batch_plan / rid_tune_batched)
@@ -410,11 +411,12 @@ hipError_t launch_sketch_f32(hipStream_t st, int64_t m, int64_t n, int64_t l, co
                              int64_t ldy, void *part, RidProf *prof);
 
 // Pivoted QR workspace and launch.
-size_t pivqr_ws_bytes(int64_t l, int64_t n);
+// kind: RID_QR_HOUSEHOLDER or RID_QR_CGS2 (k <= 1024).
+size_t pivqr_ws_bytes(int64_t l, int64_t n, int64_t k, int kind);
 bool pivqr_supported(int64_t l);
 hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y,
                         int64_t ldy, int64_t *perm, double *gaps, double rank_tol,
-                        void *ws, int *d_status, RidProf *prof);
+                        void *ws, int *d_status, RidProf *prof, int kind);
 
 // Batched pivoted QR: one grouped launch per step over the (job, column
 // block, blocks of job) table; every job's table entries are its

@@ -70,6 +70,7 @@ def test_null_handle_and_bad_args_rejected_without_gpu():
     assert lib.rid_server_stats(None, None, None, None) == rid.RID_ERR_INVALID_ARG
     assert lib.rid_server_destroy(None) == rid.RID_ERR_INVALID_ARG
     assert lib.rid_set_batch_plan(None, 1024, 1 << 18, 8) == rid.RID_ERR_INVALID_ARG
+    assert lib.rid_set_qr(None, 0) == rid.RID_ERR_INVALID_ARG
     assert lib.rid_get_batch_plan(None, None, None, None) == rid.RID_ERR_INVALID_ARG
     assert lib.rid_tune_batched(None, None, 0, 0, None, 1, 1, None, None, None) == \
         rid.RID_ERR_INVALID_ARG

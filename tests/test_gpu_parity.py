@@ -280,8 +280,8 @@ def test_invalid_arguments_rejected(h):
         rid.rid_decompose(h, A, 3, 5, seed=0, q=0)     # q < 1
     assert ei.value.status == rid.RID_ERR_INVALID_ARG
     with pytest.raises(rid.RidError) as ei:
-        rid.rid_decompose(h, A, 3, 5, seed=0, prec=rid.RID_BF16X3)
-    assert ei.value.status == rid.RID_ERR_UNSUPPORTED
+        rid.rid_decompose(h, A, 3, 5, seed=0, prec=7)  # no such product arithmetic
+    assert ei.value.status == rid.RID_ERR_INVALID_ARG
 
 
 # ------------------------------------------------------------------ S F D operator
@@ -305,6 +305,72 @@ def test_decompose_with_srft_matches_oracle(h):
     assert np.linalg.norm(Y - r["Y"]) <= 1e-12 * np.linalg.norm(r["Y"])
     J, P, s = host(J), host(P), float(host(sigma)[0])
     assert _compare_J(J, r["J"], r["gaps"]) == k
+    dP = P - r["P"]
+    assert np.abs(dP).max() <= 1e-10 * max(1.0, np.abs(r["P"]).max())
+    tol = 1e-10 * r["sigma"] + 2 * np.linalg.norm(A[:, J]) * np.linalg.norm(dP)
+    assert abs(s - r["sigma"]) <= tol
+
+
+# ------------------------------------------------------------------ QR method: CGS2 (Sec. 3.2)
+@pytest.fixture
+def h_cgs2(h):
+    rid.rid_set_qr(h, rid.RID_QR_CGS2)
+    yield h
+    rid.rid_set_qr(h, rid.RID_QR_HOUSEHOLDER)
+
+
+@pytest.mark.parametrize("l,n,k", [(30, 500, 20), (108, 2000, 100), (12, 12, 12), (8, 300, 1),
+                                   (600, 700, 300), (64, 1 << 17, 30)])
+def test_cgs2_pivqr_and_interp_match_oracle(h_cgs2, l, n, k):
+    h = h_cgs2
+    Y = synth.lowrank(l, n, k, 1e-9, seed=3 * l + n)
+    st, Jo, Ro, gaps_o = oracle.select(Y, k)
+    assert st == oracle.OK
+    Po = oracle.interp(Ro, Jo)
+    Yd = dev(Y)
+    perm, gaps = rid.rid_pivqr(h, Yd, k)
+    assert rid.rid_query_status(h) == rid.RID_OK
+    perm = host(perm)
+    assert _compare_J(perm[:k], Jo, gaps_o) == k
+    assert np.array_equal(perm[k:], np.setdiff1d(np.arange(n), perm[:k]))
+    R = host(Yd)[:k]
+    R1 = R[:, perm[:k]]
+    assert np.all(np.tril(R1, -1) == 0)
+    # CGS2 gives a real positive diagonal: the exact trailing norms
+    assert np.allclose(R1.diagonal().real, np.abs(Ro[np.arange(k), Jo]), rtol=1e-11)
+    assert np.all(R1.diagonal().imag == 0)
+    P = host(rid.rid_interp(h, Yd[:k], torch.from_numpy(perm[:k]).cuda()))
+    assert np.abs(P - Po).max() <= 1e-10 * max(1.0, np.abs(Po).max())
+
+
+def test_cgs2_and_householder_agree(h):
+    Y = synth.lowrank(108, 3000, 100, 1e-10, seed=5)
+    out = {}
+    for kind in (rid.RID_QR_HOUSEHOLDER, rid.RID_QR_CGS2):
+        rid.rid_set_qr(h, kind)
+        Yd = dev(Y)
+        perm, _ = rid.rid_pivqr(h, Yd, 100)
+        P = rid.rid_interp(h, Yd[:100], perm[:100].clone())
+        out[kind] = (host(perm), host(P))
+    rid.rid_set_qr(h, rid.RID_QR_HOUSEHOLDER)
+    (ph, Ph), (pc, Pc) = out[rid.RID_QR_HOUSEHOLDER], out[rid.RID_QR_CGS2]
+    assert np.array_equal(ph, pc)
+    assert np.abs(Ph - Pc).max() <= 1e-10 * max(1.0, np.abs(Ph).max())
+    with pytest.raises(rid.RidError) as ei:
+        rid.rid_set_qr(h, 7)
+    assert ei.value.status == rid.RID_ERR_INVALID_ARG
+
+
+@pytest.mark.parametrize("m,n,k,l,noise,q", [(1000, 500, 20, 30, 1e-10, 10),
+                                             (2500, 900, 300, 600, 1e-10, 3)])
+def test_cgs2_decompose_matches_oracle(h_cgs2, m, n, k, l, noise, q):
+    h = h_cgs2
+    A = _lowrank(m, n, k, noise, seed=0)
+    r = oracle.decompose(A, k, l, seed=0, q=q)
+    J, P, sigma, used = rid.rid_decompose(h, dev(A), k, l, seed=0, q=q)
+    J, P, s = host(J), host(P), float(host(sigma)[0])
+    assert _compare_J(J, r["J"], r["gaps"]) == k
+    assert np.array_equal(P[:, J], np.eye(k))
     dP = P - r["P"]
     assert np.abs(dP).max() <= 1e-10 * max(1.0, np.abs(r["P"]).max())
     tol = 1e-10 * r["sigma"] + 2 * np.linalg.norm(A[:, J]) * np.linalg.norm(dP)
