@@ -235,10 +235,13 @@ template <>
 struct RowPair<double2> {
   static constexpr int STEP = 256;  // distance between the thread's two rows
   static constexpr int LANE = 1;    // rows per thread index
+  // p0 and p1 point into A even for rows past m (the caller clamps them), so
+  // both loads are issued unconditionally and the rows past m are zeroed
   RID_DEV static void load(const double2 *p0, const double2 *p1, bool ok0, bool ok1, int64_t off,
                            bool, double2 &a0, double2 &a1) {
-    a0 = ok0 ? ld_stream(p0 + off) : make_double2(0.0, 0.0);
-    a1 = ok1 ? ld_stream(p1 + off) : make_double2(0.0, 0.0);
+    const double2 v0 = ld_stream(p0 + off), v1 = ld_stream(p1 + off);
+    a0 = ok0 ? v0 : make_double2(0.0, 0.0);
+    a1 = ok1 ? v1 : make_double2(0.0, 0.0);
   }
 };
 template <>
@@ -275,19 +278,24 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
   double s1r = 0, c1r = 0, s1i = 0, c1i = 0;
   const TA *a0p = A + (ok0 ? i0 : 0);
   const TA *a1p = A + (ok1 ? i1 : 0);
-  auto acc = [&](const double2 &a0, const double2 &a1, const double2 &xh, const double2 &xl) {
+  // x~ = xh + xl; xl is zero except on the k skeleton columns, so the xl
+  // products (which only add to the compensation) are skipped for a group of
+  // columns whose xl are all zero -- a uniform test, no divergence
+  auto acc_hi = [&](const double2 &a0, const double2 &a1, const double2 &xh) {
     dot2_acc(s0r, c0r, a0.x, xh.x);
     dot2_acc(s0r, c0r, -a0.y, xh.y);
     dot2_acc(s0i, c0i, a0.x, xh.y);
     dot2_acc(s0i, c0i, a0.y, xh.x);
-    c0r = fma(a0.x, xl.x, c0r);
-    c0r = fma(-a0.y, xl.y, c0r);
-    c0i = fma(a0.x, xl.y, c0i);
-    c0i = fma(a0.y, xl.x, c0i);
     dot2_acc(s1r, c1r, a1.x, xh.x);
     dot2_acc(s1r, c1r, -a1.y, xh.y);
     dot2_acc(s1i, c1i, a1.x, xh.y);
     dot2_acc(s1i, c1i, a1.y, xh.x);
+  };
+  auto acc_lo = [&](const double2 &a0, const double2 &a1, const double2 &xl) {
+    c0r = fma(a0.x, xl.x, c0r);
+    c0r = fma(-a0.y, xl.y, c0r);
+    c0i = fma(a0.x, xl.y, c0i);
+    c0i = fma(a0.y, xl.x, c0i);
     c1r = fma(a1.x, xl.x, c1r);
     c1r = fma(-a1.y, xl.y, c1r);
     c1i = fma(a1.x, xl.y, c1i);
@@ -295,16 +303,27 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
   };
   int64_t j = jb;
   for (; j + 4 <= je; j += 4) {
-    double2 a0[4], a1[4];
+    double2 a0[4], a1[4], xl[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) RP::load(a0p, a1p, ok0, ok1, (j + u) * lda, pair, a0[u], a1[u]);
+    bool lo = false;
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc(a0[u], a1[u], xth[j + u], xtl[j + u]);
+    for (int u = 0; u < 4; ++u) {
+      xl[u] = xtl[j + u];
+      lo = lo || xl[u].x != 0.0 || xl[u].y != 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc_hi(a0[u], a1[u], xth[j + u]);
+    if (lo) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc_lo(a0[u], a1[u], xl[u]);
+    }
   }
   for (; j < je; ++j) {
     double2 a0, a1;
     RP::load(a0p, a1p, ok0, ok1, j * lda, pair, a0, a1);
-    acc(a0, a1, xth[j], xtl[j]);
+    acc_hi(a0, a1, xth[j]);
+    acc_lo(a0, a1, xtl[j]);
   }
   double *zp = r.zpart + by * m * 4;
   if (ok0) {
