@@ -243,6 +243,33 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
                          int64_t *J, void *P, int64_t ldp, double *sigma,
                          uint64_t *seed_used);
 
+/* ---------------------------------------------------------------- SVD */
+
+/* SVD built on the ID (Sec. 1 lists fast SVDs among the ID's uses): the
+ * rank-k SVD of A(:, J) P,  A(:, J) P = U diag(S) V^H, computed without
+ * forming A(:, J) P: B = A(:, J) = Q R_B by shifted CholeskyQR3,
+ * M = R_B P = W diag(S) Z^H by one-sided Jacobi on M^H, U = Q W, V = Z.
+ * A: m x n (lda >= m) of type `dtype`; J: k device indices in [0, n) (as
+ * left by rid_decompose); P: k x n complex128 (ldp >= k).  Outputs (device,
+ * caller-owned): U m x k complex128 (ldu >= m) with orthonormal columns,
+ * S k doubles in descending order, V n x k complex128 (ldv >= n) with
+ * orthonormal columns; the phase of each singular pair is arbitrary.
+ * *sweeps (host, may be null) = Jacobi sweeps used.  Requires
+ * 1 <= k <= min(m, n), k <= 256 (else UNSUPPORTED), m <= 2^22, n < 2^31.
+ * Returns RID_ERR_RANK when the QR of A(:, J) breaks down: a Cholesky
+ * pivot that is not positive, or a last Gram matrix far from I (a zero
+ * column; an index outside [0, n) is read as one).  A skeleton that is only
+ * numerically rank deficient (a repeated index) still gives an SVD, whose
+ * trailing singular values are at rounding level.  The Jacobi sweeps stop
+ * when every pair is orthogonal to sqrt(n) * 2^-52 relative, at most 60.
+ * Workspace about (5mk + 2nk) complex128.
+ * SYNCHRONISES the stream.  Errors: INVALID_ARG, UNSUPPORTED, NOMEM, HIP,
+ * RANK.                                                                   */
+rid_status rid_svd(rid_handle h, hipStream_t stream, rid_dtype dtype, int64_t m, int64_t n,
+                   int64_t k, const void *A, int64_t lda, const int64_t *J, const void *P,
+                   int64_t ldp, void *U, int64_t ldu, double *S, void *V, int64_t ldv,
+                   int *sweeps);
+
 /* ---------------------------------------------------------------- profiling */
 
 /* Kernel families timed by the profiling hook. */

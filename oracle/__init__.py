@@ -12,7 +12,9 @@ allows in place of the subsampled FFT when it is the faster choice.
 
 The arithmetic lives in ``rid_oracle.c`` (plain loops, IEEE double; the power
 iteration in binary128).  This module is the ctypes marshalling around it, plus
-``decompose`` which chains the steps and redraws on a rank failure (Sec. 2).
+``decompose`` which chains the steps and redraws on a rank failure (Sec. 2),
+and ``svd_from_id``, the SVD of the ID's approximation A(:,J) P (Sec. 1 lists
+fast SVDs among the ID's uses), written as its definition over LAPACK's SVD.
 
 Every function is pinned by a CPU test (tests/test_oracle_pins.py); none is
 "parity unpinned".  Arrays are numpy complex128, column-major (Fortran order)
@@ -243,3 +245,23 @@ def decompose(A, k: int, l: int, seed: int = 0, q: int = 10, max_retries: int = 
         s += 1
     return dict(status=ERR_RANK, J=J, P=None, sigma=None, hist=None, seed_used=s - 1, Y=Y,
                 R=None, gaps=gaps)
+
+
+# --------------------------------------------------------------------------
+# Downstream use: the SVD built on the ID
+# --------------------------------------------------------------------------
+def svd_from_id(A, J, P):
+    """Rank-k SVD of the ID's approximation A(:, J) P (Sec. 1 names fast
+    SVDs among the ID's uses).
+
+    The plain definition: form the m x n product A(:, J) P and take its
+    SVD with LAPACK (numpy's zgesdd), keeping the k leading triplets.
+    Returns (U m x k, S k descending, V n x k) with A(:,J) P ~ U diag(S) V^H.
+    """
+    A = _cf(A)
+    P = _cf(P)
+    J = np.asarray(J, dtype=np.int64)
+    k = P.shape[0]
+    BP = A[:, J] @ P
+    U, S, Vh = np.linalg.svd(BP, full_matrices=False)
+    return np.asfortranarray(U[:, :k]), S[:k].copy(), np.asfortranarray(Vh[:k].conj().T)

@@ -41,7 +41,7 @@ EXPORTED = ["rid_create", "rid_destroy", "rid_status_string", "rid_last_hip_erro
             "rid_profile_read", "rid_set_sketch", "rid_srft_operator", "rid_decompose_batched",
             "rid_server_create", "rid_server_submit", "rid_server_drain", "rid_server_stats",
             "rid_server_destroy", "rid_set_batch_plan", "rid_get_batch_plan", "rid_tune_batched",
-            "rid_set_qr"]
+            "rid_set_qr", "rid_svd"]
 
 RID_SKETCH_GAUSSIAN = 0
 RID_SKETCH_SRFT = 1
@@ -122,6 +122,8 @@ _sig = {
     "rid_server_drain": ([_P], _I),
     "rid_set_batch_plan": ([_P, _I64, _I64, _I], _I),
     "rid_set_qr": ([_P, _I], _I),
+    "rid_svd": ([_P, _P, _I, _I64, _I64, _I64, _P, _I64, _P, _P, _I64, _P, _I64, _P, _P, _I64,
+                 ctypes.POINTER(_I)], _I),
     "rid_get_batch_plan": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I)],
                            _I),
     "rid_tune_batched": ([_P, _P, _I, _I, ctypes.POINTER(rid_job), _I, _I,
@@ -368,6 +370,29 @@ def rid_decompose(h, A, k: int, l: int, seed: int = 0, q: int = 10, max_retries:
                               lda, seed, q, max_retries, rank_tol, _ptr(J), _ptr(P), ldp,
                               _ptr(sigma), ctypes.byref(used)), "rid_decompose")
     return J, P, sigma, int(used.value)
+
+
+def rid_svd(h, A, J, P, U=None, S=None, V=None, stream=None):
+    """Rank-k SVD of A(:,J) P; returns (U m x k, S k descending, V n x k,
+    Jacobi sweeps).  Synchronises."""
+    torch = _torch()
+    m, n = A.shape
+    k = J.shape[0]
+    lda = _ld_colmajor(A, "A")
+    ldp = _ld_colmajor(P, "P")
+    if U is None:
+        U = _new_colmajor(m, k, torch.complex128)
+    if S is None:
+        S = torch.zeros(k, dtype=torch.float64, device="cuda")
+    if V is None:
+        V = _new_colmajor(n, k, torch.complex128)
+    ldu = _ld_colmajor(U, "U")
+    ldv = _ld_colmajor(V, "V")
+    sweeps = _I(0)
+    _check(_L.rid_svd(h, _stream(stream), _dtype_code(A), m, n, k, _ptr(A), lda, _ptr(J),
+                        _ptr(P), ldp, _ptr(U), ldu, _ptr(S), _ptr(V), ldv, ctypes.byref(sweeps)),
+           "rid_svd")
+    return U, S, V, int(sweeps.value)
 
 
 def rid_query_status(h, stream=None) -> int:

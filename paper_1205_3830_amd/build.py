@@ -19,7 +19,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librid.so")
 
 SOURCES = ["gaussian.hip", "sketch_f64.hip", "sketch_f32.hip", "sketch_bf16.hip", "pivqr.hip", "interp.hip", "residual.hip",
-           "batched.hip", "api.hip", "server.hip"]
+           "batched.hip", "svd.hip", "api.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -446,4 +446,32 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
   return RID_ERR_RANK;
 }
 
+rid_status rid_svd(rid_handle h, hipStream_t stream, rid_dtype dtype, int64_t m, int64_t n,
+                   int64_t k, const void *A, int64_t lda, const int64_t *J, const void *P,
+                   int64_t ldp, void *U, int64_t ldu, double *S, void *V, int64_t ldv,
+                   int *sweeps) {
+  if (!h || k < 1 || k > m || k > n || lda < m || ldp < k || ldu < m || ldv < n || !A || !J ||
+      !P || !U || !S || !V || !aligned(P, 16) || !aligned(U, 16) || !aligned(V, 16) ||
+      m > (int64_t(1) << 22) || n > 0x7FFFFFFFll)
+    return RID_ERR_INVALID_ARG;
+  if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
+  if (!aligned(A, dtype == RID_C128 ? 16 : 8)) return RID_ERR_INVALID_ARG;
+  if (!svd_supported(k)) return RID_ERR_UNSUPPORTED;
+  DeviceGuard g(h->device);
+  if (g.err != hipSuccess) return fail_hip(h, g.err);
+  rid_status s = ensure_ws(h, svd_ws_bytes(m, n, k));
+  if (s != RID_OK) return s;
+  int bad = 0, used = 0;
+  const hipError_t e = launch_svd(stream, dtype, m, n, k, A, lda, J,
+                                  static_cast<const double2 *>(P), ldp, static_cast<double2 *>(U),
+                                  ldu, S, static_cast<double2 *>(V), ldv, h->ws, &bad, &used);
+  if (e == hipSuccess) {
+    const hipError_t e2 = hipStreamSynchronize(stream);
+    if (e2 != hipSuccess) return fail_hip(h, e2);
+  }
+  if (e != hipSuccess) return fail_hip(h, e);
+  if (sweeps) *sweeps = used;
+  return bad ? RID_ERR_RANK : RID_OK;
+}
+
 }  // extern "C"

@@ -427,6 +427,16 @@ void pivqr_job_carve(char *base, PivJob &jb);
 hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const PivJob *djobs,
                               const int4 *dtab, int64_t count, RidProf *prof);
 
+// SVD of A(:, J) P (k <= 256): workspace size and launch.  Synchronises the
+// stream (the Jacobi sweeps end on a device flag); *rank_bad is set when
+// the Cholesky of the skeleton's Gram matrix breaks down.
+bool svd_supported(int64_t k);
+size_t svd_ws_bytes(int64_t m, int64_t n, int64_t k);
+hipError_t launch_svd(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t k,
+                      const void *A, int64_t lda, const int64_t *J, const double2 *P, int64_t ldp,
+                      double2 *U, int64_t ldu, double *S, double2 *V, int64_t ldv, void *ws,
+                      int *rank_bad, int *sweeps_used);
+
 size_t interp_ws_bytes(int64_t n, int64_t k);
 bool interp_supported(int64_t k);
 hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R, int64_t ldr,

@@ -74,6 +74,19 @@ def lowrank_device(m: int, n: int, k: int, noise: float, seed: int = 0,
     return T
 
 
+def with_spectrum(m: int, n: int, s, seed: int = 0) -> np.ndarray:
+    """Host A = U0 diag(s) V0^H, Fortran order, with U0 (m x r) and V0 (n x r)
+    orthonormal (QR of complex Gaussian factors), r = len(s): the singular
+    values of A are the entries of s (up to rounding)."""
+    s = np.asarray(s, dtype=np.float64)
+    r = s.shape[0]
+    ss = np.random.SeedSequence(seed)
+    ru, rv = [np.random.Generator(np.random.PCG64(x)) for x in ss.spawn(2)]
+    U0, _ = np.linalg.qr(_cgauss(ru, (m, r)))
+    V0, _ = np.linalg.qr(_cgauss(rv, (n, r)))
+    return np.asfortranarray((U0 * s) @ V0.conj().T)
+
+
 def hand_example():
     """The 2 x 3 integer matrix used as a worked example in the tests."""
     return np.asfortranarray(np.array([[2, 0, 1], [0, 1, 1]], dtype=np.complex128))

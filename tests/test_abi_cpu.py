@@ -74,6 +74,8 @@ def test_null_handle_and_bad_args_rejected_without_gpu():
     assert lib.rid_get_batch_plan(None, None, None, None) == rid.RID_ERR_INVALID_ARG
     assert lib.rid_tune_batched(None, None, 0, 0, None, 1, 1, None, None, None) == \
         rid.RID_ERR_INVALID_ARG
+    assert lib.rid_svd(None, None, 0, 100, 50, 5, P(16), 100, P(16), P(16), 5, P(16), 100,
+                       P(16), P(16), 50, None) == rid.RID_ERR_INVALID_ARG
 
 
 def test_binding_functions_carry_the_c_names():

@@ -109,3 +109,27 @@ def test_fullsize_residual(big):
     col_norms = [float(np.sqrt(np.sum(np.abs(Ac[:, i] - AJ @ P[:, c].astype(np.clongdouble)) ** 2)))
                  for i, c in enumerate(cols)]
     assert s >= 0.9 * max(col_norms)
+
+
+def test_fullsize_svd_on_the_id(big):
+    # The SVD built on the ID at full size, by properties that hold at any
+    # size: orthonormal U and V, descending S, U S V^H = A(:,J) P on sampled
+    # columns, and, on sampled rows, A V - U S = E V with E = A - A(:,J) P,
+    # so each row is at most ||E||_2 (~ sigma, the power estimate) long.
+    A, J, P = big["A"], big["J"], big["P"]
+    Pd = torch.from_numpy(np.ascontiguousarray(P.T)).cuda().t()
+    U, S, V, sweeps = rid.rid_svd(big["h"], A, torch.from_numpy(J).cuda(), Pd)
+    U, S, V = U.cpu().numpy(), S.cpu().numpy(), V.cpu().numpy()
+    assert 1 <= sweeps < 60
+    assert np.all(np.diff(S) <= 0.0) and S[-1] > 0.0
+    s0 = S[0]
+    assert np.abs(U.conj().T @ U - np.eye(K)).max() <= 1e-11
+    assert np.abs(V.conj().T @ V - np.eye(K)).max() <= 1e-11
+    AJ = A[:, J.tolist()].t().contiguous().cpu().numpy().T
+    for c in [0, 1, 4097, 16383] + [int(J[0]), int(J[-1])]:
+        rec = (U * S) @ V[c].conj()
+        assert np.abs(rec - AJ @ P[:, c]).max() <= 1e-11 * s0, c
+    rows = [0, 5, 65536, M - 1]
+    Ar = A[rows, :].cpu().numpy()
+    for i, r in enumerate(rows):
+        assert np.linalg.norm(Ar[i] @ V - U[r] * S) <= 4 * big["sigma"] + 1e-11 * s0, r

@@ -402,3 +402,55 @@ def test_srft_decompose_matches_pivoted_qr_of_its_sketch():
     assert np.array_equal(r["J"], piv[:20])
     E = A - A[:, r["J"]] @ r["P"]
     assert r["sigma"] <= np.linalg.norm(E, 2) * (1 + 1e-6)
+
+
+# ---------------------------------------------------------------- SVD on the ID
+def test_svd_from_id_rank_one_closed_form():
+    # A = sigma x y^H with unit x, y: the ID of rank 1 is exact, so the one
+    # singular triplet is (sigma, x, y) up to a common phase.
+    rng = np.random.default_rng(11)
+    x = rng.normal(size=40) + 1j * rng.normal(size=40)
+    y = rng.normal(size=25) + 1j * rng.normal(size=25)
+    x /= np.linalg.norm(x)
+    y /= np.linalg.norm(y)
+    sigma = 3.75
+    A = np.asfortranarray(sigma * np.outer(x, y.conj()))
+    r = oracle.decompose(A, 1, 4, seed=2, q=4)
+    U, S, V = oracle.svd_from_id(A, r["J"], r["P"])
+    assert U.shape == (40, 1) and S.shape == (1,) and V.shape == (25, 1)
+    assert abs(S[0] - sigma) < 1e-13 * sigma
+    assert abs(abs(np.vdot(x, U[:, 0])) - 1.0) < 1e-13
+    assert abs(abs(np.vdot(y, V[:, 0])) - 1.0) < 1e-13
+    # the phases of u and v agree: u S v^H reproduces A itself
+    assert np.abs(U * S @ V.conj().T - A).max() < 1e-13 * sigma
+
+
+@pytest.mark.parametrize("m,n,k", [(120, 90, 8), (60, 200, 13)])
+def test_svd_from_id_recovers_a_prescribed_spectrum(m, n, k):
+    # A = U0 diag(s0) V0^H has rank k exactly, so A(:,J) P = A up to
+    # rounding: S must be s0 and every pair must satisfy A v_i = s_i u_i and
+    # A^H u_i = s_i v_i for A itself.
+    s0 = np.logspace(0, -6, k)
+    A = synth.with_spectrum(m, n, s0, seed=k)
+    r = oracle.decompose(A, k, k + 6, seed=5, q=4)
+    U, S, V = oracle.svd_from_id(A, r["J"], r["P"])
+    assert np.abs(S - s0).max() < 1e-12
+    assert np.abs(A @ V - U * S).max() < 1e-12
+    assert np.abs(A.conj().T @ U - V * S).max() < 1e-12
+
+
+def test_svd_from_id_weyl_and_optimality_bounds():
+    # With noise A is not of rank k: Weyl's inequality bounds each singular
+    # value of A(:,J) P by the ID's error E, and no rank-k matrix beats
+    # sigma_{k+1}(A) (Eckart-Young).
+    m, n, k = 150, 110, 10
+    A = synth.lowrank(m, n, k, noise=1e-6, seed=21)
+    r = oracle.decompose(A, k, 2 * k, seed=3, q=4)
+    U, S, V = oracle.svd_from_id(A, r["J"], r["P"])
+    sA = np.linalg.svd(A, compute_uv=False)
+    normE = np.linalg.norm(A - A[:, r["J"]] @ r["P"], 2)
+    assert np.all(np.abs(S - sA[:k]) <= normE * (1 + 1e-9) + 1e-12 * sA[0])
+    assert np.linalg.norm(A - U * S @ V.conj().T, 2) >= sA[k] * (1 - 1e-9)
+    assert np.all(np.diff(S) <= 0) and S[-1] >= 0
+    assert np.abs(U.conj().T @ U - np.eye(k)).max() < 1e-13
+    assert np.abs(V.conj().T @ V - np.eye(k)).max() < 1e-13
