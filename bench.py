@@ -428,6 +428,45 @@ def bench_qr(args, torch, rid, synth) -> int:
     return 0
 
 
+def bench_svd(args, torch, rid, synth) -> int:
+    """The SVD built on the ID (rid_svd) after one ID of the benchmark matrix:
+    time per SVD, Jacobi sweeps, and the orthogonality of U and V."""
+    m, n, k, l, q = args.m, args.n, args.k, args.l, args.q
+    torch.cuda.set_device(0)
+    print("generating A %d x %d c128 on the GPU" % (m, n), file=sys.stderr, flush=True)
+    A = synth.lowrank_device(m, n, k, args.noise, seed=0).t()
+    h = rid.rid_create(0)
+    rid.rid_reserve(h, m, n, l, k)
+    t0 = time.perf_counter()
+    J, P, sigma, _ = rid.rid_decompose(h, A, k, l, seed=0, q=q)
+    torch.cuda.synchronize()
+    id_ms = (time.perf_counter() - t0) * 1e3
+    U = torch.empty((k, m), dtype=torch.complex128, device="cuda").t()
+    V = torch.empty((k, n), dtype=torch.complex128, device="cuda").t()
+    S = torch.zeros(k, dtype=torch.float64, device="cuda")
+    sweeps = 0
+    for i in range(args.warmup):
+        _, _, _, sweeps = rid.rid_svd(h, A, J, P, U=U, S=S, V=V)
+        print("warmup %d done (%d sweeps)" % (i, sweeps), file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        _, _, _, sweeps = rid.rid_svd(h, A, J, P, U=U, S=S, V=V)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    eye = torch.eye(k, dtype=torch.complex128, device="cuda")
+    orth_u = float((U.conj().t() @ U - eye).abs().max())
+    orth_v = float((V.conj().t() @ V - eye).abs().max())
+    Sh = S.cpu().numpy()
+    rid.rid_destroy(h)
+    print(json.dumps({"metric": "SVD of A(:,J) P after the ID", "m": m, "n": n, "k": k,
+                      "ms_per_svd": ms, "id_ms_first_call": id_ms, "sweeps": sweeps,
+                      "orth_U": orth_u, "orth_V": orth_v, "S0": float(Sh[0]),
+                      "S_k_over_S0": float(Sh[-1] / Sh[0]),
+                      "sigma_id": float(sigma.cpu()[0])}))
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -447,14 +486,15 @@ def main() -> int:
                     help="arithmetic of the sketch products (QR, solve, residual stay double)")
     ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--form", choices=["single", "batched", "serving", "sweep", "qr"],
+    ap.add_argument("--form", choices=["single", "batched", "serving", "sweep", "qr", "svd"],
                     default="single",
                     help="single: one large ID per step (default); batched: many uneven IDs "
                          "per call, compared with the single-ID FP64 path run one at a time; "
                          "serving: a Poisson request stream through the continuous-batching "
                          "server, compared with the plain FP64 path one request at a time; "
                          "sweep: the paper's Table 1 shapes (l = 2k, A = B P) with per-phase "
-                         "times")
+                         "times; qr: Householder against CGS2 pivoted QR; svd: the SVD built "
+                         "on the ID")
     ap.add_argument("--shapes", default="all",
                     help="sweep: comma-separated indices into the Table 1 shapes, or all")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: requests per second")
@@ -498,6 +538,8 @@ def main() -> int:
         return bench_sweep(args, torch, rid, synth)
     if args.form == "qr":
         return bench_qr(args, torch, rid, synth)
+    if args.form == "svd":
+        return bench_svd(args, torch, rid, synth)
 
     m, n, k, l, q = args.m, args.n, args.k, args.l, args.q
     torch.cuda.set_device(0)

@@ -247,22 +247,22 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
 
 /* SVD built on the ID (Sec. 1 lists fast SVDs among the ID's uses): the
  * rank-k SVD of A(:, J) P,  A(:, J) P = U diag(S) V^H, computed without
- * forming A(:, J) P: B = A(:, J) = Q R_B by shifted CholeskyQR3,
- * M = R_B P = W diag(S) Z^H by one-sided Jacobi on M^H, U = Q W, V = Z.
+ * forming A(:, J) P: B = A(:, J) = Q R_B and (R_B P)^H = Q_X R_X by shifted
+ * CholeskyQR3, R_X Z = W diag(S) by one-sided Jacobi, U = Q Z, V = Q_X W.
  * A: m x n (lda >= m) of type `dtype`; J: k device indices in [0, n) (as
  * left by rid_decompose); P: k x n complex128 (ldp >= k).  Outputs (device,
  * caller-owned): U m x k complex128 (ldu >= m) with orthonormal columns,
  * S k doubles in descending order, V n x k complex128 (ldv >= n) with
  * orthonormal columns; the phase of each singular pair is arbitrary.
- * *sweeps (host, may be null) = Jacobi sweeps used.  Requires
+ * *sweeps (host, may be null) = Jacobi sweeps used (they stop when every
+ * pair is orthogonal to sqrt(k) * 2^-52 relative, at most 60).  Requires
  * 1 <= k <= min(m, n), k <= 256 (else UNSUPPORTED), m <= 2^22, n < 2^31.
- * Returns RID_ERR_RANK when the QR of A(:, J) breaks down: a Cholesky
- * pivot that is not positive, or a last Gram matrix far from I (a zero
- * column; an index outside [0, n) is read as one).  A skeleton that is only
- * numerically rank deficient (a repeated index) still gives an SVD, whose
- * trailing singular values are at rounding level.  The Jacobi sweeps stop
- * when every pair is orthogonal to sqrt(n) * 2^-52 relative, at most 60.
- * Workspace about (5mk + 2nk) complex128.
+ * Returns RID_ERR_RANK when one of the two QRs breaks down (a Cholesky
+ * pivot that is not positive, or a last Gram matrix far from I): exact
+ * rank loss such as a zero column of A(:, J) (an index outside [0, n) is
+ * read as one) or P = 0.  An input that is only numerically rank deficient
+ * (a repeated index) still gives an SVD, whose trailing singular values
+ * are at rounding level.  Workspace about (6 max(m, n) k) complex128.
  * SYNCHRONISES the stream.  Errors: INVALID_ARG, UNSUPPORTED, NOMEM, HIP,
  * RANK.                                                                   */
 rid_status rid_svd(rid_handle h, hipStream_t stream, rid_dtype dtype, int64_t m, int64_t n,

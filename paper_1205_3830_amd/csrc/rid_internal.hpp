@@ -428,8 +428,8 @@ hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const 
                               const int4 *dtab, int64_t count, RidProf *prof);
 
 // SVD of A(:, J) P (k <= 256): workspace size and launch.  Synchronises the
-// stream (the Jacobi sweeps end on a device flag); *rank_bad is set when
-// the Cholesky of the skeleton's Gram matrix breaks down.
+// stream (to read the sweep count and the breakdown flag); *rank_bad is set
+// when one of the two CholeskyQR3 runs breaks down.
 bool svd_supported(int64_t k);
 size_t svd_ws_bytes(int64_t m, int64_t n, int64_t k);
 hipError_t launch_svd(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t k,

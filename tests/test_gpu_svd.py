@@ -78,7 +78,9 @@ SVD_CASES = [
     (333, 257, 17, 27, None),           # ragged m, n; odd k (padded pairing)
     (50, 40, 1, 5, None),               # k = 1: no rotation at all
     (64, 64, 2, 8, None),
+    (700, 400, 75, 85, None),           # odd k in (64, 100]: recorded rotations
     (2000, 300, 100, 108, None),        # k and l of the large workload
+    (900, 500, 120, 130, None),         # k > 100: Jacobi and Cholesky in global memory
     (600, 400, 256, 266, None),         # largest k
     (800, 300, 30, 40, "1e-10"),        # cond(A(:,J)) ~ 1e10: needs the shifted pass
 ]
@@ -143,7 +145,7 @@ def test_svd_of_an_exact_rank_k_matrix_is_its_svd(h):
 @pytest.mark.parametrize("kind", ["out_of_range", "zero_column"])
 def test_svd_breakdown_of_the_skeleton_qr_is_reported(h, kind):
     # a zero column of A(:,J) (or an index outside [0, n), read as one)
-    # gives an exactly zero Cholesky pivot in the second pass
+    # gives an exactly zero Cholesky pivot in the second pass of its QR
     m, n, k = 200, 150, 10
     A = synth.lowrank(m, n, k, 1e-8, seed=5)
     r = oracle.decompose(A, k, k + 6, seed=0, q=2)
@@ -203,6 +205,12 @@ def test_svd_invalid_arguments(h):
     with pytest.raises(rid.RidError) as ei:   # k > m
         rid.rid_svd(h, dev(np.ones((2, 10))), J, P)
     assert ei.value.status == rid.RID_ERR_INVALID_ARG
-    U, S, V, _ = rid.rid_svd(h, A, J, P)      # a valid call still works afterwards:
-    assert U.shape == (20, 3)                 # P = 0 gives S = 0
-    assert torch.all(S == 0.0)
+    with pytest.raises(rid.RidError) as ei:   # P = 0: A(:,J) P has rank 0 < k
+        rid.rid_svd(h, A, J, P)
+    assert ei.value.status == rid.RID_ERR_RANK
+    P1 = np.zeros((3, 10))
+    P1[:, :3] = np.eye(3)                     # a valid call still works afterwards
+    U, S, V, _ = rid.rid_svd(h, A, J, dev(P1))
+    assert U.shape == (20, 3) and V.shape == (10, 3)
+    sref = np.linalg.svd(host(A)[:, :3], compute_uv=False)
+    assert np.abs(host(S) - sref).max() <= TAU * sref[0]
