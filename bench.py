@@ -484,6 +484,9 @@ def main() -> int:
                     help="storage of A")
     ap.add_argument("--prec", choices=["fp64", "fp32", "bf16x3"], default="fp64",
                     help="arithmetic of the sketch products (QR, solve, residual stay double)")
+    ap.add_argument("--sketch", choices=["gaussian", "srft"], default="gaussian",
+                    help="random operator: Gaussian G, or the paper's S F D (four-step DFT "
+                         "form when m is a multiple of 8)")
     ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", choices=["single", "batched", "serving", "sweep", "qr", "svd"],
@@ -561,6 +564,8 @@ def main() -> int:
         torch.cuda.synchronize()
         del src, dst
     h = rid.rid_create(0)
+    if args.sketch == "srft":
+        rid.rid_set_sketch(h, rid.RID_SKETCH_SRFT)
     rid.rid_reserve(h, m, n, l, k)
     J = torch.empty(k, dtype=torch.int64, device="cuda")
     P = torch.empty((n, k), dtype=torch.complex128, device="cuda").t()
@@ -591,8 +596,8 @@ def main() -> int:
         tot, cnt = rid.rid_profile_read(h, kid)
         if cnt:
             kern[name] = {"total_ms": tot, "launches": cnt, "avg_ms": tot / cnt}
-    default_cfg = (args.dtype == "c128" and args.prec == "fp64" and (m, n, k, l, q) ==
-                   (131072, 16384, 100, 108, 10))
+    default_cfg = (args.dtype == "c128" and args.prec == "fp64" and args.sketch == "gaussian"
+                   and (m, n, k, l, q) == (131072, 16384, 100, 108, 10))
     rooflines = {}
     for name, src in (("residual_ax", "residual.hip"), ("residual_ahz", "residual.hip")):
         if name in kern:
@@ -603,7 +608,7 @@ def main() -> int:
                                "traffic": _traffic(name, src, default_cfg),
                                "algorithmic_bytes_per_launch": bytes_a,
                                "avg_launch_ms": kern[name]["avg_ms"]}
-    if "sketch" in kern:
+    if "sketch" in kern and args.sketch == "gaussian":
         avg = kern["sketch"]["avg_ms"] * 1e-3
         # the bf16 split form does six bf16 products per real product
         flops = 8.0 * l * m * n * (6 if args.prec == "bf16x3" else 1)
@@ -640,16 +645,20 @@ def main() -> int:
                                "%d x %d, k=%d, l=%d, q=%d power steps (%d passes over A)"
                                % ("plain FP64" if args.prec == "fp64" and args.dtype == "c128"
                                   else "%s storage, %s sketch" % (args.dtype, args.prec),
-                                  noise, args.dtype, m, n, k, l, q, passes),
+                                  noise, args.dtype, m, n, k, l, q, passes)
+                               + ("" if args.sketch == "gaussian" else
+                                  ", S F D operator (four-step DFT)"),
                    "m": m, "n": n, "k": k, "l": l, "q": q, "bytes_A": bytes_a,
-                   "storage": args.dtype, "sketch_products": args.prec},
+                   "storage": args.dtype, "sketch_products": args.prec,
+                   "operator": args.sketch},
         "roofline": roof,
         "kernels": kern,
         "rooflines": rooflines,
         "sigma": float(sigma.cpu()[0]),
         "identity_on_J": ok,
     }
-    if not args.no_cpu_baseline and args.cpu_cols > 0 and args.dtype == "c128":
+    if (not args.no_cpu_baseline and args.cpu_cols > 0 and args.dtype == "c128"
+            and args.sketch == "gaussian"):
         print("timing the CPU oracle on a column sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(A, k, l, q, min(args.cpu_cols, n))
     rid.rid_destroy(h)

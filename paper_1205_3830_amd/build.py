@@ -18,7 +18,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "librid.so")
 
-SOURCES = ["gaussian.hip", "sketch_f64.hip", "sketch_f32.hip", "sketch_bf16.hip", "pivqr.hip", "interp.hip", "residual.hip",
+SOURCES = ["gaussian.hip", "sketch_f64.hip", "sketch_f32.hip", "sketch_bf16.hip", "sketch_srft.hip", "pivqr.hip", "interp.hip", "residual.hip",
            "batched.hip", "svd.hip", "api.hip", "server.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -77,7 +77,7 @@ DecompWs carve_decomp(C &c, rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int
 }
 
 size_t bytes_decomp(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, int64_t l,
-                    int q, int qr_kind) {
+                    int q, int qr_kind, int sketch_kind = RID_SKETCH_GAUSSIAN) {
   WsCarve c(nullptr);
   carve_decomp(c, dt, pr, m, n, k, l);
   // the region after `scratch` must also hold each later step's workspace
@@ -87,8 +87,11 @@ size_t bytes_decomp(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, 
   c2.take<double>(k);
   const size_t base = (c2.off + 255) & ~size_t(255);
   size_t need = c.off;
+  const size_t srft = (sketch_kind == RID_SKETCH_SRFT && srft_fft_ok(pr, m, l))
+                          ? srft_sketch_ws_bytes(m, n, l)
+                          : 0;
   const size_t others[] = {pivqr_ws_bytes(l, n, k, qr_kind), interp_ws_bytes(n, k),
-                           residual_ws_bytes(m, n, k, q)};
+                           residual_ws_bytes(m, n, k, q), srft};
   for (size_t o : others)
     if (base + o > need) need = base + o;
   return need + 256;
@@ -193,9 +196,9 @@ rid_status rid_reserve(rid_handle h, int64_t max_m, int64_t max_n, int64_t max_l
   for (rid_prec pr : {RID_FP64, RID_FP32}) {
     const size_t sk = bytes_sketch(RID_C128, pr, max_m, max_n, max_l, true);
     const size_t d = std::max(bytes_decomp(RID_C128, pr, max_m, max_n, max_k, max_l, 1,
-                                           RID_QR_HOUSEHOLDER),
+                                           RID_QR_HOUSEHOLDER, h->sketch_kind),
                               bytes_decomp(RID_C128, pr, max_m, max_n, max_k, max_l, 1,
-                                           RID_QR_CGS2));
+                                           RID_QR_CGS2, h->sketch_kind));
     if (sk > need) need = sk;
     if (d > need) need = d;
   }
@@ -281,6 +284,13 @@ rid_status rid_sketch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_pre
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
   if (m == 0) return zero_fill(h, stream, Y, ldy, l, n);
+  if (h->sketch_kind == RID_SKETCH_SRFT && srft_fft_ok(prec, m, l)) {
+    s = ensure_ws(h, srft_sketch_ws_bytes(m, n, l));
+    if (s != RID_OK) return s;
+    const hipError_t e = launch_srft_sketch(stream, dtype, m, n, l, A, lda, seed,
+                                            static_cast<double2 *>(Y), ldy, h->ws, &h->prof);
+    return e == hipSuccess ? RID_OK : fail_hip(h, e);
+  }
   s = ensure_ws(h, bytes_sketch(dtype, prec, m, n, l, true));
   if (s != RID_OK) return s;
   WsCarve c(h->ws);
@@ -411,15 +421,23 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
   if (h->qr_kind == RID_QR_CGS2 && k > 1024) return RID_ERR_UNSUPPORTED;
-  rid_status s = ensure_ws(h, bytes_decomp(dtype, prec, m, n, k, l, q, h->qr_kind));
+  const bool fft = h->sketch_kind == RID_SKETCH_SRFT && srft_fft_ok(prec, m, l);
+  rid_status s =
+      ensure_ws(h, bytes_decomp(dtype, prec, m, n, k, l, q, h->qr_kind, h->sketch_kind));
   if (s != RID_OK) return s;
   WsCarve c(h->ws);
   const DecompWs d = carve_decomp(c, dtype, prec, m, n, k, l);
   for (int attempt = 0; attempt <= max_retries; ++attempt) {
     const uint64_t sd = seed + static_cast<uint64_t>(attempt);
-    hipError_t e = launch_operator(stream, h->sketch_kind, l, m, sd, d.G, m);
-    if (e == hipSuccess)
-      e = launch_sketch(stream, dtype, prec, m, n, l, A, lda, d.G, m, d.Y, l, d.part, &h->prof);
+    hipError_t e;
+    if (fft) {
+      e = launch_srft_sketch(stream, dtype, m, n, l, A, lda, sd, d.Y, l, d.scratch, &h->prof);
+    } else {
+      e = launch_operator(stream, h->sketch_kind, l, m, sd, d.G, m);
+      if (e == hipSuccess)
+        e = launch_sketch(stream, dtype, prec, m, n, l, A, lda, d.G, m, d.Y, l, d.part,
+                          &h->prof);
+    }
     if (e == hipSuccess)
       e = launch_pivqr(stream, l, n, k, d.Y, l, d.perm, d.gaps, rank_tol, d.scratch,
                        h->d_status, &h->prof, h->qr_kind);

@@ -24,11 +24,6 @@ __global__ __launch_bounds__(256) void gaussian_kernel(int64_t rows, int64_t col
 // D A, so G(i, p) = exp(2 pi i (phi_p - (s_i p mod m) / m)), with phi_p the
 // first uniform of Philox counter (p, 0, 0, 5) and s_i = floor(u m) for the
 // first uniform u of counter (i, 0, 0, 6) (i.i.d., with replacement).
-RID_DEV double rid_u1(uint64_t seed, uint32_t stream, uint64_t col) {
-  uint32_t c[4] = {static_cast<uint32_t>(col), static_cast<uint32_t>(col >> 32), 0u, stream};
-  rid_philox10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
-  return rid_u52(c[0], c[1]);
-}
 
 __global__ __launch_bounds__(256) void srft_kernel(int64_t rows, int64_t m, uint64_t seed,
                                                    double2 *out, int64_t ld) {

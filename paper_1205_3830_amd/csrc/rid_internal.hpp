@@ -139,6 +139,14 @@ RID_DEV double2 rid_gauss(uint64_t seed, uint32_t stream, uint32_t row, uint64_t
   return make_double2(rad * cos(ang), rad * sin(ang));
 }
 
+// The first uniform of Philox counter (col lo, col hi, 0, stream): the draws
+// of the S F D operator (phases: stream 5, rows: stream 6).
+RID_DEV double rid_u1(uint64_t seed, uint32_t stream, uint64_t col) {
+  uint32_t c[4] = {static_cast<uint32_t>(col), static_cast<uint32_t>(col >> 32), 0u, stream};
+  rid_philox10(c, static_cast<uint32_t>(seed), static_cast<uint32_t>(seed >> 32));
+  return rid_u52(c[0], c[1]);
+}
+
 // Streaming load of one complex128 that is read once per pass (non-temporal:
 // it does not displace cached data such as the vectors the pass reuses).
 typedef double rid_dv2 __attribute__((ext_vector_type(2)));
@@ -356,6 +364,14 @@ hipError_t launch_srft(hipStream_t st, int64_t rows, int64_t m, uint64_t seed, d
 // The sketch operator of the handle's kind (rows = l, cols = m).
 hipError_t launch_operator(hipStream_t st, int kind, int64_t rows, int64_t cols, uint64_t seed,
                            double2 *out, int64_t ld);
+
+// Y = S F D A through the four-step DFT (FP64 products; m a multiple of 8,
+// l <= 2048): draws as launch_srft's, ws of srft_sketch_ws_bytes bytes.
+bool srft_fft_ok(rid_prec prec, int64_t m, int64_t l);
+size_t srft_sketch_ws_bytes(int64_t m, int64_t n, int64_t l);
+hipError_t launch_srft_sketch(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t l,
+                              const void *A, int64_t lda, uint64_t seed, double2 *Y, int64_t ldy,
+                              void *ws, RidProf *prof);
 
 // Y (complex128) = G A, G complex128 row-major (l x m, ldg), A column-major
 // (m x n, lda) of storage type `dtype`, products in precision `prec`.

@@ -311,6 +311,49 @@ def test_decompose_with_srft_matches_oracle(h):
     assert abs(s - r["sigma"]) <= tol
 
 
+SRFT_SKETCH_CASES = [
+    # m, n, l, seed, storage; m % 8 == 0 takes the four-step DFT, else the explicit operator
+    (4096, 300, 108, 7, np.complex128),
+    (1048, 129, 30, 2, np.complex128),    # ragged n, m2 = 131
+    (8, 3, 5, 1, np.complex128),          # m2 = 1
+    (2000, 100, 30, 4, np.complex64),     # complex64 storage, FP64 products
+    (1600, 64, 250, 5, np.complex128),    # large l: about 31 rows per residue group
+    (512, 40, 1, 6, np.complex128),       # one row, one group
+    (1001, 50, 20, 3, np.complex128),     # m not a multiple of 8: explicit operator
+]
+
+
+@pytest.mark.parametrize("m,n,l,seed,dt", SRFT_SKETCH_CASES)
+def test_srft_sketch_matches_oracle(h, m, n, l, seed, dt):
+    A = _lowrank(m, n, min(8, n), 1e-6, seed=m + n).astype(dt)
+    ref = oracle.sketch(A.astype(np.complex128), oracle.srft_operator(l, m, seed))
+    rid.rid_set_sketch(h, rid.RID_SKETCH_SRFT)
+    try:
+        Y = host(rid.rid_sketch(h, dev(A), l, seed))
+    finally:
+        rid.rid_set_sketch(h, rid.RID_SKETCH_GAUSSIAN)
+    assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_srft_sketch_column_blocks_match_numpy_fft(h):
+    # 2^21 rows: the four-step form's Z buffer (2 GiB) holds 64 columns, so
+    # 150 columns take three blocks.  Sampled columns against numpy's FFT of
+    # D A(:, j), sampled at the rows s_i (eqs. (4)-(7)).
+    m, n, l, seed = 1 << 21, 150, 40, 9
+    Ad = synth.lowrank_device(m, n, 6, 1e-6, seed=3).t()
+    rid.rid_set_sketch(h, rid.RID_SKETCH_SRFT)
+    try:
+        Y = host(rid.rid_sketch(h, Ad, l, seed))
+    finally:
+        rid.rid_set_sketch(h, rid.RID_SKETCH_GAUSSIAN)
+    s = oracle.srft_rows(l, m, seed)
+    d = np.exp(2j * np.pi * oracle.srft_phases(m, seed))
+    for j in [0, 63, 64, 127, 128, 149]:
+        col = Ad[:, j].cpu().numpy()
+        ref = np.fft.fft(d * col)[s]
+        assert np.linalg.norm(Y[:, j] - ref) <= 1e-12 * np.linalg.norm(ref), j
+
+
 # ------------------------------------------------------------------ QR method: CGS2 (Sec. 3.2)
 @pytest.fixture
 def h_cgs2(h):
