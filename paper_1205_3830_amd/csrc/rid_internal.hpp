@@ -368,6 +368,15 @@ hipError_t launch_operator(hipStream_t st, int kind, int64_t rows, int64_t cols,
 // Y = S F D A through the four-step DFT (FP64 products; m a multiple of 8,
 // l <= 2048): draws as launch_srft's, ws of srft_sketch_ws_bytes bytes.
 bool srft_fft_ok(rid_prec prec, int64_t m, int64_t l);
+// Its block-diagonal product (sketch_f64.hip): off[0..8] are the row offsets
+// of the 8 residue groups in the grouped order (off[8] = l); Z holds the 8
+// planes Z_t (m2 x nb each), T the grouped twiddle rows (l x m2); the result
+// goes to Y(perm_i[r], j0 + j), rows back in draw order.
+size_t srft_gemm_ws_bytes(int64_t m2, int64_t nb, int64_t l);  // any grouping of l rows
+hipError_t launch_srft_gemm(hipStream_t st, int64_t m2, int64_t nb, int64_t j0,
+                            const int64_t *off, const double2 *Z, const double2 *T,
+                            const int64_t *perm_i, double2 *Y, int64_t ldy, void *part,
+                            RidProf *prof);
 size_t srft_sketch_ws_bytes(int64_t m, int64_t n, int64_t l);
 hipError_t launch_srft_sketch(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t l,
                               const void *A, int64_t lda, uint64_t seed, double2 *Y, int64_t ldy,

@@ -321,9 +321,133 @@ hipError_t launch_sketch_batch_f64(hipStream_t st, rid_dtype dtype, const Sketch
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- S F D groups
+namespace {
+
+// The block-diagonal product of the four-step S F D sketch: for each residue
+// group t < 8 with rows off[t] .. off[t+1]-1 of the grouped order,
+//   part_t = T_t Z_t,  T_t = T(off[t] .., :) (l_t x m2, row-major, ld m2),
+//   Z_t = Z + t m2 nb (m2 x nb, ld m2),
+// split over K like one sketch; grid z runs over (group, row slice).  The
+// reduce then writes Y(perm_i[r], j0 + j) = sum of the splits, so the rows
+// come back in draw order.
+struct SrftGemmPlan {
+  int MT, nbz, S;
+  int64_t nbx, pchunk, lmax;
+};
+
+// lmax: the largest group.  The splits S only grow as lmax shrinks (fewer
+// row slices), so lmax = 1 bounds the partials of any grouping.
+SrftGemmPlan plan_srft_gemm(int64_t m2, int64_t nb, int64_t lmax) {
+  SrftGemmPlan p;
+  p.lmax = lmax < 1 ? 1 : lmax;
+  const int64_t tiles = (2 * p.lmax + 15) / 16;
+  p.MT = pick_mt(tiles);
+  p.nbz = static_cast<int>((tiles + p.MT - 1) / p.MT);
+  p.nbx = (nb + 63) / 64;
+  const int64_t base = p.nbx * p.nbz * 8;
+  int64_t S = (4096 + base - 1) / base;
+  const int64_t maxS = (m2 + 255) / 256;
+  if (S > maxS) S = maxS;
+  if (S < 1) S = 1;
+  int64_t pchunk = (m2 + S - 1) / S;
+  pchunk = (pchunk + 15) / 16 * 16;
+  if (pchunk < 16) pchunk = 16;
+  if ((m2 + pchunk - 1) / pchunk > 65535) pchunk = ((m2 + 65534) / 65535 + 15) / 16 * 16;
+  p.S = static_cast<int>((m2 + pchunk - 1) / pchunk);
+  p.pchunk = pchunk;
+  return p;
+}
+
+struct SrftOff {
+  int64_t off[9];
+};
+
+template <int MT>
+__global__ __launch_bounds__(256) void srft_group_gemm_kernel(
+    int64_t m2, int64_t nb, SrftOff g, int nbz, int64_t pchunk, int S,
+    const double2 *__restrict__ Z, const double2 *__restrict__ T, double *__restrict__ part) {
+  const int t = blockIdx.z / nbz, bz = blockIdx.z % nbz;
+  const int64_t lt = g.off[t + 1] - g.off[t];
+  if (lt == 0 || int64_t(bz) * 8 * MT >= lt) return;  // uniform over the workgroup
+  double *pt = part + int64_t(S) * 2 * nb * g.off[t];
+  sketch_f64_body<MT, double2>(m2, nb, lt, Z + int64_t(t) * m2 * nb, m2, T + g.off[t] * m2, m2,
+                               pt, 2 * lt, 2 * lt * nb, pchunk, blockIdx.x, blockIdx.y, bz);
+}
+
+__global__ __launch_bounds__(256) void srft_group_reduce_kernel(
+    int64_t l, int64_t nb, int64_t j0, SrftOff g, int S, const double *__restrict__ part,
+    const int64_t *__restrict__ perm_i, double2 *__restrict__ Y, int64_t ldy) {
+  const int64_t total = l * nb;
+  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
+       e += int64_t(gridDim.x) * blockDim.x) {
+    const int64_t j = e / l, rg = e - j * l;  // grouped row rg of column j
+    int t = 0;
+    while (t < 7 && rg >= g.off[t + 1]) ++t;
+    const int64_t lt = g.off[t + 1] - g.off[t], r = rg - g.off[t];
+    const double *pt = part + int64_t(S) * 2 * nb * g.off[t] + j * 2 * lt + 2 * r;
+    const int64_t stride = 2 * lt * nb;
+    double re = 0.0, im = 0.0;
+    for (int sp = 0; sp < S; ++sp) {
+      re += pt[sp * stride];
+      im += pt[sp * stride + 1];
+    }
+    const int64_t i = perm_i[rg];
+    if (i >= 0 && i < l) Y[(j0 + j) * ldy + i] = make_double2(re, im);
+  }
+}
+
+}  // namespace
+
 template hipError_t launch_sketch_f64<double2>(hipStream_t, int64_t, int64_t, int64_t,
                                                const double2 *, int64_t, const double2 *,
                                                int64_t, double2 *, int64_t, void *, RidProf *);
 template hipError_t launch_sketch_f64<float2>(hipStream_t, int64_t, int64_t, int64_t,
                                               const float2 *, int64_t, const double2 *, int64_t,
                                               double2 *, int64_t, void *, RidProf *);
+
+size_t srft_gemm_ws_bytes(int64_t m2, int64_t nb, int64_t l) {
+  const SrftGemmPlan p = plan_srft_gemm(m2, nb, 1);
+  return size_t(p.S) * 2 * size_t(nb) * size_t(l) * sizeof(double);
+}
+
+hipError_t launch_srft_gemm(hipStream_t st, int64_t m2, int64_t nb, int64_t j0,
+                            const int64_t *off, const double2 *Z, const double2 *T,
+                            const int64_t *perm_i, double2 *Y, int64_t ldy, void *partv,
+                            RidProf *prof) {
+  int64_t lmax = 0;
+  for (int t = 0; t < 8; ++t) lmax = std::max(lmax, off[t + 1] - off[t]);
+  const SrftGemmPlan p = plan_srft_gemm(m2, nb, lmax);
+  SrftOff g;
+  for (int t = 0; t < 9; ++t) g.off[t] = off[t];
+  double *part = static_cast<double *>(partv);
+  const dim3 grid(static_cast<unsigned>(p.nbx), static_cast<unsigned>(p.S),
+                  static_cast<unsigned>(8 * p.nbz));
+  {
+    ProfScope ps(prof, st, RID_KERNEL_SKETCH);
+    switch (p.MT) {
+#define RID_MT_CASE(X)                                                                         \
+  case X:                                                                                      \
+    hipLaunchKernelGGL((srft_group_gemm_kernel<X>), grid, dim3(256), 0, st, m2, nb, g, p.nbz,  \
+                       p.pchunk, p.S, Z, T, part);                                             \
+    break;
+      RID_MT_CASE(1) RID_MT_CASE(2) RID_MT_CASE(3) RID_MT_CASE(4) RID_MT_CASE(5)
+      RID_MT_CASE(6) RID_MT_CASE(7) RID_MT_CASE(8) RID_MT_CASE(9) RID_MT_CASE(10)
+      RID_MT_CASE(11) RID_MT_CASE(12) RID_MT_CASE(13) RID_MT_CASE(14) RID_MT_CASE(15)
+      RID_MT_CASE(16) RID_MT_CASE(18) RID_MT_CASE(20) RID_MT_CASE(22) RID_MT_CASE(24)
+      RID_MT_CASE(26) RID_MT_CASE(28)
+#undef RID_MT_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+    ps.stop();
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t total = off[8] * nb;
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(srft_group_reduce_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0,
+                     st, off[8], nb, j0, g, p.S, part, perm_i, Y, ldy);
+  return hipGetLastError();
+}

@@ -8,7 +8,7 @@
 // The 8-point DFTs (pass 1) read A once and write Z; the outer sums are one
 // GEMM per residue t, K = m2, on the FP64 matrix cores (the sketch kernel
 // with the twiddles T_t(r, p2) = e^{-2 pi i s p2 / m} of the rows r of group
-// t as its operator).  That is 8 l m2 + O(m) complex multiply-adds per
+// t as its operator), all eight in one launch.  That is 8 l m2 + O(m) complex multiply-adds per
 // column instead of l m.  The draws are those of the explicit operator:
 // d_p = e^{2 pi i phi_p}, phi_p the first uniform of Philox counter
 // (p, 0, 0, 5), s_i = floor(u m) for the first uniform u of (i, 0, 0, 6).
@@ -167,23 +167,9 @@ __global__ __launch_bounds__(256) void srft_dft8_kernel(int64_t m2, int64_t nb, 
   }
 }
 
-// Y(perm_i[r], j) = Yg(r, j): the grouped rows back in draw order.
-__global__ __launch_bounds__(256) void srft_unperm_kernel(int64_t l, int64_t n,
-                                                          const int64_t *__restrict__ perm_i,
-                                                          const double2 *__restrict__ Yg,
-                                                          double2 *__restrict__ Y, int64_t ldy) {
-  const int64_t total = l * n;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * blockDim.x) {
-    const int64_t j = e / l, r = e - j * l;
-    const int64_t i = perm_i[r];
-    if (i >= 0 && i < l) Y[j * ldy + i] = Yg[e];
-  }
-}
-
 struct SrftWs {
   int64_t *perm_i, *perm_s;
-  double2 *d, *T, *Yg, *Z;
+  double2 *d, *T, *Z;
   void *part;
   int64_t nb;  // columns per block of Z
 };
@@ -205,13 +191,8 @@ SrftWs carve_srft(C &c, int64_t m, int64_t n, int64_t l) {
   w.perm_s = c.template take<int64_t>(size_t(l));
   w.d = c.template take<double2>(size_t(m));
   w.T = c.template take<double2>(size_t(l) * size_t(m2));
-  w.Yg = c.template take<double2>(size_t(l) * size_t(n));
   w.Z = c.template take<double2>(size_t(m) * size_t(w.nb));
-  // the split-K partials of any group size (a group holds 1 .. l rows)
-  size_t part = 0;
-  for (int64_t r = 1; r <= l; ++r)
-    part = std::max(part, sketch_ws_bytes(RID_C128, RID_FP64, m2, w.nb, r));
-  w.part = c.template take<char>(part);
+  w.part = c.template take<char>(srft_gemm_ws_bytes(m2, w.nb, l));
   return w;
 }
 
@@ -259,17 +240,8 @@ hipError_t launch_srft_sketch(hipStream_t st, rid_dtype dtype, int64_t m, int64_
       hipLaunchKernelGGL(srft_dft8_kernel<double2>, grid, dim3(256), 0, st, m2, nb, j0,
                          static_cast<const double2 *>(A), lda, w.d, w.Z);
     e = hipGetLastError();
-    for (int t = 0; t < R1 && e == hipSuccess; ++t) {
-      const int64_t rows = g.off[t + 1] - g.off[t];
-      if (rows == 0) continue;
-      e = launch_sketch(st, RID_C128, RID_FP64, m2, nb, rows, w.Z + t * m2 * nb, m2,
-                        w.T + g.off[t] * m2, m2, w.Yg + g.off[t] + j0 * l, l, w.part, prof);
-    }
-  }
-  if (e == hipSuccess) {
-    hipLaunchKernelGGL(srft_unperm_kernel, dim3(grid_1d(l * n)), dim3(256), 0, st, l, n,
-                       w.perm_i, w.Yg, Y, ldy);
-    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = launch_srft_gemm(st, m2, nb, j0, g.off, w.Z, w.T, w.perm_i, Y, ldy, w.part, prof);
   }
   return e;
 }
