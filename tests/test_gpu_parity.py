@@ -335,6 +335,27 @@ def test_srft_sketch_matches_oracle(h, m, n, l, seed, dt):
     assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
+@pytest.mark.parametrize("form", ["fused", "two_pass"])
+@pytest.mark.parametrize("m,n,l,seed", [(4096, 300, 108, 7), (2048, 70, 30, 11),
+                                         (1024, 65, 400, 12)])
+def test_srft_sketch_forms_match_oracle(h, monkeypatch, form, m, n, l, seed):
+    # The one-pass (fused) and two-pass four-step forms on the same input.
+    # With l = 400 the residue groups exceed 32 rows, so both runs take the
+    # two-pass form.
+    if form == "two_pass":
+        monkeypatch.setenv("RID_SRFT_TWO_PASS", "1")
+    else:
+        monkeypatch.delenv("RID_SRFT_TWO_PASS", raising=False)
+    A = _lowrank(m, n, 8, 1e-6, seed=m + l)
+    ref = oracle.sketch(A, oracle.srft_operator(l, m, seed))
+    rid.rid_set_sketch(h, rid.RID_SKETCH_SRFT)
+    try:
+        Y = host(rid.rid_sketch(h, dev(A), l, seed))
+    finally:
+        rid.rid_set_sketch(h, rid.RID_SKETCH_GAUSSIAN)
+    assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
 def test_srft_sketch_column_blocks_match_numpy_fft(h):
     # 2^21 rows: the four-step form's Z buffer (2 GiB) holds 64 columns, so
     # 150 columns take three blocks.  Sampled columns against numpy's FFT of
