@@ -340,6 +340,10 @@ __global__ __launch_bounds__(256) void srft_fused_kernel(int64_t m2, int64_t n,
   load_g(pbeg);
   store_g(0);
   load_a(pbeg, va);
+  // Wait for the first step's loads here: loads still pending into va when
+  // the loop starts would make every iteration wait for all outstanding
+  // loads -- the next step's prefetch included -- before its first use of va.
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int b = 0;
   for (int64_t p0 = pbeg; p0 < pend; p0 += KS) {
