@@ -171,6 +171,17 @@ RID_DEV void ld_stream_pair(const float2 *p, double2 &a, double2 &b) {
   b = make_double2(static_cast<double>(v.z), static_cast<double>(v.w));
 }
 
+template <class T>
+RID_DEV T zero_of();
+template <>
+RID_DEV double2 zero_of<double2>() {
+  return make_double2(0.0, 0.0);
+}
+template <>
+RID_DEV float2 zero_of<float2>() {
+  return make_float2(0.0f, 0.0f);
+}
+
 RID_DEV double2 to_d2(double2 v) { return v; }
 RID_DEV double2 to_d2(float2 v) {
   return make_double2(static_cast<double>(v.x), static_cast<double>(v.y));

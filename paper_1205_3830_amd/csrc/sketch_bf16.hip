@@ -72,14 +72,22 @@ __global__ __launch_bounds__(256) void bf16_split_kernel(int64_t l, int64_t m, i
   }
 }
 
+// The lane's four entries of A in their stored type (converted later, by
+// to_floats: converting right after the load would make the wave wait for
+// the load there, serialising the prefetch with the step's products).
 template <class TA>
-RID_DEV void load_a(const TA *Acol, int64_t pb, int64_t pend, bool ok, float (&v)[8]) {
+RID_DEV void load_a(const TA *Acol, int64_t pb, int64_t pend, bool ok, TA (&v)[4]) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) v[u] = (ok && pb + u < pend) ? Acol[pb + u] : zero_of<TA>();
+}
+
+template <class TA>
+RID_DEV void to_floats(const TA (&a)[4], float (&v)[8]) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
-    double2 a = make_double2(0.0, 0.0);
-    if (ok && pb + u < pend) a = to_d2(Acol[pb + u]);
-    v[2 * u] = static_cast<float>(a.x);
-    v[2 * u + 1] = static_cast<float>(a.y);
+    const double2 d = to_d2(a[u]);
+    v[2 * u] = static_cast<float>(d.x);
+    v[2 * u + 1] = static_cast<float>(d.y);
   }
 }
 
@@ -163,10 +171,17 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
     }
   };
 
-  float av[2][8], an[2][8];
+  float av[2][8];
+  TA an[2][4];
   load_slab(pbeg);
 #pragma unroll
-  for (int g = 0; g < 2; ++g) load_a(Acol[g], pbeg + 4 * q, pend, ok[g], av[g]);
+  for (int g = 0; g < 2; ++g) {
+    load_a(Acol[g], pbeg + 4 * q, pend, ok[g], an[g]);
+    to_floats(an[g], av[g]);
+  }
+  // nothing may be pending into av when the loop starts (it would make every
+  // step wait for its own prefetch before the first product)
+  __builtin_amdgcn_s_waitcnt(0);
   for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
     const bool more = p0 + 16 < pend;
     __syncthreads();  // the previous step has finished reading the slab
@@ -212,9 +227,7 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
     }
     if (more) {
 #pragma unroll
-      for (int g = 0; g < 2; ++g)
-#pragma unroll
-        for (int e = 0; e < 8; ++e) av[g][e] = an[g][e];
+      for (int g = 0; g < 2; ++g) to_floats(an[g], av[g]);
     }
   }
   const int64_t rows = 2 * l;

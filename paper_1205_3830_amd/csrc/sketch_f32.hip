@@ -44,40 +44,48 @@ RID_DEV void sketch_f32_body(
   for (int t = 0; t < MT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
   const TA *Acol = A + (colok ? jcol : 0) * lda;
-  float2 stg[PER];
+  // Prefetched values stay in their stored type until the end of the step:
+  // converting right after a load would make the wave wait for that load
+  // there, serialising the prefetch with the step's products.
+  double2 stg[PER];
   auto load_g = [&](int64_t p0) {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const int e = tid + 256 * r;
       const int row = e >> 4, col = e & 15;
       const int64_t i = g0 + row, p = p0 + col;
-      stg[r] = (e < NR * 16 && i < l && p < pend) ? to_f2(G[i * ldg + p])
-                                                  : make_float2(0.0f, 0.0f);
+      stg[r] = (e < NR * 16 && i < l && p < pend) ? G[i * ldg + p] : make_double2(0.0, 0.0);
     }
   };
   auto store_g = [&](int b) {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const int e = tid + 256 * r;
-      if (e < NR * 16) gs[b][(e >> 4) * RS + (e & 15)] = stg[r];
+      if (e < NR * 16) gs[b][(e >> 4) * RS + (e & 15)] = to_f2(stg[r]);
     }
   };
-  auto load_a = [&](int64_t p0, float2 *a4) {
+  auto load_a = [&](int64_t p0, TA *raw) {
     const int64_t pb = p0 + 4 * q;
     if (colok && pb + 4 <= pend) {
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a4[u] = to_f2(Acol[pb + u]);
+      for (int u = 0; u < 4; ++u) raw[u] = Acol[pb + u];
     } else {
 #pragma unroll
       for (int u = 0; u < 4; ++u)
-        a4[u] = (colok && pb + u < pend) ? to_f2(Acol[pb + u]) : make_float2(0.0f, 0.0f);
+        raw[u] = (colok && pb + u < pend) ? Acol[pb + u] : zero_of<TA>();
     }
   };
 
-  float2 a4[4], an[4];
+  float2 a4[4];
+  TA an[4];
   load_g(pbeg);
   store_g(0);
-  load_a(pbeg, a4);
+  load_a(pbeg, an);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) a4[u] = to_f2(an[u]);
+  // nothing may be pending into a4 when the loop starts (it would make every
+  // step wait for its own prefetch before the first product)
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int b = 0;
   for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
@@ -104,7 +112,7 @@ RID_DEV void sketch_f32_body(
     if (more) {
       store_g(b ^ 1);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a4[u] = an[u];
+      for (int u = 0; u < 4; ++u) a4[u] = to_f2(an[u]);
     }
     __syncthreads();
     b ^= 1;

@@ -85,6 +85,10 @@ RID_DEV void sketch_f64_body(
   load_g(pbeg);
   store_g(0);
   load_a(pbeg, a4);
+  // Wait for the first step's loads here: loads still pending into a4 when
+  // the loop starts would make every iteration wait for all outstanding
+  // loads -- the next step's prefetch included -- before its first MFMA.
+  __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int b = 0;
   for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
