@@ -414,14 +414,24 @@ RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
     dot2_acc(si[u], ci[u], -a.y, zz.x);
   };
   if (!C64) {
+    // software pipelined: the next row's entries are loaded before the
+    // current row's products, and nothing is pending into `a` at loop entry
+    double2 a[AHZ_CPW], an[AHZ_CPW];
+#pragma unroll
+    for (int u = 0; u < AHZ_CPW; ++u)
+      a[u] = (cok[u] && lane < rows) ? ld_stream(cp[u] + lane) : make_double2(0.0, 0.0);
+    __builtin_amdgcn_s_waitcnt(0);
     for (int i = lane; i < rows; i += 64) {
-      const double2 zz = zs[i];
-      double2 a[AHZ_CPW];
+      const int in = i + 64;
+      const bool more = in < rows;
 #pragma unroll
       for (int u = 0; u < AHZ_CPW; ++u)
-        a[u] = cok[u] ? ld_stream(cp[u] + i) : make_double2(0.0, 0.0);
+        an[u] = (cok[u] && more) ? ld_stream(cp[u] + in) : make_double2(0.0, 0.0);
+      const double2 zz = zs[i];
 #pragma unroll
       for (int u = 0; u < AHZ_CPW; ++u) acc(u, a[u], zz);
+#pragma unroll
+      for (int u = 0; u < AHZ_CPW; ++u) a[u] = an[u];
     }
   } else {
     for (int i = 2 * lane; i < rows; i += 128) {
