@@ -341,6 +341,8 @@ def bench_sweep(args, torch, rid, synth) -> int:
     idx = range(len(TABLE1)) if args.shapes == "all" else [int(x) for x in args.shapes.split(",")]
     q = args.q
     h = rid.rid_create(0)
+    if args.sketch == "srft":
+        rid.rid_set_sketch(h, rid.RID_SKETCH_SRFT)
     rows = []
     for i in idx:
         k, m, n, paper_s, paper_err = TABLE1[i]
@@ -384,7 +386,8 @@ def bench_sweep(args, torch, rid, synth) -> int:
         "value": None, "unit": "GB/s", "n_gpus": 1, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
         "config": {"workload": "the paper's Table 1 shapes, A = B P with complex Gaussian "
-                               "B (m x k) and P (k x n), no noise, l = 2k, q=%d" % q},
+                               "B (m x k) and P (k x n), no noise, l = 2k, q=%d, %s operator"
+                               % (q, "S F D" if args.sketch == "srft" else "Gaussian")},
         "rows": rows,
     }
     print(json.dumps(out))
