@@ -490,6 +490,9 @@ def main() -> int:
     ap.add_argument("--sketch", choices=["gaussian", "srft"], default="gaussian",
                     help="random operator: Gaussian G, or the paper's S F D (four-step DFT "
                          "form when m is a multiple of 8)")
+    ap.add_argument("--compare-fp64", action="store_true",
+                    help="with --prec fp32/bf16x3: also run the FP64-products ID on the same A "
+                         "(same seed) and report J agreement and the P and sigma differences")
     ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--form", choices=["single", "batched", "serving", "sweep", "qr", "svd"],
@@ -629,6 +632,19 @@ def main() -> int:
 
     J_h = J.cpu()
     ok = bool((P[:, J_h].cpu() == torch.eye(k, dtype=torch.complex128)).all())
+    vs64 = None
+    if args.compare_fp64 and args.prec != "fp64":
+        # the FP64-products path on the same A and seed; it is held to 1e-10
+        # of the FP64 oracle, which cannot itself run at this size
+        J64, P64, s64, _ = rid.rid_decompose(h, A, k, l, seed=0, q=q, prec=rid.RID_FP64)
+        torch.cuda.synchronize()
+        j_lo, j_hi = J_h.tolist(), J64.cpu().tolist()
+        lead = next((t for t in range(k) if j_lo[t] != j_hi[t]), k)
+        pmax = float(P64.abs().max())
+        s_lo, s_hi = float(sigma.cpu()[0]), float(s64.cpu()[0])
+        vs64 = {"J_leading_match": lead, "J_same_set": sorted(j_lo) == sorted(j_hi),
+                "P_max_abs_diff_rel": float((P - P64).abs().max()) / max(1.0, pmax),
+                "sigma": s_lo, "sigma_fp64": s_hi, "sigma_rel_diff": abs(s_lo - s_hi) / s_hi}
 
     out = {
         "metric": "A GB/s streamed & IDs/sec at <=1e-10 rel err; p50/p99 latency vs plain FP64",
@@ -660,6 +676,8 @@ def main() -> int:
         "sigma": float(sigma.cpu()[0]),
         "identity_on_J": ok,
     }
+    if vs64 is not None:
+        out["vs_fp64_path"] = vs64
     if (not args.no_cpu_baseline and args.cpu_cols > 0 and args.dtype == "c128"
             and args.sketch == "gaussian"):
         print("timing the CPU oracle on a column sample", file=sys.stderr, flush=True)

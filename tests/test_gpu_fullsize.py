@@ -1,6 +1,7 @@
-"""Parity at the full benchmark size, in the launch configuration bench.py
-times: A = X W + 1e-12 N, complex128, m = 131072, n = 16384, k = 100,
-l = 108, q = 10 (34.4 GB on the device).
+"""Parity at the full benchmark sizes, in the launch configuration bench.py
+times: A = X W + 1e-12 N, complex128, q = 10, at m = 131072, n = 16384,
+k = 100, l = 108 (34.4 GB on the device) and at the square case
+m = n = 32768, k = 200, l = 208 (17.2 GB).
 
 The oracle cannot redo a 34 GB ID in seconds, so this checks
   * sampled columns of Y against the oracle, one column at a time;
@@ -24,13 +25,17 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 rid = pytest.importorskip("paper_1205_3830_amd")
 
-M, N, K, L, Q, NOISE = 131072, 16384, 100, 108, 10, 1e-12
+Q, NOISE = 10, 1e-12
+# the two shapes of the large workload: 131072 x 16384, k = 100, l = 108, and
+# the square case 32768 x 32768, k = 200, l = 208
+SHAPES = [(131072, 16384, 100, 108), (32768, 32768, 200, 208)]
 
 
-@pytest.fixture(scope="module")
-def big():
+@pytest.fixture(scope="module", params=SHAPES, ids=["131072x16384", "32768x32768"])
+def big(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    M, N, K, L = request.param
     free, _ = torch.cuda.mem_get_info()
     if free < 60e9:
         pytest.skip("needs ~40 GB of free device memory")
@@ -42,7 +47,8 @@ def big():
     sig, hist = rid.rid_residual(h, A, J, P, Q, used)
     torch.cuda.synchronize()
     out = dict(A=A, h=h, J=J.cpu().numpy(), P=P.cpu().numpy(), sigma=float(sigma.cpu()[0]),
-               Y=Y.cpu().numpy(), hist=hist.cpu().numpy(), sigma2=float(sig.cpu()[0]), seed=used)
+               Y=Y.cpu().numpy(), hist=hist.cpu().numpy(), sigma2=float(sig.cpu()[0]), seed=used,
+               shape=(M, N, K, L))
     yield out
     rid.rid_destroy(h)
     del out["A"]
@@ -50,7 +56,8 @@ def big():
 
 
 def test_fullsize_sampled_sketch_columns(big):
-    cols = [0, 1, 63, 64, 8191, 16383]
+    M, N, K, L = big["shape"]
+    cols = [0, 1, 63, 64, 8191, N - 1]
     Ah = big["A"][:, cols].t().contiguous().cpu().numpy().T
     ref = oracle.sketch_seeded_columns(Ah, L, big["seed"])
     Y = big["Y"][:, cols]
@@ -59,6 +66,7 @@ def test_fullsize_sampled_sketch_columns(big):
 
 
 def test_fullsize_pivots_are_greedy(big):
+    M, N, K, L = big["shape"]
     Y = big["Y"].astype(np.complex128)
     J = big["J"]
     R = Y.copy()
@@ -79,6 +87,7 @@ def test_fullsize_pivots_are_greedy(big):
 
 
 def test_fullsize_interpolation_matrix(big):
+    M, N, K, L = big["shape"]
     P, J, Y = big["P"], big["J"], big["Y"]
     assert np.array_equal(P[:, J], np.eye(K))
     assert np.abs(P).max() <= 2.0
@@ -94,6 +103,7 @@ def test_fullsize_interpolation_matrix(big):
 
 
 def test_fullsize_residual(big):
+    M, N, K, L = big["shape"]
     s, hist = big["sigma"], big["hist"]
     assert s == big["sigma2"]                              # decompose == residual call
     assert np.all(np.diff(hist) >= -1e-12 * hist[-1])      # power steps do not decrease
@@ -112,6 +122,7 @@ def test_fullsize_residual(big):
 
 
 def test_fullsize_svd_on_the_id(big):
+    M, N, K, L = big["shape"]
     # The SVD built on the ID at full size, by properties that hold at any
     # size: orthonormal U and V, descending S, U S V^H = A(:,J) P on sampled
     # columns, and, on sampled rows, A V - U S = E V with E = A - A(:,J) P,
@@ -126,10 +137,10 @@ def test_fullsize_svd_on_the_id(big):
     assert np.abs(U.conj().T @ U - np.eye(K)).max() <= 1e-11
     assert np.abs(V.conj().T @ V - np.eye(K)).max() <= 1e-11
     AJ = A[:, J.tolist()].t().contiguous().cpu().numpy().T
-    for c in [0, 1, 4097, 16383] + [int(J[0]), int(J[-1])]:
+    for c in [0, 1, 4097, N - 1] + [int(J[0]), int(J[-1])]:
         rec = (U * S) @ V[c].conj()
         assert np.abs(rec - AJ @ P[:, c]).max() <= 1e-11 * s0, c
-    rows = [0, 5, 65536, M - 1]
+    rows = [0, 5, M // 2, M - 1]
     Ar = A[rows, :].cpu().numpy()
     for i, r in enumerate(rows):
         assert np.linalg.norm(Ar[i] @ V - U[r] * S) <= 4 * big["sigma"] + 1e-11 * s0, r
