@@ -63,12 +63,12 @@ def test_gaussian_matches_oracle(h, rows, cols, seed, sid):
 SKETCH_CASES = [
     (1000, 500, 30),   # 1000 x 500 parity workload, l = k + 10
     (1037, 131, 30),   # ragged m, n
-    (257, 70, 108),    # l of the large workload (14 row tiles)
+    (257, 70, 108),    # l of the large workload (7 row tiles of Y)
     (64, 64, 1),
     (5, 3, 2),
     (1, 1, 1),
-    (600, 97, 208),    # l of the square workload (26 -> 28 tiles)
-    (300, 65, 250),    # 32 tiles: split along the rows of Y
+    (600, 97, 208),    # l of the square workload (13 row tiles)
+    (300, 65, 250),    # 16 row tiles: split along the rows of Y (two z-slices)
     (4096, 40, 16),    # several K splits
 ]
 
@@ -79,6 +79,24 @@ def test_sketch_explicit_matches_oracle(h, m, n, l):
     G = oracle.sketch_operator(l, m, seed=1)
     Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda()))
     ref = oracle.sketch(A, G)
+    assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+# Every row tiling of the FP64 sketch (1 to 14 tiles of 16 rows of Y, each
+# full and ragged, then z-slices of 8 tiles beyond 224 rows), with complex128
+# and complex64 storage; the grid spans two column blocks with a ragged tail
+# and several K splits with a ragged last step.
+SKETCH_TILING_LS = sorted({16 * r - d for r in range(1, 15) for d in (0, 7)} | {225, 300, 401})
+
+
+@pytest.mark.parametrize("dt", [np.complex128, np.complex64])
+@pytest.mark.parametrize("l", SKETCH_TILING_LS)
+def test_sketch_every_row_tiling_matches_oracle(h, l, dt):
+    m, n = 1100, 77
+    A = _lowrank(m, n, 6, 1e-6, seed=l).astype(dt)
+    G = oracle.sketch_operator(l, m, seed=l + 1)
+    Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda()))
+    ref = oracle.sketch(A.astype(np.complex128), G)
     assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
