@@ -5,12 +5,15 @@
 // the triangular solve and the residual that follow stay in double.
 //
 // Same real embedding and tiling as the double-precision kernel
-// (sketch_f64.hip): a workgroup of 4 waves owns 64 columns of A and MT
-// 16-row tiles of Yr; lane (r16, q) holds four consecutive complex entries
-// of its column for each 16-row K step and k-slot q of MFMA s stands for
-// real row 8q + s.  G (complex128 in memory) is rounded to complex64 as it
-// is staged into LDS, double buffered, row stride 17 entries.  The FP32 MFMA
-// output layout differs from the FP64 one: lane l, register r holds row
+// (sketch_f64.hip): [Yr Yi] = [Gr Gi] Ae with the 2x2 blocks [[Re a, Im a],
+// [-Im a, Re a]] of Ae built per lane from the A entries it loaded, once per
+// K step; a workgroup of 8 waves owns 64 columns of A and RT 16-row tiles of
+// Y, each wave 8 of the columns (real column r16 of a tile is part r16 & 1 of
+// complex column r16 >> 1); lane (r16, q) holds four consecutive complex
+// entries of its column for each 16-row K step and k-slot q of MFMA s stands
+// for k-index 8q + s.  G (complex128 in memory) is rounded to complex64 as
+// it is staged into LDS, double buffered, row stride 17 entries.  The FP32
+// MFMA output layout differs from the FP64 one: lane l, register r holds row
 // 4 (l / 16) + r, column l % 16 (measured on gfx950).
 #include "rid_internal.hpp"
 
@@ -18,30 +21,31 @@ namespace {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-template <int MT, class TA>
+template <int RT, class TA>
 RID_DEV void sketch_f32_body(
     int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
     const double2 *__restrict__ G, int64_t ldg, float *__restrict__ out, int64_t ldo,
     int64_t split_stride, int64_t pchunk, int64_t bx, int64_t by, int64_t bz) {
-  constexpr int NR = 8 * MT;
+  constexpr int NT = 512;
+  constexpr int NR = 16 * RT;
   constexpr int RS = 17;
-  constexpr int PER = (NR * 16 + 255) / 256;
+  constexpr int PER = (NR * 16 + NT - 1) / NT;
   __shared__ float2 gs[2][NR * RS];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int q = lane >> 4;
   const int r16 = lane & 15;
-  const int c = lane & 1;
-  const int64_t jcol = bx * 64 + wave * 16 + r16;
+  const int c = r16 & 1;
+  const int64_t jcol = bx * 64 + wave * 8 + (r16 >> 1);
   const bool colok = jcol < n;
   const int64_t pbeg = by * pchunk;
   const int64_t pend = min(m, pbeg + pchunk);
   const int64_t g0 = bz * NR;
 
-  f4 acc[MT];
+  f4 acc[RT];
 #pragma unroll
-  for (int t = 0; t < MT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+  for (int t = 0; t < RT; ++t) acc[t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
   const TA *Acol = A + (colok ? jcol : 0) * lda;
   // Prefetched values stay in their stored type until the end of the step:
@@ -51,7 +55,7 @@ RID_DEV void sketch_f32_body(
   auto load_g = [&](int64_t p0) {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       const int row = e >> 4, col = e & 15;
       const int64_t i = g0 + row, p = p0 + col;
       stg[r] = (e < NR * 16 && i < l && p < pend) ? G[i * ldg + p] : make_double2(0.0, 0.0);
@@ -60,7 +64,7 @@ RID_DEV void sketch_f32_body(
   auto store_g = [&](int b) {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       if (e < NR * 16) gs[b][(e >> 4) * RS + (e & 15)] = to_f2(stg[r]);
     }
   };
@@ -76,77 +80,82 @@ RID_DEV void sketch_f32_body(
     }
   };
 
-  float2 a4[4];
-  TA an[4];
+  TA a[4], an[4];
   load_g(pbeg);
   store_g(0);
-  load_a(pbeg, an);
-#pragma unroll
-  for (int u = 0; u < 4; ++u) a4[u] = to_f2(an[u]);
-  // nothing may be pending into a4 when the loop starts (it would make every
+  load_a(pbeg, a);
+  // nothing may be pending into `a` when the loop starts (it would make every
   // step wait for its own prefetch before the first product)
   __builtin_amdgcn_s_waitcnt(0);
   __syncthreads();
   int b = 0;
   for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
     const bool more = p0 + 16 < pend;
+    // B operand of MFMA s: k-index 2p (s even) carries [Re a, Im a] for
+    // parts c = 0, 1; k-index 2p+1 carries [-Im a, Re a]
+    float bop[8];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const float2 v = to_f2(a[u]);
+      bop[2 * u] = c ? v.y : v.x;
+      bop[2 * u + 1] = c ? v.x : -v.y;
+    }
     if (more) {
       load_g(p0 + 16);
       load_a(p0 + 16, an);
     }
     const float2 *gb = gs[b];
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      const int row = 8 * t + (r16 >> 1);
+    for (int t = 0; t < RT; ++t) {
+      const int row = 16 * t + r16;
       float2 g4[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) g4[u] = gb[row * RS + 4 * q + u];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        const float o0 = c ? g4[u].y : g4[u].x;
-        const float o1 = c ? g4[u].x : -g4[u].y;
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(o0, a4[u].x, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(o1, a4[u].y, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g4[u].x, bop[2 * u], acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(g4[u].y, bop[2 * u + 1], acc[t], 0, 0, 0);
       }
     }
     if (more) {
       store_g(b ^ 1);
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a4[u] = to_f2(an[u]);
+      for (int u = 0; u < 4; ++u) a[u] = an[u];
     }
     __syncthreads();
     b ^= 1;
   }
   if (!colok) return;
+  // `out` holds the real parts of Y's rows at even and the imaginary parts
+  // at odd offsets of each column (ldo floats apart)
   float *o = out + by * split_stride + jcol * ldo;
-  const int64_t rows = 2 * l;
-  const int64_t mu0 = 2 * g0;
 #pragma unroll
-  for (int t = 0; t < MT; ++t)
+  for (int t = 0; t < RT; ++t)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t mu = mu0 + int64_t(t) * 16 + 4 * q + r;
-      if (mu < rows) o[mu] = acc[t][r];
+      const int64_t i = g0 + int64_t(t) * 16 + 4 * q + r;
+      if (i < l) o[2 * i + c] = acc[t][r];
     }
 }
 
 // One sketch: grid (column blocks, K splits, row slices).
-template <int MT, class TA>
-__global__ __launch_bounds__(256) void sketch_f32_kernel(
+template <int RT, class TA>
+__global__ __launch_bounds__(512) void sketch_f32_kernel(
     int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
     const double2 *__restrict__ G, int64_t ldg, float *__restrict__ out, int64_t ldo,
     int64_t split_stride, int64_t pchunk) {
-  sketch_f32_body<MT, TA>(m, n, l, A, lda, G, ldg, out, ldo, split_stride, pchunk, blockIdx.x,
+  sketch_f32_body<RT, TA>(m, n, l, A, lda, G, ldg, out, ldo, split_stride, pchunk, blockIdx.x,
                           blockIdx.y, blockIdx.z);
 }
 
-// A batch: block b runs (job, column block, split) = tab[b] of that job.
-template <int MT, class TA>
-__global__ __launch_bounds__(256) void sketch_f32_kernel_grouped(const SketchJob *__restrict__ jobs,
+// A batch: block b runs (job, column block, split) = tab[b] of that job
+// (every job of the launch has l <= 16 RT).
+template <int RT, class TA>
+__global__ __launch_bounds__(512) void sketch_f32_kernel_grouped(const SketchJob *__restrict__ jobs,
                                                      const int4 *__restrict__ tab) {
   const int4 e = tab[blockIdx.x];
   const SketchJob &j = jobs[e.x];
-  sketch_f32_body<MT, TA>(j.m, j.n, j.l, static_cast<const TA *>(j.A), j.lda, j.G, j.ldg,
+  sketch_f32_body<RT, TA>(j.m, j.n, j.l, static_cast<const TA *>(j.A), j.lda, j.G, j.ldg,
                    static_cast<float *>(j.part), 2 * j.l, 2 * j.l * j.n, j.pchunk, e.y, e.z, 0);
 }
 
@@ -183,7 +192,7 @@ __global__ __launch_bounds__(256) void sketch_f32_reduce_kernel_grouped(const Sk
 }
 
 struct Plan32 {
-  int MT, nbz;
+  int RT, nbz;
   int64_t nbx;
   int S;
   int64_t pchunk;
@@ -197,11 +206,15 @@ int pick_mt32(int64_t tiles) {
   return 16;
 }
 
+// Row tiles of Y per block for `tiles` 16-row tiles: all of them up to 14,
+// else z-slices of 8.
+int pick_rt32(int64_t tiles) { return tiles <= 14 ? static_cast<int>(tiles < 1 ? 1 : tiles) : 8; }
+
 Plan32 plan32(int64_t m, int64_t n, int64_t l) {
   Plan32 p;
-  const int64_t tiles = (2 * l + 15) / 16;
-  p.MT = pick_mt32(tiles);
-  p.nbz = static_cast<int>((tiles + p.MT - 1) / p.MT);
+  const int64_t tiles = (l + 15) / 16;
+  p.RT = pick_rt32(tiles);
+  p.nbz = static_cast<int>((tiles + p.RT - 1) / p.RT);
   p.nbx = (n + 63) / 64;
   const int64_t base = p.nbx * p.nbz;
   int64_t S = (2048 + base - 1) / base;
@@ -220,12 +233,12 @@ Plan32 plan32(int64_t m, int64_t n, int64_t l) {
   return p;
 }
 
-template <int MT, class TA>
+template <int RT, class TA>
 void launch32(hipStream_t st, const Plan32 &p, int64_t m, int64_t n, int64_t l, const TA *A,
               int64_t lda, const double2 *G, int64_t ldg, float *part) {
   dim3 grid(static_cast<unsigned>(p.nbx), static_cast<unsigned>(p.S),
             static_cast<unsigned>(p.nbz));
-  hipLaunchKernelGGL((sketch_f32_kernel<MT, TA>), grid, dim3(256), 0, st, m, n, l, A, lda, G,
+  hipLaunchKernelGGL((sketch_f32_kernel<RT, TA>), grid, dim3(512), 0, st, m, n, l, A, lda, G,
                      ldg, part, 2 * l, 2 * l * n, p.pchunk);
 }
 
@@ -244,17 +257,15 @@ hipError_t launch_sketch_f32(hipStream_t st, int64_t m, int64_t n, int64_t l, co
   float *part = static_cast<float *>(partv);
   const Plan32 p = plan32(m, n, l);
   ProfScope ps(prof, st, RID_KERNEL_SKETCH);
-  switch (p.MT) {
-#define RID_MT_CASE(X) \
+  switch (p.RT) {
+#define RID_RT_CASE(X) \
   case X:              \
     launch32<X, TA>(st, p, m, n, l, A, lda, G, ldg, part); \
     break;
-    RID_MT_CASE(1) RID_MT_CASE(2) RID_MT_CASE(3) RID_MT_CASE(4) RID_MT_CASE(5)
-    RID_MT_CASE(6) RID_MT_CASE(7) RID_MT_CASE(8) RID_MT_CASE(9) RID_MT_CASE(10)
-    RID_MT_CASE(11) RID_MT_CASE(12) RID_MT_CASE(13) RID_MT_CASE(14) RID_MT_CASE(15)
-    RID_MT_CASE(16) RID_MT_CASE(18) RID_MT_CASE(20) RID_MT_CASE(22) RID_MT_CASE(24)
-    RID_MT_CASE(26) RID_MT_CASE(28)
-#undef RID_MT_CASE
+    RID_RT_CASE(1) RID_RT_CASE(2) RID_RT_CASE(3) RID_RT_CASE(4) RID_RT_CASE(5)
+    RID_RT_CASE(6) RID_RT_CASE(7) RID_RT_CASE(8) RID_RT_CASE(9) RID_RT_CASE(10)
+    RID_RT_CASE(11) RID_RT_CASE(12) RID_RT_CASE(13) RID_RT_CASE(14)
+#undef RID_RT_CASE
     default:
       return hipErrorInvalidValue;
   }
@@ -278,19 +289,20 @@ hipError_t launch_sketch_batch_f32(hipStream_t st, rid_dtype dtype, const Sketch
     if (cnt[b] == 0) continue;
     const dim3 grid(static_cast<unsigned>(cnt[b]));
     const int4 *tb = dtab + off[b];
-    switch (mts[b]) {
+    // mts[b] counts 16-row tiles of 2l real rows (the bucket key shared by
+    // the batch kernels); every job of the bucket has l <= 8 mts[b], so
+    // (mts[b] + 1) / 2 row tiles of Y cover it here
+    switch ((mts[b] + 1) / 2) {
 #define RID_MT_CASE(X)                                                                    \
   case X:                                                                                 \
     if (dtype == RID_C64)                                                                 \
-      hipLaunchKernelGGL((sketch_f32_kernel_grouped<X, float2>), grid, dim3(256), 0, st, djobs, tb);  \
+      hipLaunchKernelGGL((sketch_f32_kernel_grouped<X, float2>), grid, dim3(512), 0, st, djobs, tb);  \
     else                                                                                  \
-      hipLaunchKernelGGL((sketch_f32_kernel_grouped<X, double2>), grid, dim3(256), 0, st, djobs, tb); \
+      hipLaunchKernelGGL((sketch_f32_kernel_grouped<X, double2>), grid, dim3(512), 0, st, djobs, tb); \
     break;
       RID_MT_CASE(1) RID_MT_CASE(2) RID_MT_CASE(3) RID_MT_CASE(4) RID_MT_CASE(5)
       RID_MT_CASE(6) RID_MT_CASE(7) RID_MT_CASE(8) RID_MT_CASE(9) RID_MT_CASE(10)
-      RID_MT_CASE(11) RID_MT_CASE(12) RID_MT_CASE(13) RID_MT_CASE(14) RID_MT_CASE(15)
-      RID_MT_CASE(16) RID_MT_CASE(18) RID_MT_CASE(20) RID_MT_CASE(22) RID_MT_CASE(24)
-      RID_MT_CASE(26) RID_MT_CASE(28)
+      RID_MT_CASE(11) RID_MT_CASE(12) RID_MT_CASE(13) RID_MT_CASE(14)
 #undef RID_MT_CASE
       default:
         return hipErrorInvalidValue;

@@ -76,6 +76,19 @@ def test_sketch_reduced_precision_products(h, prec, dt, m, n, l):
     assert err > 0.0          # the products really are of reduced precision
 
 
+# Every row tiling of the FP32 sketch: 1 to 14 tiles of 16 rows of Y, full and
+# ragged, then z-slices of 8 tiles beyond 224 rows.
+@pytest.mark.parametrize("l", sorted({16 * r - d for r in range(1, 15) for d in (0, 7)} | {225, 401}))
+def test_sketch_fp32_every_row_tiling(h, l):
+    m, n = 1100, 77
+    A = lowrank64(m, n, 6, 1e-3, seed=l)
+    G = oracle.sketch_operator(l, m, seed=l + 3)
+    Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda(), prec=rid.RID_FP32))
+    ref = oracle.sketch(A.astype(np.complex128), G)
+    err = np.linalg.norm(Y - ref) / np.linalg.norm(ref)
+    assert 0.0 < err <= 2e-5, err
+
+
 @pytest.mark.parametrize("m,n,k,l,q", [(1000, 500, 20, 30, 8), (777, 333, 9, 17, 6)])
 def test_residual_complex64_call_for_call(h, m, n, k, l, q):
     A = lowrank64(m, n, k, 1e-3, seed=k)
