@@ -93,7 +93,8 @@ __global__ void pivqr_init_kernel(int64_t n, int *pstep, int *status) {
 }
 
 // Step t of the QR for workgroup bx of nb (the column owner of [64 bx, 64 bx + 64)).
-template <int RR>
+// A wave handles CB of its 16 columns at a time.
+template <int RR, int CB>
 RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y, int64_t ldy,
                              int64_t *perm, double *gaps, double rank_tol, const PivWs &w,
                              int *status, int64_t bx, int64_t nb) {
@@ -199,58 +200,146 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
   const double2 tau = (t > 0) ? tau_s : make_double2(0.0, 0.0);
   const double beta = (t > 0) ? beta_s : 0.0;
   Cand wc = cand_empty();
-  for (int cc = 0; cc < 16; ++cc) {
-    const int64_t j = cbeg + wave * 16 + cc;
-    if (j >= n) break;
-    double2 *col = Y + j * ldy;
-    if (j == jstar) {
+  if constexpr (CB == 1) {
+    // one column at a time
+    for (int cc = 0; cc < 16; ++cc) {
+      const int64_t j = cbeg + wave * 16 + cc;
+      if (j >= n) break;
+      double2 *col = Y + j * ldy;
+      if (j == jstar) {
+#pragma unroll
+        for (int h = 0; h < RR; ++h) {
+          const int64_t row = r0 + lane + 64 * h;
+          if (row < l) col[row] = (row == r0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
+        }
+        if (lane == 0) w.pstep[j] = t - 1;
+        continue;
+      }
+      if (w.pstep[j] >= 0) continue;
+      double2 y[RR];
 #pragma unroll
       for (int h = 0; h < RR; ++h) {
         const int64_t row = r0 + lane + 64 * h;
-        if (row < l) col[row] = (row == r0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
+        y[h] = (row < l) ? col[row] : make_double2(0.0, 0.0);
       }
-      if (lane == 0) w.pstep[j] = t - 1;
-      continue;
+      if (t > 0) {
+        // d = v^H y
+        double dr = 0.0, di = 0.0;
+#pragma unroll
+        for (int h = 0; h < RR; ++h) {
+          const double2 v = v_s[lane + 64 * h];
+          dr += v.x * y[h].x + v.y * y[h].y;
+          di += v.x * y[h].y - v.y * y[h].x;
+        }
+        dr = wave_sum(dr);
+        di = wave_sum(di);
+        // y -= conj(tau) d v
+        const double cr = tau.x * dr + tau.y * di;
+        const double ci = tau.x * di - tau.y * dr;
+#pragma unroll
+        for (int h = 0; h < RR; ++h) {
+          const double2 v = v_s[lane + 64 * h];
+          y[h].x -= v.x * cr - v.y * ci;
+          y[h].y -= v.x * ci + v.y * cr;
+          const int64_t row = r0 + lane + 64 * h;
+          if (row < l) col[row] = y[h];
+        }
+      }
+      if (t < k) {
+        double ss = 0.0;
+#pragma unroll
+        for (int h = 0; h < RR; ++h) {
+          const int64_t row = r0 + lane + 64 * h;
+          if (row >= t && row < l) ss += y[h].x * y[h].x + y[h].y * y[h].y;
+        }
+        const double nrm = sqrt(wave_sum(ss));
+        wc = cand_merge(wc, Cand{nrm, j, -1.0, wave});
+      }
     }
-    if (w.pstep[j] >= 0) continue;
-    double2 y[RR];
+  } else {
+    // CB columns at a time: their loads, reductions and stores are independent
+    // chains that overlap; each column's own arithmetic and reduction order is
+    // the same as one column at a time, so the results are too.  The merge of
+    // candidates is independent of order (max value, lowest index on ties).
+    for (int c0 = 0; c0 < 16; c0 += CB) {
+      double2 y[CB][RR];
+      bool live[CB];
 #pragma unroll
-    for (int h = 0; h < RR; ++h) {
-      const int64_t row = r0 + lane + 64 * h;
-      y[h] = (row < l) ? col[row] : make_double2(0.0, 0.0);
-    }
-    if (t > 0) {
-      // d = v^H y
-      double dr = 0.0, di = 0.0;
+      for (int b = 0; b < CB; ++b) {
+        const int64_t j = cbeg + wave * 16 + c0 + b;
+        live[b] = false;
+        if (j < n) {
+          double2 *col = Y + j * ldy;
+          if (j == jstar) {
 #pragma unroll
-      for (int h = 0; h < RR; ++h) {
-        const double2 v = v_s[lane + 64 * h];
-        dr += v.x * y[h].x + v.y * y[h].y;
-        di += v.x * y[h].y - v.y * y[h].x;
+            for (int h = 0; h < RR; ++h) {
+              const int64_t row = r0 + lane + 64 * h;
+              if (row < l) col[row] = (row == r0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
+            }
+            if (lane == 0) w.pstep[j] = t - 1;
+          } else {
+            live[b] = w.pstep[j] < 0;
+          }
+        }
+#pragma unroll
+        for (int h = 0; h < RR; ++h) {
+          const int64_t row = r0 + lane + 64 * h;
+          y[b][h] = (live[b] && row < l) ? Y[j * ldy + row] : make_double2(0.0, 0.0);
+        }
       }
-      dr = wave_sum(dr);
-      di = wave_sum(di);
-      // y -= conj(tau) d v
-      const double cr = tau.x * dr + tau.y * di;
-      const double ci = tau.x * di - tau.y * dr;
+      if (t > 0) {
+        // d = v^H y
+        double dr[CB], di[CB];
 #pragma unroll
-      for (int h = 0; h < RR; ++h) {
-        const double2 v = v_s[lane + 64 * h];
-        y[h].x -= v.x * cr - v.y * ci;
-        y[h].y -= v.x * ci + v.y * cr;
-        const int64_t row = r0 + lane + 64 * h;
-        if (row < l) col[row] = y[h];
-      }
-    }
-    if (t < k) {
-      double ss = 0.0;
+        for (int b = 0; b < CB; ++b) {
+          dr[b] = 0.0;
+          di[b] = 0.0;
 #pragma unroll
-      for (int h = 0; h < RR; ++h) {
-        const int64_t row = r0 + lane + 64 * h;
-        if (row >= t && row < l) ss += y[h].x * y[h].x + y[h].y * y[h].y;
+          for (int h = 0; h < RR; ++h) {
+            const double2 v = v_s[lane + 64 * h];
+            dr[b] += v.x * y[b][h].x + v.y * y[b][h].y;
+            di[b] += v.x * y[b][h].y - v.y * y[b][h].x;
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+          dr[b] = wave_sum(dr[b]);
+          di[b] = wave_sum(di[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+          if (!live[b]) continue;
+          // y -= conj(tau) d v
+          const double cr = tau.x * dr[b] + tau.y * di[b];
+          const double ci = tau.x * di[b] - tau.y * dr[b];
+          double2 *col = Y + (cbeg + wave * 16 + c0 + b) * ldy;
+#pragma unroll
+          for (int h = 0; h < RR; ++h) {
+            const double2 v = v_s[lane + 64 * h];
+            y[b][h].x -= v.x * cr - v.y * ci;
+            y[b][h].y -= v.x * ci + v.y * cr;
+            const int64_t row = r0 + lane + 64 * h;
+            if (row < l) col[row] = y[b][h];
+          }
+        }
       }
-      const double nrm = sqrt(wave_sum(ss));
-      wc = cand_merge(wc, Cand{nrm, j, -1.0, wave});
+      if (t < k) {
+        double ss[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+          ss[b] = 0.0;
+#pragma unroll
+          for (int h = 0; h < RR; ++h) {
+            const int64_t row = r0 + lane + 64 * h;
+            if (row >= t && row < l) ss[b] += y[b][h].x * y[b][h].x + y[b][h].y * y[b][h].y;
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+          const double nrm = sqrt(wave_sum(ss[b]));
+          if (live[b]) wc = cand_merge(wc, Cand{nrm, cbeg + wave * 16 + c0 + b, -1.0, wave});
+        }
+      }
     }
   }
   if (t >= k) return;
@@ -280,8 +369,11 @@ __global__ __launch_bounds__(256) void pivqr_step_kernel(int t, int64_t l, int64
                                                          int64_t *perm, double *gaps,
                                                          double rank_tol, PivWs w,
                                                          int *status) {
-  pivqr_step_body<RR>(t, l, n, k, Y, ldy, perm, gaps, rank_tol, w, status, blockIdx.x,
-                      gridDim.x);
+  // one ID: a step has few workgroups (n / 64), so the waves gain from
+  // overlapping several columns more than they lose in occupancy
+  constexpr int CB = RR <= 4 ? 4 : (RR <= 8 ? 2 : 1);
+  pivqr_step_body<RR, CB>(t, l, n, k, Y, ldy, perm, gaps, rank_tol, w, status, blockIdx.x,
+                          gridDim.x);
 }
 
 // A batch: block b is column block tab[b].y of job tab[b].x (tab[b].z blocks
@@ -293,8 +385,10 @@ __global__ __launch_bounds__(256) void pivqr_step_grouped(int t, const PivJob *_
   const PivJob &jb = jobs[e.x];
   if (t > jb.k) return;
   const PivWs w{jb.cnorm, jb.cnorm2, jb.cidx, jb.ccol, jb.mark, jb.nu0};
-  pivqr_step_body<RR>(t, jb.l, jb.n, jb.k, jb.Y, jb.ldy, jb.J, nullptr, jb.rank_tol, w,
-                      jb.status, e.y, e.z);
+  // a batch fills the device with workgroups: one column at a time keeps
+  // the registers, and so the occupancy, of the plain loop
+  pivqr_step_body<RR, 1>(t, jb.l, jb.n, jb.k, jb.Y, jb.ldy, jb.J, nullptr, jb.rank_tol, w,
+                         jb.status, e.y, e.z);
 }
 
 // A batch: the picked-step marks of each job's own columns start at -1; the
