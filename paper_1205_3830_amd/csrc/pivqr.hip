@@ -526,6 +526,190 @@ __global__ __launch_bounds__(256) void cgs2_pick_kernel(int t, int64_t l, int64_
   }
 }
 
+// The second pass of a step with many earlier directions, spread over the
+// device (one workgroup reads every earlier direction twice per step, which
+// at k = 1000 costs more than the rest of the QR):
+//   head   (1 workgroup)  merge, pivot, copy of the pivot's residual into v;
+//   coef   (16 directions per workgroup)  c_i = q_i^H v, each by one wave
+//          exactly as in the one-workgroup pick;
+//   update (256 rows x CG_DCH directions per workgroup)  chunk 0 starts from
+//          v and subtracts its c_i q_i in order, later chunks accumulate theirs
+//          from zero;
+//   finish (1 workgroup)  v' = chunk 0 - chunk 1 - ... in order, norm,
+//          q_{t-1} = v' / |v'|, R(t-1, j*).
+// With one chunk the arithmetic is that of the one-workgroup pick, term by
+// term; with more, only the association of the row sums differs.
+constexpr int CG_SPLIT = 64;    // earlier directions above which the pass is spread
+constexpr int CG_DCH = 128;     // directions per update chunk
+
+struct CgsSplit {
+  double2 *v;      // [l] the pivot's residual
+  double2 *c;      // [k] coefficients of the second pass
+  double2 *part;   // [ceil(k / CG_DCH)][l] row sums per chunk
+  int64_t *jst;    // [1] the pivot of the step
+};
+
+template <int RR>
+__global__ __launch_bounds__(256) void cgs2_head_kernel(int t, int64_t l, int64_t *perm,
+                                                        double *gaps, double rank_tol, PivWs w,
+                                                        CgsSplit cs, int *status, int64_t nb) {
+  __shared__ Cand red[256];
+  __shared__ int status_s;
+  if (threadIdx.x == 0) status_s = *status;
+  __syncthreads();
+  if (status_s != RID_OK) return;
+  const int tid = threadIdx.x;
+  const int64_t rd = ((t - 1) & 1) * nb;
+  Cand cd = cand_empty();
+  for (int64_t b = tid; b < nb; b += 256) {
+    Cand x{w.cnorm[rd + b], w.cidx[rd + b], w.cnorm2[rd + b], 0};
+    if (x.v1 < 0.0) x = cand_empty();
+    cd = cand_merge(cd, x);
+  }
+  red[tid] = cd;
+  __syncthreads();
+  for (int st = 128; st >= 1; st >>= 1) {
+    if (tid < st) red[tid] = cand_merge(red[tid], red[tid + st]);
+    __syncthreads();
+  }
+  const Cand best = red[0];
+  const double nu1 = best.v1;
+  const double nu0 = (t == 1) ? nu1 : *w.nu0;
+  const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
+  if (tid == 0) {
+    perm[t - 1] = best.i1;
+    if (gaps) gaps[t - 1] = (best.v2 < 0.0) ? 1.0 : (nu1 - best.v2) / nu1;
+    if (t == 1) *w.nu0 = nu1;
+    if (fail) *status = RID_ERR_RANK;
+    else *cs.jst = best.i1;
+  }
+  if (fail) return;
+  const double2 *x = w.ccol + (rd + best.i1 / PQ_COLS) * l;
+  for (int64_t row = tid; row < l; row += 256) cs.v[row] = x[row];
+}
+
+template <int RR>
+__global__ __launch_bounds__(256) void cgs2_coef_kernel(int t, int64_t l, const double2 *Q,
+                                                        CgsSplit cs, const int *status) {
+  constexpr int QU = 4;
+  __shared__ double2 vs[64 * RR];
+  __shared__ int status_s;
+  if (threadIdx.x == 0) status_s = *status;
+  __syncthreads();
+  if (status_s != RID_OK) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  for (int idx = tid; idx < 64 * RR; idx += 256)
+    vs[idx] = (idx < l) ? cs.v[idx] : make_double2(0.0, 0.0);
+  __syncthreads();
+  const int64_t nq = t - 1;
+  const int64_t i0 = int64_t(blockIdx.x) * 16 + wave * QU;
+  if (i0 >= nq) return;
+  double dr[QU], di[QU];
+#pragma unroll
+  for (int e = 0; e < QU; ++e) dr[e] = di[e] = 0.0;
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const int64_t row = lane + 64 * h;
+    if (row >= l) break;
+    const double2 vv = vs[row];
+#pragma unroll
+    for (int e = 0; e < QU; ++e) {
+      if (i0 + e < nq) {
+        const double2 qv = Q[(i0 + e) * l + row];
+        dr[e] += qv.x * vv.x + qv.y * vv.y;
+        di[e] += qv.x * vv.y - qv.y * vv.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < QU; ++e) {
+    const double a = wave_sum(dr[e]), b = wave_sum(di[e]);
+    if (lane == 0 && i0 + e < nq) cs.c[i0 + e] = make_double2(a, b);
+  }
+}
+
+// grid (row blocks of 256, direction chunks of CG_DCH)
+__global__ __launch_bounds__(256) void cgs2_update_kernel(int t, int64_t l, const double2 *Q,
+                                                          CgsSplit cs, const int *status) {
+  constexpr int QU = 4;
+  if (*status != RID_OK) return;
+  const int64_t row = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (row >= l) return;
+  const int64_t nq = t - 1;
+  const int64_t dc = blockIdx.y;
+  const int64_t ib = dc * CG_DCH;
+  const int64_t ie = min(nq, ib + CG_DCH);
+  double2 acc;
+  if (dc == 0) {
+    acc = cs.v[row];
+    for (int64_t i = ib; i < ie; i += QU) {
+#pragma unroll
+      for (int e = 0; e < QU; ++e) {
+        if (i + e < ie) {
+          const double2 c = cs.c[i + e];
+          const double2 qv = Q[(i + e) * l + row];
+          acc.x -= qv.x * c.x - qv.y * c.y;
+          acc.y -= qv.x * c.y + qv.y * c.x;
+        }
+      }
+    }
+  } else {
+    acc = make_double2(0.0, 0.0);
+    for (int64_t i = ib; i < ie; i += QU) {
+#pragma unroll
+      for (int e = 0; e < QU; ++e) {
+        if (i + e < ie) {
+          const double2 c = cs.c[i + e];
+          const double2 qv = Q[(i + e) * l + row];
+          acc.x += qv.x * c.x - qv.y * c.y;
+          acc.y += qv.x * c.y + qv.y * c.x;
+        }
+      }
+    }
+  }
+  cs.part[dc * l + row] = acc;
+}
+
+template <int RR>
+__global__ __launch_bounds__(256) void cgs2_finish_kernel(int t, int64_t l, int64_t k, int ndc,
+                                                          PivWs w, CgsSplit cs, double2 *Q,
+                                                          double2 *Rk, const int *status) {
+  __shared__ double2 vs[64 * RR];
+  __shared__ double part[256];
+  __shared__ int status_s;
+  if (threadIdx.x == 0) status_s = *status;
+  __syncthreads();
+  if (status_s != RID_OK) return;
+  const int tid = threadIdx.x;
+  double ss = 0.0;
+  for (int64_t row = tid; row < l; row += 256) {
+    double2 acc = cs.part[row];
+    for (int dc = 1; dc < ndc; ++dc) {
+      const double2 p = cs.part[dc * l + row];
+      acc.x -= p.x;
+      acc.y -= p.y;
+    }
+    vs[row] = acc;
+    ss += acc.x * acc.x + acc.y * acc.y;
+  }
+  part[tid] = ss;
+  __syncthreads();
+  for (int st = 128; st >= 1; st >>= 1) {
+    if (tid < st) part[tid] += part[tid + st];
+    __syncthreads();
+  }
+  const double nrm = sqrt(part[0]);
+  for (int64_t row = tid; row < l; row += 256)
+    Q[(t - 1) * l + row] = make_double2(vs[row].x / nrm, vs[row].y / nrm);
+  if (tid == 0) {
+    const int64_t jstar = *cs.jst;
+    Rk[jstar * k + (t - 1)] = make_double2(nrm, 0.0);
+    w.pstep[jstar] = t - 1;
+  }
+}
+
 template <int RR>
 __global__ __launch_bounds__(256) void cgs2_apply_kernel(int t, int64_t l, int64_t n, int64_t k,
                                                          double2 *Y, int64_t ldy, PivWs w,
@@ -693,6 +877,10 @@ size_t pivqr_ws_bytes(int64_t l, int64_t n, int64_t k, int kind) {
     WsCarve c(nullptr);
     c.take<double2>(size_t(l) * size_t(k));
     c.take<double2>(size_t(k) * size_t(n));
+    c.take<double2>(size_t(l));
+    c.take<double2>(size_t(k > 0 ? k : 1));
+    c.take<double2>(size_t((k + CG_DCH - 1) / CG_DCH + 1) * size_t(l));
+    c.take<int64_t>(1);
     b += c.off + 256;
   }
   return b;
@@ -748,6 +936,11 @@ hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2
     WsCarve c(static_cast<char *>(ws) + piv_bytes(l, n));
     double2 *Q = c.take<double2>(size_t(l) * size_t(k));
     double2 *Rk = c.take<double2>(size_t(k) * size_t(n));
+    CgsSplit cs;
+    cs.v = c.take<double2>(size_t(l));
+    cs.c = c.take<double2>(size_t(k > 0 ? k : 1));
+    cs.part = c.take<double2>(size_t((k + CG_DCH - 1) / CG_DCH + 1) * size_t(l));
+    cs.jst = c.take<int64_t>(1);
     const int64_t rcount = k * n;
     hipLaunchKernelGGL(cgs2_zero_kernel,
                        dim3(static_cast<unsigned>(std::min<int64_t>((rcount + 255) / 256, 65536))),
@@ -756,9 +949,22 @@ hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2
     with_rr(pick_rr(l), [&](auto R) {
       constexpr int RR = decltype(R)::value;
       for (int t = 0; t <= k; ++t) {
-        if (t > 0)
+        const int64_t nq = t - 1;  // earlier directions of the second pass
+        if (t > 0 && nq <= CG_SPLIT) {
           hipLaunchKernelGGL(cgs2_pick_kernel<RR>, dim3(1), dim3(256), 0, st, t, l, n, k, perm,
                              gaps, rank_tol, w, Q, Rk, d_status, int64_t(nb));
+        } else if (t > 0) {
+          const int ndc = static_cast<int>((nq + CG_DCH - 1) / CG_DCH);
+          hipLaunchKernelGGL(cgs2_head_kernel<RR>, dim3(1), dim3(256), 0, st, t, l, perm, gaps,
+                             rank_tol, w, cs, d_status, int64_t(nb));
+          hipLaunchKernelGGL(cgs2_coef_kernel<RR>, dim3(static_cast<unsigned>((nq + 15) / 16)),
+                             dim3(256), 0, st, t, l, Q, cs, d_status);
+          hipLaunchKernelGGL(cgs2_update_kernel,
+                             dim3(static_cast<unsigned>((l + 255) / 256), static_cast<unsigned>(ndc)),
+                             dim3(256), 0, st, t, l, Q, cs, d_status);
+          hipLaunchKernelGGL(cgs2_finish_kernel<RR>, dim3(1), dim3(256), 0, st, t, l, k, ndc, w,
+                             cs, Q, Rk, d_status);
+        }
         hipLaunchKernelGGL(cgs2_apply_kernel<RR>, dim3(nb), dim3(256), 0, st, t, l, n, k, Y, ldy,
                            w, Q, Rk, d_status);
       }

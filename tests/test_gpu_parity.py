@@ -401,8 +401,10 @@ def h_cgs2(h):
     rid.rid_set_qr(h, rid.RID_QR_HOUSEHOLDER)
 
 
+# k > 65 takes the second pass spread over the device (one direction chunk
+# at k = 100, two at k = 200, three at k = 300)
 @pytest.mark.parametrize("l,n,k", [(30, 500, 20), (108, 2000, 100), (12, 12, 12), (8, 300, 1),
-                                   (600, 700, 300), (64, 1 << 17, 30)])
+                                   (600, 700, 300), (64, 1 << 17, 30), (250, 3000, 200)])
 def test_cgs2_pivqr_and_interp_match_oracle(h_cgs2, l, n, k):
     h = h_cgs2
     Y = synth.lowrank(l, n, k, 1e-9, seed=3 * l + n)
