@@ -18,6 +18,7 @@
 // Columns stay in place: after the last kernel, Y(0:k, :) is R in original
 // column order.  No floating-point atomics; every reduction has a fixed order.
 #include <algorithm>
+#include <cstdlib>
 #include <climits>
 #include <type_traits>
 
@@ -363,15 +364,252 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
   }
 }
 
+// ---------------------------------------------------------------- panel form
+// For a Y much larger than the last-level cache (8.4 GB at 2000 x 2^18) each
+// step of the plain kernel re-reads and rewrites the trailing rows.  The panel
+// form keeps up to QP_NB reflectors pending.  Step t applies the pending
+// reflectors a .. t-1 to each unpicked column in registers, in order and each
+// as in the plain kernel, takes the exact trailing norms from the result, and
+// writes the updated rows back only when the panel is full (t - a = QP_NB) or
+// at the last step; so the pivots are chosen on exact norms as before.  The
+// pivot column is written at its own step: the pending reflectors a .. t-2
+// applied to its rows a .. t-2 (its entries of R), beta at row t-1, zeros
+// below.  Reflector s is kept, full length and zero above row s, in global
+// slot s % QP_NB (written by workgroup 0 when it is built); each step loads
+// the pending ones into LDS, rows relative to a.  When a step writes nothing,
+// the owning wave of a block's best column recomputes it (re-read, pending
+// reflectors applied) for the candidate copy.
+constexpr int QP_NB = 4;
+
+struct PanelWs {
+  double2 *V;    // [QP_NB][l] reflector slots
+  double2 *tau;  // [QP_NB]
+};
+
+// y -= conj(tau) (v^H y) v over the lane's RR rows, as in the plain kernel
 template <int RR>
+RID_DEV void panel_apply(double2 (&y)[RR], const double2 *vl, double2 tau, int lane) {
+  double dr = 0.0, di = 0.0;
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const double2 v = vl[lane + 64 * h];
+    dr += v.x * y[h].x + v.y * y[h].y;
+    di += v.x * y[h].y - v.y * y[h].x;
+  }
+  dr = wave_sum(dr);
+  di = wave_sum(di);
+  const double cr = tau.x * dr + tau.y * di;
+  const double ci = tau.x * di - tau.y * dr;
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const double2 v = vl[lane + 64 * h];
+    y[h].x -= v.x * cr - v.y * ci;
+    y[h].y -= v.x * ci + v.y * cr;
+  }
+}
+
+template <int RR>
+__global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, int64_t l,
+                                                          int64_t n, int64_t k, double2 *Y,
+                                                          int64_t ldy, int64_t *perm,
+                                                          double *gaps, double rank_tol,
+                                                          PivWs w, PanelWs pw, int *status) {
+  __shared__ double2 vl[QP_NB][64 * RR];
+  __shared__ double2 taus[QP_NB];
+  __shared__ Cand red[256];
+  __shared__ double beta_s;
+  __shared__ int status_s;
+  if (threadIdx.x == 0) status_s = *status;
+  __syncthreads();
+  if (status_s != RID_OK) return;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t bx = blockIdx.x;
+  const int64_t nb = gridDim.x;
+  const int64_t cbeg = bx * PQ_COLS;
+  const int64_t rd = ((t - 1) & 1) * nb;  // candidates of step t-1
+  const int64_t wrb = (t & 1) * nb;       // candidates of step t
+  int64_t jstar = -1;
+  double beta = 0.0;
+  // the pending reflectors a .. t-2, rows relative to a
+  for (int s = a; s < t - 1; ++s) {
+    const int sl = s % QP_NB;
+    for (int idx = tid; idx < 64 * RR; idx += 256) {
+      const int64_t row = a + idx;
+      vl[sl][idx] = (row < l) ? pw.V[sl * l + row] : make_double2(0.0, 0.0);
+    }
+    if (tid == 0) taus[sl] = pw.tau[sl];
+  }
+  if (t > 0) {
+    // ---- pivot of step t-1 (as in the plain kernel)
+    Cand cd = cand_empty();
+    for (int64_t b = tid; b < nb; b += 256) {
+      Cand x{w.cnorm[rd + b], w.cidx[rd + b], w.cnorm2[rd + b], 0};
+      if (x.v1 < 0.0) x = cand_empty();
+      cd = cand_merge(cd, x);
+    }
+    red[tid] = cd;
+    __syncthreads();
+    for (int st = 128; st >= 1; st >>= 1) {
+      if (tid < st) red[tid] = cand_merge(red[tid], red[tid + st]);
+      __syncthreads();
+    }
+    const Cand best = red[0];
+    const double nu1 = best.v1;
+    const double nu0 = (t == 1) ? nu1 : *w.nu0;
+    const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
+    if (bx == 0 && tid == 0) {
+      perm[t - 1] = best.i1;
+      if (gaps) gaps[t - 1] = (best.v2 < 0.0) ? 1.0 : (nu1 - best.v2) / nu1;
+      if (t == 1) *w.nu0 = nu1;
+      if (fail) *status = RID_ERR_RANK;
+    }
+    if (fail) return;
+    jstar = best.i1;
+    // ---- reflector of step t-1 from the candidate copy (wave 0), into slot
+    // (t-1) % QP_NB: rows a .. t-2 zero, 1 at row t-1, the scaled copy below
+    const int sl = (t - 1) % QP_NB;
+    if (wave == 0) {
+      const int64_t r0 = t - 1;
+      const double2 *x = w.ccol + (rd + jstar / PQ_COLS) * l;
+      double2 xv[RR];
+      double ss = 0.0;
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int64_t row = r0 + lane + 64 * h;
+        xv[h] = (row < l) ? x[row] : make_double2(0.0, 0.0);
+        if (lane + 64 * h >= 1) ss += xv[h].x * xv[h].x + xv[h].y * xv[h].y;
+      }
+      const double xnorm2 = wave_sum(ss);
+      const double ar = __shfl(xv[0].x, 0, 64);
+      const double ai = __shfl(xv[0].y, 0, 64);
+      double2 tau;
+      double2 scale;
+      if (xnorm2 == 0.0 && ai == 0.0) {
+        tau = make_double2(0.0, 0.0);
+        beta = ar;
+        scale = make_double2(0.0, 0.0);
+      } else {
+        const double mag = sqrt(ar * ar + ai * ai + xnorm2);
+        beta = (ar >= 0.0) ? -mag : mag;
+        tau = make_double2((beta - ar) / beta, -ai / beta);
+        const double dr = ar - beta, di = ai;
+        const double den = dr * dr + di * di;
+        scale = make_double2(dr / den, -di / den);
+      }
+      for (int64_t idx = lane; idx < 64 * RR; idx += 64) vl[sl][idx] = make_double2(0.0, 0.0);
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int idx = lane + 64 * h;
+        const int64_t row = r0 + idx;
+        if (row < l) {
+          const double2 v = (idx == 0) ? make_double2(1.0, 0.0)
+                                       : make_double2(xv[h].x * scale.x - xv[h].y * scale.y,
+                                                      xv[h].x * scale.y + xv[h].y * scale.x);
+          vl[sl][row - a] = v;
+          if (bx == 0) pw.V[sl * l + row] = v;
+        }
+      }
+      if (bx == 0)
+        for (int64_t row = lane; row < r0; row += 64) pw.V[sl * l + row] = make_double2(0.0, 0.0);
+      if (lane == 0) {
+        taus[sl] = tau;
+        beta_s = beta;
+        if (bx == 0) pw.tau[sl] = tau;
+      }
+    }
+    __syncthreads();
+    beta = beta_s;
+  } else {
+    __syncthreads();
+  }
+
+  // ---- the columns: pending reflectors in order, then the exact trailing norm
+  Cand wc = cand_empty();
+  for (int cc = 0; cc < 16; ++cc) {
+    const int64_t j = cbeg + wave * 16 + cc;
+    if (j >= n) break;
+    if (j != jstar && w.pstep[j] >= 0) continue;
+    double2 *col = Y + j * ldy;
+    double2 y[RR];
+#pragma unroll
+    for (int h = 0; h < RR; ++h) {
+      const int64_t row = a + lane + 64 * h;
+      y[h] = (row < l) ? col[row] : make_double2(0.0, 0.0);
+    }
+    if (j == jstar) {
+      for (int s = a; s < t - 1; ++s) panel_apply<RR>(y, vl[s % QP_NB], taus[s % QP_NB], lane);
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int64_t row = a + lane + 64 * h;
+        if (row < l)
+          col[row] = (row < t - 1) ? y[h]
+                                   : ((row == t - 1) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0));
+      }
+      if (lane == 0) w.pstep[j] = t - 1;
+      continue;
+    }
+    for (int s = a; s < t; ++s) panel_apply<RR>(y, vl[s % QP_NB], taus[s % QP_NB], lane);
+    if (wr) {
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int64_t row = a + lane + 64 * h;
+        if (row < l) col[row] = y[h];
+      }
+    }
+    if (t < k) {
+      double ss = 0.0;
+#pragma unroll
+      for (int h = 0; h < RR; ++h) {
+        const int64_t row = a + lane + 64 * h;
+        if (row >= t && row < l) ss += y[h].x * y[h].x + y[h].y * y[h].y;
+      }
+      const double nrm = sqrt(wave_sum(ss));
+      wc = cand_merge(wc, Cand{nrm, j, -1.0, wave});
+    }
+  }
+  if (t >= k) return;
+
+  // ---- block-level candidate, merged in wave order
+  if (lane == 0) red[wave] = wc;
+  __syncthreads();
+  Cand bc = cand_empty();
+  for (int wv = 0; wv < 4; ++wv) bc = cand_merge(bc, red[wv]);
+  if (tid == 0) {
+    w.cnorm[wrb + bx] = bc.v1;
+    w.cnorm2[wrb + bx] = bc.v2;
+    w.cidx[wrb + bx] = bc.i1;
+  }
+  if (bc.src < 0) return;
+  double2 *dst = w.ccol + (wrb + bx) * l;
+  if (wr || t == a) {
+    // Y holds the column as of this step (written above, or nothing pending)
+    const double2 *src = Y + bc.i1 * ldy;
+    for (int64_t row = t + tid; row < l; row += 256) dst[row] = src[row];
+  } else if (wave == bc.src) {
+    const double2 *src = Y + bc.i1 * ldy;
+    double2 y[RR];
+#pragma unroll
+    for (int h = 0; h < RR; ++h) {
+      const int64_t row = a + lane + 64 * h;
+      y[h] = (row < l) ? src[row] : make_double2(0.0, 0.0);
+    }
+    for (int s = a; s < t; ++s) panel_apply<RR>(y, vl[s % QP_NB], taus[s % QP_NB], lane);
+#pragma unroll
+    for (int h = 0; h < RR; ++h) {
+      const int64_t row = a + lane + 64 * h;
+      if (row >= t && row < l) dst[row] = y[h];
+    }
+  }
+}
+
+template <int RR, int CB>
 __global__ __launch_bounds__(256) void pivqr_step_kernel(int t, int64_t l, int64_t n,
                                                          int64_t k, double2 *Y, int64_t ldy,
                                                          int64_t *perm, double *gaps,
                                                          double rank_tol, PivWs w,
                                                          int *status) {
-  // one ID: a step has few workgroups (n / 64), so the waves gain from
-  // overlapping several columns more than they lose in occupancy
-  constexpr int CB = RR <= 4 ? 4 : (RR <= 8 ? 2 : 1);
   pivqr_step_body<RR, CB>(t, l, n, k, Y, ldy, perm, gaps, rank_tol, w, status, blockIdx.x,
                           gridDim.x);
 }
@@ -862,9 +1100,44 @@ template <int RR>
 void launch_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y, int64_t ldy,
                   int64_t *perm, double *gaps, double rank_tol, const PivWs &w, int *status) {
   const unsigned nb = static_cast<unsigned>((n + PQ_COLS - 1) / PQ_COLS);
-  for (int t = 0; t <= k; ++t)
-    hipLaunchKernelGGL(pivqr_step_kernel<RR>, dim3(nb), dim3(256), 0, st, t, l, n, k, Y, ldy,
-                       perm, gaps, rank_tol, w, status);
+  // With few workgroups per step (n / 64 <= 512: at most two waves per
+  // SIMD) each wave is a chain of dependent loads and reductions, and taking
+  // several columns at a time gains more than the occupancy it costs; with
+  // more workgroups the occupancy wins (200 x 2^16: 5.9 ms one at a time,
+  // 7.3 ms four at a time).
+  constexpr int CBW = RR <= 4 ? 4 : (RR <= 8 ? 2 : 1);
+  const bool wide = nb <= 512;
+  for (int t = 0; t <= k; ++t) {
+    if (wide)
+      hipLaunchKernelGGL((pivqr_step_kernel<RR, CBW>), dim3(nb), dim3(256), 0, st, t, l, n, k, Y,
+                         ldy, perm, gaps, rank_tol, w, status);
+    else
+      hipLaunchKernelGGL((pivqr_step_kernel<RR, 1>), dim3(nb), dim3(256), 0, st, t, l, n, k, Y,
+                         ldy, perm, gaps, rank_tol, w, status);
+  }
+}
+
+// The panel form for a Y that does not fit the last-level cache; the
+// environment variable RID_QR_PANEL=1 (=0) forces (forbids) it.
+bool pivqr_panel_wanted(int64_t l, int64_t n) {
+  const char *e = std::getenv("RID_QR_PANEL");
+  if (e && e[0] == '1') return true;
+  if (e && e[0] == '0') return false;
+  return double(l) * double(n) * 16.0 > 512.0 * 1024 * 1024;
+}
+
+template <int RR>
+void launch_panel_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y,
+                        int64_t ldy, int64_t *perm, double *gaps, double rank_tol,
+                        const PivWs &w, const PanelWs &pw, int *status) {
+  const unsigned nb = static_cast<unsigned>((n + PQ_COLS - 1) / PQ_COLS);
+  int a = 0;  // first reflector not yet written into Y
+  for (int t = 0; t <= k; ++t) {
+    const int wr = (t > 0 && (t - a >= QP_NB || t == k)) ? 1 : 0;
+    hipLaunchKernelGGL(pivqr_panel_kernel<RR>, dim3(nb), dim3(256), 0, st, t, a, wr, l, n, k, Y,
+                       ldy, perm, gaps, rank_tol, w, pw, status);
+    if (wr) a = t;
+  }
 }
 
 }  // namespace
@@ -873,6 +1146,12 @@ bool pivqr_supported(int64_t l) { return l >= 1 && pick_rr(l) > 0; }
 
 size_t pivqr_ws_bytes(int64_t l, int64_t n, int64_t k, int kind) {
   size_t b = piv_bytes(l, n);
+  {
+    WsCarve c(nullptr);  // panel reflector slots
+    c.take<double2>(size_t(QP_NB) * size_t(l));
+    c.take<double2>(QP_NB);
+    b += c.off + 256;
+  }
   if (kind == RID_QR_CGS2) {
     WsCarve c(nullptr);
     c.take<double2>(size_t(l) * size_t(k));
@@ -972,6 +1251,15 @@ hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2
     hipLaunchKernelGGL(cgs2_copy_r_kernel,
                        dim3(static_cast<unsigned>(std::min<int64_t>((rcount + 255) / 256, 65536))),
                        dim3(256), 0, st, n, k, Rk, Y, ldy, d_status);
+  } else if (pivqr_panel_wanted(l, n)) {
+    WsCarve c(static_cast<char *>(ws) + piv_bytes(l, n));
+    PanelWs pw;
+    pw.V = c.take<double2>(size_t(QP_NB) * size_t(l));
+    pw.tau = c.take<double2>(QP_NB);
+    with_rr(pick_rr(l), [&](auto R) {
+      launch_panel_steps<decltype(R)::value>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, pw,
+                                             d_status);
+    });
   } else {
     with_rr(pick_rr(l), [&](auto R) {
       launch_steps<decltype(R)::value>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);

@@ -141,8 +141,21 @@ PIVQR_CASES = [(30, 500, 20), (108, 2000, 100), (12, 12, 12), (40, 9, 9), (8, 30
                (600, 700, 300), (2000, 400, 100), (1024, 1100, 1000)]
 
 
+# both forms of the Householder steps: "plain" rewrites the trailing rows every
+# step; "panel" keeps up to 4 reflectors pending and writes every 4th step
+# (chosen by size for a Y beyond the last-level cache, forced here)
+QR_FORMS = ["plain", "panel"]
+
+
+@pytest.fixture
+def qr_form(request, monkeypatch):
+    monkeypatch.setenv("RID_QR_PANEL", "1" if request.param == "panel" else "0")
+    return request.param
+
+
+@pytest.mark.parametrize("qr_form", QR_FORMS, indirect=True)
 @pytest.mark.parametrize("l,n,k", PIVQR_CASES)
-def test_pivqr_and_interp_match_oracle(h, l, n, k):
+def test_pivqr_and_interp_match_oracle(h, qr_form, l, n, k):
     A = _lowrank(max(l, 400), n, k, 1e-9, seed=l * 7 + n)
     Y = oracle.sketch(A, oracle.sketch_operator(l, A.shape[0], seed=1))
     st, Jo, Ro, gaps_o = oracle.select(Y, k)
@@ -168,8 +181,9 @@ def test_pivqr_and_interp_match_oracle(h, l, n, k):
     assert np.abs(P - Po).max() <= 1e-10 * max(1.0, np.abs(Po).max())
 
 
+@pytest.mark.parametrize("qr_form", QR_FORMS, indirect=True)
 @pytest.mark.parametrize("l,n,k", [(64, 1 << 18, 48), (800, 1 << 17, 40)])
-def test_pivqr_with_more_workgroups_than_fit_at_once(h, l, n, k):
+def test_pivqr_with_more_workgroups_than_fit_at_once(h, qr_form, l, n, k):
     # 4096 (2048) column workgroups per step launch: many start after others
     # finished, so a step must not overwrite what the same launch still reads
     Y = synth.lowrank(l, n, k, 1e-9, seed=n + l)
@@ -183,6 +197,21 @@ def test_pivqr_with_more_workgroups_than_fit_at_once(h, l, n, k):
     assert _compare_J(perm[:k], Jo, gaps_o) == k
     P = host(rid.rid_interp(h, Yd[:k], torch.from_numpy(perm[:k]).cuda()))
     assert np.abs(P - Po).max() <= 1e-10 * max(1.0, np.abs(Po).max())
+
+
+@pytest.mark.parametrize("m,n,k,l,q", [(1000, 500, 20, 30, 10), (2500, 900, 300, 600, 3)])
+def test_decompose_with_panel_qr_matches_oracle(h, monkeypatch, m, n, k, l, q):
+    monkeypatch.setenv("RID_QR_PANEL", "1")
+    A = _lowrank(m, n, k, 1e-10, seed=1)
+    r = oracle.decompose(A, k, l, seed=0, q=q)
+    J, P, sigma, used = rid.rid_decompose(h, dev(A), k, l, seed=0, q=q)
+    J, P, s = host(J), host(P), float(host(sigma)[0])
+    assert _compare_J(J, r["J"], r["gaps"]) == k
+    assert np.array_equal(P[:, J], np.eye(k))
+    dP = P - r["P"]
+    assert np.abs(dP).max() <= 1e-10 * max(1.0, np.abs(r["P"]).max())
+    tol = 1e-10 * r["sigma"] + 2 * np.linalg.norm(A[:, J]) * np.linalg.norm(dP)
+    assert abs(s - r["sigma"]) <= tol
 
 
 @pytest.mark.parametrize("l,n,k,tol", [(30, 500, 20, 1e-12), (108, 1000, 100, 1e-12),
