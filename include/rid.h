@@ -138,7 +138,11 @@ typedef enum {
 
 /* Select the operator kind of this handle's later rid_sketch and
  * rid_decompose calls (Sec. 2 names S F D and allows a faster
- * randomization in its place).  Errors: INVALID_ARG.                     */
+ * randomization in its place).  With S F D and m a multiple of 8 the sketch
+ * runs as a four-step DFT, in one pass over A when no residue group of the
+ * sampled rows exceeds 32 rows, else in two; RID_SRFT_TWO_PASS=1 in the
+ * environment forces the two-pass form (the results agree to rounding).
+ * Errors: INVALID_ARG.                                                    */
 rid_status rid_set_sketch(rid_handle h, int kind);
 
 /* The paper's randomization operator (Sec. 2, eqs. (4)-(7)) written out as
@@ -191,7 +195,11 @@ rid_status rid_sketch_explicit(rid_handle h, hipStream_t stream, rid_dtype dtype
  * If at some step the best trailing norm is <= rank_tol * (the best norm of
  * step 0), the handle's status word is set to RID_ERR_RANK and the outputs
  * are undefined (Sec. 2: rank(Y) < k).  Requires 1 <= k <= min(l, n),
- * ldy >= l.  Errors: INVALID_ARG, NOMEM, HIP.                             */
+ * ldy >= l.  For a Y of more than 512 MB the Householder steps keep up to 4
+ * reflectors pending and write the trailing rows back every 4th step, still
+ * pivoting on exact norms; RID_QR_PANEL=1 (=0) in the environment forces
+ * (forbids) that form (the results agree to rounding).
+ * Errors: INVALID_ARG, NOMEM, HIP.                                        */
 rid_status rid_pivqr(rid_handle h, hipStream_t stream, int64_t l, int64_t n, int64_t k,
                      void *Y, int64_t ldy, int64_t *perm, double *gaps, double rank_tol);
 
