@@ -9,23 +9,28 @@
 // the FP32 MFMA rate.  The pivoted QR, the solve and the residual that
 // follow stay in double.
 //
-// Real embedding as in the other sketches: Yr (2l x n) = Ge (2l x 2m) Ar
-// (2m x n), Ge built from 2 x 2 blocks [[Re g, -Im g], [Im g, Re g]].
-// Operand layouts of the bf16 16x16x32 MFMA (measured on gfx950): lane l
-// supplies row l % 16 of the A operand (and column l % 16 of the B operand)
-// at k = 8 (l / 16) .. 8 (l / 16) + 7; D lane l, register r is row
+// Real embedding as in the other sketches, on the A side: [Yr Yi] (l x 2n) =
+// [Gr Gi] (l x 2m) Ae (2m x 2n), with the 2 x 2 blocks [[Re a, Im a],
+// [-Im a, Re a]] of Ae built per lane from the A entries it loaded, once per
+// K step.  Operand layouts of the bf16 16x16x32 MFMA (measured on gfx950):
+// lane l supplies row l % 16 of the A operand (and column l % 16 of the B
+// operand) at k = 8 (l / 16) .. 8 (l / 16) + 7; D lane l, register r is row
 // 4 (l / 16) + r, column l % 16.  So one MFMA covers 16 complex rows of A: a
-// lane's four consecutive complex entries of its column are exactly its eight
-// k-slots (re, im interleaved), and row mu of Ge over those k-slots is 16
-// contiguous bytes of a pre-split plane.
+// lane's four consecutive complex entries of its column give its eight
+// k-slots (k-index 2p + e), and row i of [Gr Gi] over those k-slots is 16
+// contiguous bytes of a pre-split plane; real column r16 of a tile is part
+// r16 & 1 of complex column r16 >> 1.
 //
-// G is split once per call into three bf16 planes of Ge (row-major, 2m_pad
-// columns, zero padding), reused by every column block.  A workgroup (4
-// waves) owns 128 columns of A -- 2 groups of 16 per wave, so each G operand
-// read from LDS feeds two MFMA sets -- and MT 16-row tiles of Yr.  Per K step
-// of 16 complex rows the workgroup stages the three planes' slab in LDS (one
-// buffer, two barriers; the next slab and the next A entries are loaded into
-// registers while the current step computes).
+// G is split once per call into three bf16 planes of [Gr Gi] (row-major,
+// 2 m_pad columns, zero padding), reused by every column block.  A
+// workgroup (8 waves) owns 128 columns of A -- 2 groups of 8 per wave, so
+// each G operand read from LDS feeds two MFMA sets -- and RT 16-row tiles of
+// Y.  Per K step of 16 complex rows the workgroup stages the three planes'
+// slab in LDS (one buffer, two barriers; the next slab and the next A
+// entries are loaded into registers while the current step computes).  The
+// staged slab is l rows, half of the 2l rows a G-side embedding stages for
+// the same 128 columns, so the slab reads from L2 and the last-level cache
+// per matrix-core operation are halved.
 #include "rid_internal.hpp"
 
 namespace {
@@ -33,7 +38,7 @@ namespace {
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 
-constexpr int BF_MT_MAX = 14;  // tiles per workgroup (LDS: 3 KB per tile)
+constexpr int BF_RT_MAX = 14;  // row tiles of Y per workgroup (LDS: 3 KB per tile)
 
 RID_DEV void split3(double v, __bf16 &h, __bf16 &m, __bf16 &l) {
   h = static_cast<__bf16>(static_cast<float>(v));
@@ -43,9 +48,10 @@ RID_DEV void split3(double v, __bf16 &h, __bf16 &m, __bf16 &l) {
   l = static_cast<__bf16>(static_cast<float>(r2));
 }
 
-// Gs plane p (p = 0, 1, 2 at p * pstride), entry (mu, kappa) at mu * ldk + kappa:
-// the three bf16 terms of Ge(mu, kappa) for mu < 2 * rows_pad, kappa < ldk
-// (zero outside 2l x 2m).  One thread per complex entry (i, p).
+// Gs plane p (p = 0, 1, 2 at p * pstride), entry (i, kappa) at i * ldk + kappa:
+// the three bf16 terms of [Gr Gi](i, kappa) -- Re G(i, kappa/2) for even,
+// Im G(i, kappa/2) for odd kappa -- for i < rows_pad, kappa < ldk (zero
+// outside l x 2m).  One thread per complex entry (i, p).
 __global__ __launch_bounds__(256) void bf16_split_kernel(int64_t l, int64_t m, int64_t rows_pad,
                                                          int64_t mpad,
                                                          const double2 *__restrict__ G,
@@ -57,18 +63,16 @@ __global__ __launch_bounds__(256) void bf16_split_kernel(int64_t l, int64_t m, i
     const int64_t i = e / mpad;
     const int64_t p = e - i * mpad;
     const double2 g = (i < l && p < m) ? G[i * ldg + p] : make_double2(0.0, 0.0);
-    const double v[2][2] = {{g.x, -g.y}, {g.y, g.x}};  // Ge(2i + c, 2p + part)
+    const double v[2] = {g.x, g.y};
 #pragma unroll
-    for (int c = 0; c < 2; ++c)
-#pragma unroll
-      for (int part = 0; part < 2; ++part) {
-        __bf16 h, mi, lo;
-        split3(v[c][part], h, mi, lo);
-        const int64_t at = (2 * i + c) * ldk + 2 * p + part;
-        Gs[at] = h;
-        Gs[pstride + at] = mi;
-        Gs[2 * pstride + at] = lo;
-      }
+    for (int part = 0; part < 2; ++part) {
+      __bf16 h, mi, lo;
+      split3(v[part], h, mi, lo);
+      const int64_t at = i * ldk + 2 * p + part;
+      Gs[at] = h;
+      Gs[pstride + at] = mi;
+      Gs[2 * pstride + at] = lo;
+    }
   }
 }
 
@@ -105,23 +109,25 @@ RID_DEV void split_vec(const float (&v)[8], bf8 &h, bf8 &m, bf8 &l) {
 }
 
 // Block (bx, by, bz): columns [128 bx, 128 bx + 128), K split by (rows
-// [by pchunk, ...) of A), tiles [MT bz, MT bz + MT) of Yr.
-template <int MT, class TA>
+// [by pchunk, ...) of A), row tiles [RT bz, RT bz + RT) of Y.
+template <int RT, class TA>
 RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restrict__ A,
                               int64_t lda, const __bf16 *__restrict__ Gs, int64_t ldk,
                               int64_t pstride, float *__restrict__ out, int64_t ldo,
                               int64_t split_stride, int64_t pchunk, int64_t bx, int64_t by,
                               int64_t bz) {
-  constexpr int ROWS = 16 * MT;                 // Yr rows of the slab
+  constexpr int NT = 512;
+  constexpr int ROWS = 16 * RT;                 // rows of Y (and of the planes) in the slab
   constexpr int CHUNKS = 3 * ROWS * 4;          // 16-byte pieces of the slab (3 planes)
-  constexpr int PER = (CHUNKS + 255) / 256;     // pieces staged per thread
+  constexpr int PER = (CHUNKS + NT - 1) / NT;   // pieces staged per thread
   __shared__ uint4 gsl[3][ROWS][4];             // [plane][row][k-group of 8]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int q = lane >> 4;
   const int r16 = lane & 15;
-  const int64_t mu0 = bz * ROWS;                // first Yr row of the slab
+  const int c = r16 & 1;
+  const int64_t i0 = bz * ROWS;                 // first row of Y of the slab
   const int64_t pbeg = by * pchunk;
   const int64_t pend = min(m, pbeg + pchunk);
   int64_t jcol[2];
@@ -129,30 +135,30 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
   const TA *Acol[2];
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
-    jcol[g] = bx * 128 + wave * 32 + g * 16 + r16;
+    jcol[g] = bx * 128 + wave * 16 + g * 8 + (r16 >> 1);
     ok[g] = jcol[g] < n;
     Acol[g] = A + (ok[g] ? jcol[g] : 0) * lda;
   }
-  f4 acc[2][MT];
+  f4 acc[2][RT];
 #pragma unroll
   for (int g = 0; g < 2; ++g)
 #pragma unroll
-    for (int t = 0; t < MT; ++t) acc[g][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
+    for (int t = 0; t < RT; ++t) acc[g][t] = f4{0.0f, 0.0f, 0.0f, 0.0f};
 
-  const int64_t rows_all = ((2 * l + ROWS - 1) / ROWS) * ROWS;  // rows of the planes
+  const int64_t rows_all = ((l + ROWS - 1) / ROWS) * ROWS;  // rows of the planes
   uint4 stg[PER];
   auto load_slab = [&](int64_t p0) {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
       if (e < CHUNKS && p0 < pend) {
         const int plane = e / (ROWS * 4);
         const int rem = e - plane * ROWS * 4;
         const int row = rem >> 2, kg = rem & 3;
-        const int64_t mu = mu0 + row;
-        if (mu < rows_all) {
-          const __bf16 *src = Gs + plane * pstride + mu * ldk + 2 * p0 + 8 * kg;
+        const int64_t i = i0 + row;
+        if (i < rows_all) {
+          const __bf16 *src = Gs + plane * pstride + i * ldk + 2 * p0 + 8 * kg;
           v = *reinterpret_cast<const uint4 *>(src);
         }
       }
@@ -162,7 +168,7 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
   auto store_slab = [&]() {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      const int e = tid + 256 * r;
+      const int e = tid + NT * r;
       if (e < CHUNKS) {
         const int plane = e / (ROWS * 4);
         const int rem = e - plane * ROWS * 4;
@@ -192,19 +198,29 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
 #pragma unroll
       for (int g = 0; g < 2; ++g) load_a(Acol[g], p0 + 16 + 4 * q, pend, ok[g], an[g]);
     }
+    // B operand: k-index 2p (e = 0) carries [Re a, Im a] for parts c = 0, 1;
+    // k-index 2p+1 carries [-Im a, Re a]; then its three bf16 terms
     bf8 bh[2], bm[2], bl[2];
 #pragma unroll
-    for (int g = 0; g < 2; ++g) split_vec(av[g], bh[g], bm[g], bl[g]);
+    for (int g = 0; g < 2; ++g) {
+      float bv[8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        bv[2 * u] = c ? av[g][2 * u + 1] : av[g][2 * u];
+        bv[2 * u + 1] = c ? av[g][2 * u] : -av[g][2 * u + 1];
+      }
+      split_vec(bv, bh[g], bm[g], bl[g]);
+    }
     // tiles in groups of TG: each of the six products sweeps TG tiles x 2
     // column groups, so consecutive MFMAs use 2 TG different accumulators
     // (no back-to-back dependence); smallest products first
     constexpr int TG = 4;
 #pragma unroll
-    for (int t0 = 0; t0 < MT; t0 += TG) {
+    for (int t0 = 0; t0 < RT; t0 += TG) {
       bf8 ah[TG], am[TG], al[TG];
 #pragma unroll
       for (int u = 0; u < TG; ++u) {
-        if (t0 + u < MT) {
+        if (t0 + u < RT) {
           ah[u] = __builtin_bit_cast(bf8, gsl[0][16 * (t0 + u) + r16][q]);
           am[u] = __builtin_bit_cast(bf8, gsl[1][16 * (t0 + u) + r16][q]);
           al[u] = __builtin_bit_cast(bf8, gsl[2][16 * (t0 + u) + r16][q]);
@@ -212,7 +228,7 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
       }
 #define RID_BF_PRODUCT(AX, BX)                                                        \
   _Pragma("unroll") for (int u = 0; u < TG; ++u) {                                   \
-    if (t0 + u < MT) {                                                               \
+    if (t0 + u < RT) {                                                               \
       _Pragma("unroll") for (int g = 0; g < 2; ++g) acc[g][t0 + u] =                 \
           __builtin_amdgcn_mfma_f32_16x16x32_bf16(AX[u], BX[g], acc[g][t0 + u], 0, 0, 0); \
     }                                                                                \
@@ -230,27 +246,28 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
       for (int g = 0; g < 2; ++g) to_floats(an[g], av[g]);
     }
   }
-  const int64_t rows = 2 * l;
+  // `out` holds the real parts of Y's rows at even and the imaginary parts
+  // at odd offsets of each column (ldo floats apart)
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     if (!ok[g]) continue;
     float *o = out + by * split_stride + jcol[g] * ldo;
 #pragma unroll
-    for (int t = 0; t < MT; ++t)
+    for (int t = 0; t < RT; ++t)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t mu = mu0 + int64_t(t) * 16 + 4 * q + r;
-        if (mu < rows) o[mu] = acc[g][t][r];
+        const int64_t i = i0 + int64_t(t) * 16 + 4 * q + r;
+        if (i < l) o[2 * i + c] = acc[g][t][r];
       }
   }
 }
 
-template <int MT, class TA>
-__global__ __launch_bounds__(256) void sketch_bf16_kernel(
+template <int RT, class TA>
+__global__ __launch_bounds__(512) void sketch_bf16_kernel(
     int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
     const __bf16 *__restrict__ Gs, int64_t ldk, int64_t pstride, float *__restrict__ out,
     int64_t ldo, int64_t split_stride, int64_t pchunk) {
-  sketch_bf16_body<MT, TA>(m, n, l, A, lda, Gs, ldk, pstride, out, ldo, split_stride, pchunk,
+  sketch_bf16_body<RT, TA>(m, n, l, A, lda, Gs, ldk, pstride, out, ldo, split_stride, pchunk,
                            blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
@@ -270,21 +287,21 @@ __global__ __launch_bounds__(256) void bf16_reduce_kernel(int64_t rows, int64_t 
 }
 
 struct BfPlan {
-  int MT;          // tiles per workgroup
-  int nbz;         // workgroups along the Yr rows
+  int RT;          // row tiles of Y per workgroup
+  int nbz;         // workgroups along the rows of Y
   int64_t nbx;     // workgroups along the columns (128 each)
   int S;           // K splits
   int64_t pchunk;  // rows of A per split (multiple of 16)
   int64_t mpad;    // complex columns of the planes (multiple of 16)
-  int64_t rows_pad;  // complex rows of the planes
+  int64_t rows_pad;  // rows of the planes
   int64_t ldk, pstride;
 };
 
 BfPlan plan_bf16(int64_t m, int64_t n, int64_t l) {
   BfPlan p;
-  const int64_t tiles = (2 * l + 15) / 16;
-  p.nbz = static_cast<int>((tiles + BF_MT_MAX - 1) / BF_MT_MAX);
-  p.MT = static_cast<int>((tiles + p.nbz - 1) / p.nbz);
+  const int64_t tiles = (l + 15) / 16;
+  p.nbz = static_cast<int>((tiles + BF_RT_MAX - 1) / BF_RT_MAX);
+  p.RT = static_cast<int>((tiles + p.nbz - 1) / p.nbz);
   p.nbx = (n + 127) / 128;
   const int64_t base = p.nbx * p.nbz;
   int64_t S = (2048 + base - 1) / base;
@@ -300,18 +317,18 @@ BfPlan plan_bf16(int64_t m, int64_t n, int64_t l) {
   if (p.S < 1) p.S = 1;
   p.pchunk = pchunk;
   p.mpad = ((m + 15) / 16) * 16;
-  p.rows_pad = int64_t(p.nbz) * p.MT * 8;  // complex rows: every slab row exists
+  p.rows_pad = int64_t(p.nbz) * p.RT * 16;  // every slab row exists
   p.ldk = 2 * p.mpad;
-  p.pstride = 2 * p.rows_pad * p.ldk;
+  p.pstride = p.rows_pad * p.ldk;
   return p;
 }
 
-template <int MT, class TA>
-void launch_bf16_mt(hipStream_t st, const BfPlan &p, int64_t m, int64_t n, int64_t l,
+template <int RT, class TA>
+void launch_bf16_rt(hipStream_t st, const BfPlan &p, int64_t m, int64_t n, int64_t l,
                     const TA *A, int64_t lda, const __bf16 *Gs, float *part) {
   dim3 grid(static_cast<unsigned>(p.nbx), static_cast<unsigned>(p.S),
             static_cast<unsigned>(p.nbz));
-  hipLaunchKernelGGL((sketch_bf16_kernel<MT, TA>), grid, dim3(256), 0, st, m, n, l, A, lda, Gs,
+  hipLaunchKernelGGL((sketch_bf16_kernel<RT, TA>), grid, dim3(512), 0, st, m, n, l, A, lda, Gs,
                      p.ldk, p.pstride, part, 2 * l, 2 * l * n, p.pchunk);
 }
 
@@ -343,10 +360,10 @@ hipError_t launch_sketch_bf16(hipStream_t st, int64_t m, int64_t n, int64_t l, c
                        l, m, p.rows_pad, p.mpad, G, ldg, Gs, p.ldk, p.pstride);
   }
   ProfScope ps(prof, st, RID_KERNEL_SKETCH);
-  switch (p.MT) {
+  switch (p.RT) {
 #define RID_BF_CASE(X)                                               \
   case X:                                                            \
-    launch_bf16_mt<X, TA>(st, p, m, n, l, A, lda, Gs, part);         \
+    launch_bf16_rt<X, TA>(st, p, m, n, l, A, lda, Gs, part);         \
     break;
     RID_BF_CASE(1) RID_BF_CASE(2) RID_BF_CASE(3) RID_BF_CASE(4) RID_BF_CASE(5) RID_BF_CASE(6)
     RID_BF_CASE(7) RID_BF_CASE(8) RID_BF_CASE(9) RID_BF_CASE(10) RID_BF_CASE(11)
