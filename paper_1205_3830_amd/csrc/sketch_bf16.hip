@@ -26,8 +26,8 @@
 // workgroup (8 waves) owns 128 columns of A -- 2 groups of 8 per wave, so
 // each G operand read from LDS feeds two MFMA sets -- and RT 16-row tiles of
 // Y.  Per K step of 16 complex rows the workgroup stages the three planes'
-// slab in LDS (one buffer, two barriers; the next slab and the next A
-// entries are loaded into registers while the current step computes).  The
+// slab in LDS (double buffered, one barrier per step; the next slab and the
+// next A entries are loaded into registers while the current step computes).  The
 // staged slab is l rows, half of the 2l rows a G-side embedding stages for
 // the same 128 columns, so the slab reads from L2 and the last-level cache
 // per matrix-core operation are halved.
@@ -120,7 +120,7 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
   constexpr int ROWS = 16 * RT;                 // rows of Y (and of the planes) in the slab
   constexpr int CHUNKS = 3 * ROWS * 4;          // 16-byte pieces of the slab (3 planes)
   constexpr int PER = (CHUNKS + NT - 1) / NT;   // pieces staged per thread
-  __shared__ uint4 gsl[3][ROWS][4];             // [plane][row][k-group of 8]
+  __shared__ uint4 gsl[2][3][ROWS][4];          // [buffer][plane][row][k-group of 8]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -165,14 +165,14 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
       stg[r] = v;
     }
   };
-  auto store_slab = [&]() {
+  auto store_slab = [&](int b) {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
       const int e = tid + NT * r;
       if (e < CHUNKS) {
         const int plane = e / (ROWS * 4);
         const int rem = e - plane * ROWS * 4;
-        gsl[plane][rem >> 2][rem & 3] = stg[r];
+        gsl[b][plane][rem >> 2][rem & 3] = stg[r];
       }
     }
   };
@@ -180,6 +180,7 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
   float av[2][8];
   TA an[2][4];
   load_slab(pbeg);
+  store_slab(0);
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
     load_a(Acol[g], pbeg + 4 * q, pend, ok[g], an[g]);
@@ -188,11 +189,10 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
   // nothing may be pending into av when the loop starts (it would make every
   // step wait for its own prefetch before the first product)
   __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  int b = 0;
   for (int64_t p0 = pbeg; p0 < pend; p0 += 16) {
     const bool more = p0 + 16 < pend;
-    __syncthreads();  // the previous step has finished reading the slab
-    store_slab();
-    __syncthreads();
     if (more) {
       load_slab(p0 + 16);
 #pragma unroll
@@ -221,9 +221,9 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
 #pragma unroll
       for (int u = 0; u < TG; ++u) {
         if (t0 + u < RT) {
-          ah[u] = __builtin_bit_cast(bf8, gsl[0][16 * (t0 + u) + r16][q]);
-          am[u] = __builtin_bit_cast(bf8, gsl[1][16 * (t0 + u) + r16][q]);
-          al[u] = __builtin_bit_cast(bf8, gsl[2][16 * (t0 + u) + r16][q]);
+          ah[u] = __builtin_bit_cast(bf8, gsl[b][0][16 * (t0 + u) + r16][q]);
+          am[u] = __builtin_bit_cast(bf8, gsl[b][1][16 * (t0 + u) + r16][q]);
+          al[u] = __builtin_bit_cast(bf8, gsl[b][2][16 * (t0 + u) + r16][q]);
         }
       }
 #define RID_BF_PRODUCT(AX, BX)                                                        \
@@ -242,9 +242,12 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
 #undef RID_BF_PRODUCT
     }
     if (more) {
+      store_slab(b ^ 1);
 #pragma unroll
       for (int g = 0; g < 2; ++g) to_floats(an[g], av[g]);
     }
+    __syncthreads();  // the next slab is in place, and this one no longer read
+    b ^= 1;
   }
   // `out` holds the real parts of Y's rows at even and the imaginary parts
   // at odd offsets of each column (ldo floats apart)
