@@ -95,6 +95,75 @@ __global__ void pivqr_init_kernel(int64_t n, int *pstep, int *status) {
 
 // Step t of the QR for workgroup bx of nb (the column owner of [64 bx, 64 bx + 64)).
 // A wave handles CB of its 16 columns at a time.
+// A raw buffer resource over the given bytes: loads past the end read zeros
+// and stores past it are dropped by the hardware's range check, so a column
+// slice needs no per-row predicates (and an empty one no branch).  Word 3 is
+// the 32-bit data format that every gfx9 target takes.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+RID_DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
+}
+RID_DEV double2 buf_ld(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+RID_DEV void buf_st(__amdgpu_buffer_rsrc_t r, int off, double2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+}
+
+// A value that is the same in every lane but that the compiler cannot see
+// as such (read from LDS), made explicitly uniform.
+RID_DEV int64_t uniform_i64(int64_t v) {
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32));
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<int>(v));
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+RID_DEV double uniform_f64(double v) {
+  return __builtin_bit_cast(double, uniform_i64(__builtin_bit_cast(int64_t, v)));
+}
+
+// y_b -= conj(tau) (v^H y_b) v for CB columns over the lane's RR rows, with
+// one LDS read of v per row for all of them; bit b of zmask gives column b a
+// zero coefficient (it is left as it is).  Sums and updates are plain FMA
+// chains, the same for every column.
+template <int RR, int CB>
+RID_DEV void apply_reflector(double2 (&y)[CB][RR], const double2 *vl, double2 tau, int lane,
+                         unsigned zmask) {
+  double dr[CB], di[CB];
+#pragma unroll
+  for (int b = 0; b < CB; ++b) dr[b] = di[b] = 0.0;
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const double2 v = vl[lane + 64 * h];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      dr[b] = fma(v.x, y[b][h].x, dr[b]);
+      dr[b] = fma(v.y, y[b][h].y, dr[b]);
+      di[b] = fma(v.x, y[b][h].y, di[b]);
+      di[b] = fma(-v.y, y[b][h].x, di[b]);
+    }
+  }
+  double cr[CB], ci[CB];
+#pragma unroll
+  for (int b = 0; b < CB; ++b) {
+    dr[b] = wave_sum(dr[b]);
+    di[b] = wave_sum(di[b]);
+    const bool z = (zmask >> b) & 1u;
+    cr[b] = z ? 0.0 : tau.x * dr[b] + tau.y * di[b];
+    ci[b] = z ? 0.0 : tau.x * di[b] - tau.y * dr[b];
+  }
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const double2 v = vl[lane + 64 * h];
+#pragma unroll
+    for (int b = 0; b < CB; ++b) {
+      y[b][h].x = fma(-v.x, cr[b], y[b][h].x);
+      y[b][h].x = fma(v.y, ci[b], y[b][h].x);
+      y[b][h].y = fma(-v.x, ci[b], y[b][h].y);
+      y[b][h].y = fma(-v.y, cr[b], y[b][h].y);
+    }
+  }
+}
+
 template <int RR, int CB>
 RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y, int64_t ldy,
                              int64_t *perm, double *gaps, double rank_tol, const PivWs &w,
@@ -112,7 +181,9 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
   if (status_s != RID_OK) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  // uniform in the wave; read as such, so that buffer resources built from
+  // it stay in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t cbeg = bx * PQ_COLS;
   int64_t jstar = -1;
   const int64_t r0 = (t > 0) ? t - 1 : 0;  // first row touched by this kernel
@@ -133,7 +204,11 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
       if (tid < s) red[tid] = cand_merge(red[tid], red[tid + s]);
       __syncthreads();
     }
-    const Cand best = red[0];
+    // the same in every lane: read as uniform, so that what depends on it
+    // (the exit on failure, the pivot index) stays uniform for the compiler
+    Cand best = red[0];
+    best.v1 = uniform_f64(best.v1);
+    best.i1 = uniform_i64(best.i1);
     const double nu1 = best.v1;
     const double nu0 = (t == 1) ? nu1 : *w.nu0;
     const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
@@ -197,149 +272,71 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
     __syncthreads();
   }
 
-  // ---- 2b/3. apply the reflector, then the trailing norms of step t
+  // ---- 2b/3. apply the reflector, then the trailing norms of step t.  A
+  // column slice is rows r0 .. l-1 through a range-checked buffer resource:
+  // rows past l load as zeros (as v holds there) and are never stored.
   const double2 tau = (t > 0) ? tau_s : make_double2(0.0, 0.0);
   const double beta = (t > 0) ? beta_s : 0.0;
+  const int64_t jw = cbeg + wave * 16;
+  const int64_t jp = uniform_i64(jstar);  // scalar, as the buffer resources need
+  // picked-step marks of the wave's 16 columns, read at once: bit c is set
+  // for an unpicked column (the pivot of step t-1 included)
+  const bool inr = lane < 16 && jw + lane < n;
+  const uint64_t open = __ballot(inr && w.pstep[inr ? jw + lane : 0] < 0);
+  const int nbytes = static_cast<int>((l - r0) * 16);
+  const int lo = lane * 16;
   Cand wc = cand_empty();
-  if constexpr (CB == 1) {
-    // one column at a time
-    for (int cc = 0; cc < 16; ++cc) {
-      const int64_t j = cbeg + wave * 16 + cc;
-      if (j >= n) break;
-      double2 *col = Y + j * ldy;
-      if (j == jstar) {
+  // CB columns at a time: their loads, reductions and stores are independent
+  // chains that overlap; each column's own arithmetic and reduction order is
+  // the same as one column at a time, so the results are too.  The merge of
+  // candidates is independent of order (max value, lowest index on ties).
+  for (int c0 = 0; c0 < 16; c0 += CB) {
+    double2 y[CB][RR];
+    __amdgpu_buffer_rsrc_t rs[CB];
+    bool live[CB];
 #pragma unroll
-        for (int h = 0; h < RR; ++h) {
-          const int64_t row = r0 + lane + 64 * h;
-          if (row < l) col[row] = (row == r0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
-        }
+    for (int b = 0; b < CB; ++b) {
+      const int64_t j = jw + c0 + b;
+      const bool open_j = (open >> (c0 + b)) & 1;
+      if (open_j && j == jp) {
+        // the pivot of step t-1: beta at row r0, zeros below
+        const __amdgpu_buffer_rsrc_t rp = buf_rsrc(Y + j * ldy + r0, nbytes);
+#pragma unroll
+        for (int h = 0; h < RR; ++h)
+          buf_st(rp, lo + 1024 * h,
+                 (h == 0 && lane == 0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0));
         if (lane == 0) w.pstep[j] = t - 1;
-        continue;
       }
-      if (w.pstep[j] >= 0) continue;
-      double2 y[RR];
+      live[b] = open_j && j != jp;
+      rs[b] = buf_rsrc(live[b] ? Y + j * ldy + r0 : Y, live[b] ? nbytes : 0);
 #pragma unroll
-      for (int h = 0; h < RR; ++h) {
-        const int64_t row = r0 + lane + 64 * h;
-        y[h] = (row < l) ? col[row] : make_double2(0.0, 0.0);
-      }
-      if (t > 0) {
-        // d = v^H y
-        double dr = 0.0, di = 0.0;
-#pragma unroll
-        for (int h = 0; h < RR; ++h) {
-          const double2 v = v_s[lane + 64 * h];
-          dr += v.x * y[h].x + v.y * y[h].y;
-          di += v.x * y[h].y - v.y * y[h].x;
-        }
-        dr = wave_sum(dr);
-        di = wave_sum(di);
-        // y -= conj(tau) d v
-        const double cr = tau.x * dr + tau.y * di;
-        const double ci = tau.x * di - tau.y * dr;
-#pragma unroll
-        for (int h = 0; h < RR; ++h) {
-          const double2 v = v_s[lane + 64 * h];
-          y[h].x -= v.x * cr - v.y * ci;
-          y[h].y -= v.x * ci + v.y * cr;
-          const int64_t row = r0 + lane + 64 * h;
-          if (row < l) col[row] = y[h];
-        }
-      }
-      if (t < k) {
-        double ss = 0.0;
-#pragma unroll
-        for (int h = 0; h < RR; ++h) {
-          const int64_t row = r0 + lane + 64 * h;
-          if (row >= t && row < l) ss += y[h].x * y[h].x + y[h].y * y[h].y;
-        }
-        const double nrm = sqrt(wave_sum(ss));
-        wc = cand_merge(wc, Cand{nrm, j, -1.0, wave});
-      }
+      for (int h = 0; h < RR; ++h) y[b][h] = buf_ld(rs[b], lo + 1024 * h);
     }
-  } else {
-    // CB columns at a time: their loads, reductions and stores are independent
-    // chains that overlap; each column's own arithmetic and reduction order is
-    // the same as one column at a time, so the results are too.  The merge of
-    // candidates is independent of order (max value, lowest index on ties).
-    for (int c0 = 0; c0 < 16; c0 += CB) {
-      double2 y[CB][RR];
-      bool live[CB];
+    if (t > 0) {
+      apply_reflector<RR, CB>(y, v_s, tau, lane, 0u);
+#pragma unroll
+      for (int b = 0; b < CB; ++b)
+#pragma unroll
+        for (int h = 0; h < RR; ++h) buf_st(rs[b], lo + 1024 * h, y[b][h]);
+    }
+    if (t < k) {
+      // rows t .. l-1: all but row r0 = t-1 (lane 0 of slot 0) when t > 0
+      const bool below = lane >= t - r0;
+      double ss[CB];
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
-        const int64_t j = cbeg + wave * 16 + c0 + b;
-        live[b] = false;
-        if (j < n) {
-          double2 *col = Y + j * ldy;
-          if (j == jstar) {
-#pragma unroll
-            for (int h = 0; h < RR; ++h) {
-              const int64_t row = r0 + lane + 64 * h;
-              if (row < l) col[row] = (row == r0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0);
-            }
-            if (lane == 0) w.pstep[j] = t - 1;
-          } else {
-            live[b] = w.pstep[j] < 0;
-          }
-        }
+        ss[b] = 0.0;
 #pragma unroll
         for (int h = 0; h < RR; ++h) {
-          const int64_t row = r0 + lane + 64 * h;
-          y[b][h] = (live[b] && row < l) ? Y[j * ldy + row] : make_double2(0.0, 0.0);
+          const double2 q = (h > 0 || below) ? y[b][h] : make_double2(0.0, 0.0);
+          ss[b] = fma(q.x, q.x, ss[b]);
+          ss[b] = fma(q.y, q.y, ss[b]);
         }
       }
-      if (t > 0) {
-        // d = v^H y
-        double dr[CB], di[CB];
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-          dr[b] = 0.0;
-          di[b] = 0.0;
-#pragma unroll
-          for (int h = 0; h < RR; ++h) {
-            const double2 v = v_s[lane + 64 * h];
-            dr[b] += v.x * y[b][h].x + v.y * y[b][h].y;
-            di[b] += v.x * y[b][h].y - v.y * y[b][h].x;
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-          dr[b] = wave_sum(dr[b]);
-          di[b] = wave_sum(di[b]);
-        }
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-          if (!live[b]) continue;
-          // y -= conj(tau) d v
-          const double cr = tau.x * dr[b] + tau.y * di[b];
-          const double ci = tau.x * di[b] - tau.y * dr[b];
-          double2 *col = Y + (cbeg + wave * 16 + c0 + b) * ldy;
-#pragma unroll
-          for (int h = 0; h < RR; ++h) {
-            const double2 v = v_s[lane + 64 * h];
-            y[b][h].x -= v.x * cr - v.y * ci;
-            y[b][h].y -= v.x * ci + v.y * cr;
-            const int64_t row = r0 + lane + 64 * h;
-            if (row < l) col[row] = y[b][h];
-          }
-        }
-      }
-      if (t < k) {
-        double ss[CB];
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-          ss[b] = 0.0;
-#pragma unroll
-          for (int h = 0; h < RR; ++h) {
-            const int64_t row = r0 + lane + 64 * h;
-            if (row >= t && row < l) ss[b] += y[b][h].x * y[b][h].x + y[b][h].y * y[b][h].y;
-          }
-        }
-#pragma unroll
-        for (int b = 0; b < CB; ++b) {
-          const double nrm = sqrt(wave_sum(ss[b]));
-          if (live[b]) wc = cand_merge(wc, Cand{nrm, cbeg + wave * 16 + c0 + b, -1.0, wave});
-        }
+      for (int b = 0; b < CB; ++b) {
+        const double nrm = sqrt(wave_sum(ss[b]));
+        if (live[b]) wc = cand_merge(wc, Cand{nrm, jw + c0 + b, -1.0, wave});
       }
     }
   }
@@ -386,29 +383,7 @@ struct PanelWs {
   double2 *tau;  // [QP_NB]
 };
 
-// y -= conj(tau) (v^H y) v over the lane's RR rows, as in the plain kernel
-template <int RR>
-RID_DEV void panel_apply(double2 (&y)[RR], const double2 *vl, double2 tau, int lane) {
-  double dr = 0.0, di = 0.0;
-#pragma unroll
-  for (int h = 0; h < RR; ++h) {
-    const double2 v = vl[lane + 64 * h];
-    dr += v.x * y[h].x + v.y * y[h].y;
-    di += v.x * y[h].y - v.y * y[h].x;
-  }
-  dr = wave_sum(dr);
-  di = wave_sum(di);
-  const double cr = tau.x * dr + tau.y * di;
-  const double ci = tau.x * di - tau.y * dr;
-#pragma unroll
-  for (int h = 0; h < RR; ++h) {
-    const double2 v = vl[lane + 64 * h];
-    y[h].x -= v.x * cr - v.y * ci;
-    y[h].y -= v.x * ci + v.y * cr;
-  }
-}
-
-template <int RR>
+template <int RR, int CB>
 __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, int64_t l,
                                                           int64_t n, int64_t k, double2 *Y,
                                                           int64_t ldy, int64_t *perm,
@@ -424,7 +399,9 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
   if (status_s != RID_OK) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  // uniform in the wave; read as such, so that buffer resources built from
+  // it stay in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t bx = blockIdx.x;
   const int64_t nb = gridDim.x;
   const int64_t cbeg = bx * PQ_COLS;
@@ -455,7 +432,11 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
       if (tid < st) red[tid] = cand_merge(red[tid], red[tid + st]);
       __syncthreads();
     }
-    const Cand best = red[0];
+    // the same in every lane: read as uniform, so that what depends on it
+    // (the exit on failure, the pivot index) stays uniform for the compiler
+    Cand best = red[0];
+    best.v1 = uniform_f64(best.v1);
+    best.i1 = uniform_i64(best.i1);
     const double nu1 = best.v1;
     const double nu0 = (t == 1) ? nu1 : *w.nu0;
     const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
@@ -525,48 +506,76 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
     __syncthreads();
   }
 
-  // ---- the columns: pending reflectors in order, then the exact trailing norm
+  // ---- the columns, CB at a time: pending reflectors in order, then the
+  // exact trailing norm.  A reflector is read from LDS once for the CB
+  // columns, and their reduction chains overlap; each column's operations
+  // are those of one column alone (the pivot column of step t-1 takes a zero
+  // coefficient for reflector t-1).  A column slice is rows a .. l-1 through
+  // a range-checked buffer resource: rows past l load as zeros (and stay
+  // zero, as do the reflectors there) and are never stored.
+  const int64_t jw = cbeg + wave * 16;
+  // picked-step marks of the wave's 16 columns, read at once: bit c is set
+  // for an unpicked column (the pivot of step t-1 included)
+  const bool inr = lane < 16 && jw + lane < n;
+  const uint64_t open = __ballot(inr && w.pstep[inr ? jw + lane : 0] < 0);
+  const int nbytes = static_cast<int>((l - a) * 16);
+  const int lo = lane * 16;
   Cand wc = cand_empty();
-  for (int cc = 0; cc < 16; ++cc) {
-    const int64_t j = cbeg + wave * 16 + cc;
-    if (j >= n) break;
-    if (j != jstar && w.pstep[j] >= 0) continue;
-    double2 *col = Y + j * ldy;
-    double2 y[RR];
+  for (int c0 = 0; c0 < 16; c0 += CB) {
+    double2 y[CB][RR];
+    __amdgpu_buffer_rsrc_t rs[CB];
+    bool live[CB];
+    unsigned zmask = 0;
 #pragma unroll
-    for (int h = 0; h < RR; ++h) {
-      const int64_t row = a + lane + 64 * h;
-      y[h] = (row < l) ? col[row] : make_double2(0.0, 0.0);
+    for (int b = 0; b < CB; ++b) {
+      const int64_t j = jw + c0 + b;
+      live[b] = (open >> (c0 + b)) & 1;
+      if (j == jstar) zmask |= 1u << b;
+      rs[b] = buf_rsrc(live[b] ? Y + j * ldy + a : Y, live[b] ? nbytes : 0);
+#pragma unroll
+      for (int h = 0; h < RR; ++h) y[b][h] = buf_ld(rs[b], lo + 1024 * h);
     }
-    if (j == jstar) {
-      for (int s = a; s < t - 1; ++s) panel_apply<RR>(y, vl[s % QP_NB], taus[s % QP_NB], lane);
+    for (int s = a; s < t; ++s)
+      apply_reflector<RR, CB>(y, vl[s % QP_NB], taus[s % QP_NB], lane, (s == t - 1) ? zmask : 0u);
 #pragma unroll
-      for (int h = 0; h < RR; ++h) {
-        const int64_t row = a + lane + 64 * h;
-        if (row < l)
-          col[row] = (row < t - 1) ? y[h]
-                                   : ((row == t - 1) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0));
-      }
-      if (lane == 0) w.pstep[j] = t - 1;
-      continue;
-    }
-    for (int s = a; s < t; ++s) panel_apply<RR>(y, vl[s % QP_NB], taus[s % QP_NB], lane);
-    if (wr) {
+    for (int b = 0; b < CB; ++b) {
+      if (!live[b]) continue;
+      if ((zmask >> b) & 1u) {
+        // rows a .. t-2: its entries of R; beta at row t-1; zeros below
 #pragma unroll
-      for (int h = 0; h < RR; ++h) {
-        const int64_t row = a + lane + 64 * h;
-        if (row < l) col[row] = y[h];
+        for (int h = 0; h < RR; ++h) {
+          const int64_t row = a + lane + 64 * h;
+          const double2 v = (row < t - 1) ? y[b][h]
+                                          : ((row == t - 1) ? make_double2(beta, 0.0)
+                                                            : make_double2(0.0, 0.0));
+          buf_st(rs[b], lo + 1024 * h, v);
+        }
+        if (lane == 0) w.pstep[jw + c0 + b] = t - 1;
+      } else if (wr) {
+#pragma unroll
+        for (int h = 0; h < RR; ++h) buf_st(rs[b], lo + 1024 * h, y[b][h]);
       }
     }
     if (t < k) {
-      double ss = 0.0;
+      // rows t .. l-1: all but rows a .. t-1, which sit in slot 0
+      const bool below = lane >= t - a;
+      double ss[CB];
 #pragma unroll
-      for (int h = 0; h < RR; ++h) {
-        const int64_t row = a + lane + 64 * h;
-        if (row >= t && row < l) ss += y[h].x * y[h].x + y[h].y * y[h].y;
+      for (int b = 0; b < CB; ++b) {
+        ss[b] = 0.0;
+#pragma unroll
+        for (int h = 0; h < RR; ++h) {
+          const double2 q = (h > 0 || below) ? y[b][h] : make_double2(0.0, 0.0);
+          ss[b] = fma(q.x, q.x, ss[b]);
+          ss[b] = fma(q.y, q.y, ss[b]);
+        }
       }
-      const double nrm = sqrt(wave_sum(ss));
-      wc = cand_merge(wc, Cand{nrm, j, -1.0, wave});
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const double nrm = sqrt(wave_sum(ss[b]));
+        if (live[b] && !((zmask >> b) & 1u))
+          wc = cand_merge(wc, Cand{nrm, jw + c0 + b, -1.0, wave});
+      }
     }
   }
   if (t >= k) return;
@@ -588,18 +597,16 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
     const double2 *src = Y + bc.i1 * ldy;
     for (int64_t row = t + tid; row < l; row += 256) dst[row] = src[row];
   } else if (wave == bc.src) {
-    const double2 *src = Y + bc.i1 * ldy;
-    double2 y[RR];
+    // the same loads and arithmetic as in the column loop above
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(Y + uniform_i64(bc.i1) * ldy + a, nbytes);
+    double2 y[1][RR];
+#pragma unroll
+    for (int h = 0; h < RR; ++h) y[0][h] = buf_ld(rs, lo + 1024 * h);
+    for (int s = a; s < t; ++s) apply_reflector<RR, 1>(y, vl[s % QP_NB], taus[s % QP_NB], lane, 0u);
 #pragma unroll
     for (int h = 0; h < RR; ++h) {
       const int64_t row = a + lane + 64 * h;
-      y[h] = (row < l) ? src[row] : make_double2(0.0, 0.0);
-    }
-    for (int s = a; s < t; ++s) panel_apply<RR>(y, vl[s % QP_NB], taus[s % QP_NB], lane);
-#pragma unroll
-    for (int h = 0; h < RR; ++h) {
-      const int64_t row = a + lane + 64 * h;
-      if (row >= t && row < l) dst[row] = y[h];
+      if (row >= t && row < l) dst[row] = y[0][h];
     }
   }
 }
@@ -1073,10 +1080,10 @@ __global__ __launch_bounds__(1024) void pivqr_tail_kernel(int64_t n, int64_t k,
   }
 }
 
-// rows per lane for a sketch of l rows: the smallest of 1, 2, 3, 4, 8, 16, 32
-// with 64 RR >= l (0 when l > 2048)
+// rows per lane for l rows in play: the smallest of 1, 2, 3, 4, 6, 8, 12, 16,
+// 24, 32 with 64 RR >= l (0 when l > 2048)
 int pick_rr(int64_t l) {
-  static const int opts[] = {1, 2, 3, 4, 8, 16, 32};
+  static const int opts[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32};
   for (int o : opts)
     if (64 * o >= l) return o;
   return 0;
@@ -1089,14 +1096,18 @@ void with_rr(int rr, F &&f) {
     case 2: f(std::integral_constant<int, 2>()); break;
     case 3: f(std::integral_constant<int, 3>()); break;
     case 4: f(std::integral_constant<int, 4>()); break;
+    case 6: f(std::integral_constant<int, 6>()); break;
     case 8: f(std::integral_constant<int, 8>()); break;
+    case 12: f(std::integral_constant<int, 12>()); break;
     case 16: f(std::integral_constant<int, 16>()); break;
+    case 24: f(std::integral_constant<int, 24>()); break;
     case 32: f(std::integral_constant<int, 32>()); break;
     default: break;
   }
 }
 
-template <int RR>
+// Step t touches rows t-1 .. l-1 only, so each launch takes the smallest RR
+// that covers them: at l = 2k the rows in play halve over the QR.
 void launch_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y, int64_t ldy,
                   int64_t *perm, double *gaps, double rank_tol, const PivWs &w, int *status) {
   const unsigned nb = static_cast<unsigned>((n + PQ_COLS - 1) / PQ_COLS);
@@ -1105,15 +1116,19 @@ void launch_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y, i
   // several columns at a time gains more than the occupancy it costs; with
   // more workgroups the occupancy wins (200 x 2^16: 5.9 ms one at a time,
   // 7.3 ms four at a time).
-  constexpr int CBW = RR <= 4 ? 4 : (RR <= 8 ? 2 : 1);
   const bool wide = nb <= 512;
   for (int t = 0; t <= k; ++t) {
-    if (wide)
-      hipLaunchKernelGGL((pivqr_step_kernel<RR, CBW>), dim3(nb), dim3(256), 0, st, t, l, n, k, Y,
-                         ldy, perm, gaps, rank_tol, w, status);
-    else
-      hipLaunchKernelGGL((pivqr_step_kernel<RR, 1>), dim3(nb), dim3(256), 0, st, t, l, n, k, Y,
-                         ldy, perm, gaps, rank_tol, w, status);
+    const int64_t r0 = (t > 0) ? t - 1 : 0;
+    with_rr(pick_rr(l - r0), [&](auto R) {
+      constexpr int RR = decltype(R)::value;
+      constexpr int CBW = RR <= 4 ? 4 : (RR <= 8 ? 2 : 1);
+      if (wide)
+        hipLaunchKernelGGL((pivqr_step_kernel<RR, CBW>), dim3(nb), dim3(256), 0, st, t, l, n, k,
+                           Y, ldy, perm, gaps, rank_tol, w, status);
+      else
+        hipLaunchKernelGGL((pivqr_step_kernel<RR, 1>), dim3(nb), dim3(256), 0, st, t, l, n, k, Y,
+                           ldy, perm, gaps, rank_tol, w, status);
+    });
   }
 }
 
@@ -1126,7 +1141,7 @@ bool pivqr_panel_wanted(int64_t l, int64_t n) {
   return double(l) * double(n) * 16.0 > 512.0 * 1024 * 1024;
 }
 
-template <int RR>
+// rows a .. l-1 are in play at step t; RR is picked per launch as above
 void launch_panel_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y,
                         int64_t ldy, int64_t *perm, double *gaps, double rank_tol,
                         const PivWs &w, const PanelWs &pw, int *status) {
@@ -1134,8 +1149,13 @@ void launch_panel_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2
   int a = 0;  // first reflector not yet written into Y
   for (int t = 0; t <= k; ++t) {
     const int wr = (t > 0 && (t - a >= QP_NB || t == k)) ? 1 : 0;
-    hipLaunchKernelGGL(pivqr_panel_kernel<RR>, dim3(nb), dim3(256), 0, st, t, a, wr, l, n, k, Y,
-                       ldy, perm, gaps, rank_tol, w, pw, status);
+    with_rr(pick_rr(l - a), [&](auto R) {
+      constexpr int RR = decltype(R)::value;
+      // one column at a time: two (CB = 2) gained under 2% at RR = 24 and
+      // lost at RR <= 16, where their registers cost occupancy
+      hipLaunchKernelGGL((pivqr_panel_kernel<RR, 1>), dim3(nb), dim3(256), 0, st, t, a, wr, l,
+                         n, k, Y, ldy, perm, gaps, rank_tol, w, pw, status);
+    });
     if (wr) a = t;
   }
 }
@@ -1195,7 +1215,8 @@ hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const 
   ProfScope ps(prof, st, RID_KERNEL_PIVQR);
   hipLaunchKernelGGL(pivqr_init_grouped, grid, dim3(256), 0, st, djobs, dtab);
   for (int t = 0; t <= kmax; ++t) {
-    with_rr(pick_rr(lmax), [&](auto R) {
+    // every job's rows in play, t-1 .. l-1, fit in lmax - (t-1)
+    with_rr(pick_rr(lmax - (t > 0 ? t - 1 : 0)), [&](auto R) {
       hipLaunchKernelGGL(pivqr_step_grouped<decltype(R)::value>, grid, dim3(256), 0, st, t,
                          djobs, dtab);
     });
@@ -1256,14 +1277,9 @@ hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2
     PanelWs pw;
     pw.V = c.take<double2>(size_t(QP_NB) * size_t(l));
     pw.tau = c.take<double2>(QP_NB);
-    with_rr(pick_rr(l), [&](auto R) {
-      launch_panel_steps<decltype(R)::value>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, pw,
-                                             d_status);
-    });
+    launch_panel_steps(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, pw, d_status);
   } else {
-    with_rr(pick_rr(l), [&](auto R) {
-      launch_steps<decltype(R)::value>(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
-    });
+    launch_steps(st, l, n, k, Y, ldy, perm, gaps, rank_tol, w, d_status);
   }
   hipLaunchKernelGGL(pivqr_tail_kernel, dim3(1), dim3(1024), 0, st, n, k, w.pstep, perm,
                      d_status);
