@@ -968,7 +968,9 @@ __global__ __launch_bounds__(256) void cgs2_apply_kernel(int t, int64_t l, int64
   if (status_s != RID_OK) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  // uniform in the wave; read as such, so that buffer resources built from
+  // it stay in scalar registers
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t bx = blockIdx.x;
   const int64_t nb = gridDim.x;
   const int64_t cbeg = bx * PQ_COLS;
@@ -978,25 +980,33 @@ __global__ __launch_bounds__(256) void cgs2_apply_kernel(int t, int64_t l, int64
       q_s[idx] = (idx < l) ? Q[(t - 1) * l + idx] : make_double2(0.0, 0.0);
     __syncthreads();
   }
+  // A column is rows 0 .. l-1 through a range-checked buffer resource: rows
+  // past l load as zeros (as q holds there) and are never stored.  The
+  // picked-step marks of the wave's 16 columns are read at once (bit c set:
+  // unpicked; the pivot of this step is already marked).
+  const int64_t jw = cbeg + wave * 16;
+  const bool inr = lane < 16 && jw + lane < n;
+  const uint64_t open = __ballot(inr && w.pstep[inr ? jw + lane : 0] < 0);
+  const int nbytes = static_cast<int>(l * 16);
+  const int lo = lane * 16;
   Cand wc = cand_empty();
   for (int cc = 0; cc < 16; ++cc) {
-    const int64_t j = cbeg + wave * 16 + cc;
-    if (j >= n) break;
-    if (w.pstep[j] >= 0) continue;  // picked, the pivot of this step included
-    double2 *col = Y + j * ldy;
+    if (!((open >> cc) & 1)) continue;
+    const int64_t j = jw + cc;
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(Y + j * ldy, nbytes);
     double2 y[RR];
 #pragma unroll
-    for (int h = 0; h < RR; ++h) {
-      const int64_t row = lane + 64 * h;
-      y[h] = (row < l) ? col[row] : make_double2(0.0, 0.0);
-    }
+    for (int h = 0; h < RR; ++h) y[h] = buf_ld(rs, lo + 1024 * h);
     if (t > 0) {
+      // r = q^H y, then y -= q r, as FMA chains
       double dr = 0.0, di = 0.0;
 #pragma unroll
       for (int h = 0; h < RR; ++h) {
         const double2 qv = q_s[lane + 64 * h];
-        dr += qv.x * y[h].x + qv.y * y[h].y;
-        di += qv.x * y[h].y - qv.y * y[h].x;
+        dr = fma(qv.x, y[h].x, dr);
+        dr = fma(qv.y, y[h].y, dr);
+        di = fma(qv.x, y[h].y, di);
+        di = fma(-qv.y, y[h].x, di);
       }
       dr = wave_sum(dr);
       di = wave_sum(di);
@@ -1004,16 +1014,20 @@ __global__ __launch_bounds__(256) void cgs2_apply_kernel(int t, int64_t l, int64
 #pragma unroll
       for (int h = 0; h < RR; ++h) {
         const double2 qv = q_s[lane + 64 * h];
-        y[h].x -= qv.x * dr - qv.y * di;
-        y[h].y -= qv.x * di + qv.y * dr;
-        const int64_t row = lane + 64 * h;
-        if (row < l) col[row] = y[h];
+        y[h].x = fma(-qv.x, dr, y[h].x);
+        y[h].x = fma(qv.y, di, y[h].x);
+        y[h].y = fma(-qv.x, di, y[h].y);
+        y[h].y = fma(-qv.y, dr, y[h].y);
+        buf_st(rs, lo + 1024 * h, y[h]);
       }
     }
     if (t < k) {
       double ss = 0.0;
 #pragma unroll
-      for (int h = 0; h < RR; ++h) ss += y[h].x * y[h].x + y[h].y * y[h].y;
+      for (int h = 0; h < RR; ++h) {
+        ss = fma(y[h].x, y[h].x, ss);
+        ss = fma(y[h].y, y[h].y, ss);
+      }
       wc = cand_merge(wc, Cand{sqrt(wave_sum(ss)), j, -1.0, wave});
     }
   }
