@@ -182,6 +182,30 @@ def test_pivqr_and_interp_match_oracle(h, qr_form, l, n, k):
 
 
 @pytest.mark.parametrize("qr_form", QR_FORMS, indirect=True)
+def test_pivqr_rows_per_lane_shrink_over_the_steps(h, qr_form):
+    # each step launches with the fewest rows per lane that cover the rows in
+    # play: here 1600 -> 951 rows, so RR 32, 24 and 16 in turn (the panel form
+    # changes RR only where it writes back)
+    l, n, k = 1600, 1500, 650
+    Y = synth.lowrank(l, n, k, 1e-9, seed=3100)
+    st, Jo, Ro, gaps_o = oracle.select(Y, k)
+    assert st == oracle.OK
+    Po = oracle.interp(Ro, Jo)
+    Yd = dev(Y)
+    perm, gaps = rid.rid_pivqr(h, Yd, k)
+    assert rid.rid_query_status(h) == rid.RID_OK
+    perm = host(perm)
+    assert _compare_J(perm[:k], Jo, gaps_o) == k
+    R = host(Yd)[:k]
+    assert np.allclose(np.abs(R[np.arange(k), perm[:k]]), np.abs(Ro[np.arange(k), Jo]),
+                       rtol=1e-11)
+    assert np.all(np.tril(R[:, perm[:k]], -1) == 0)
+    P = host(rid.rid_interp(h, Yd[:k], torch.from_numpy(perm[:k]).cuda()))
+    assert np.array_equal(P[:, Jo], np.eye(k))
+    assert np.abs(P - Po).max() <= 1e-10 * max(1.0, np.abs(Po).max())
+
+
+@pytest.mark.parametrize("qr_form", QR_FORMS, indirect=True)
 @pytest.mark.parametrize("l,n,k", [(64, 1 << 18, 48), (800, 1 << 17, 40)])
 def test_pivqr_with_more_workgroups_than_fit_at_once(h, qr_form, l, n, k):
     # 4096 (2048) column workgroups per step launch: many start after others
