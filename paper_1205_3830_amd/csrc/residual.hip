@@ -260,7 +260,10 @@ struct RowPair<float2> {
 };
 
 // z partials: rows [512 bx, +512) x columns of split by
-template <class TA>
+// WIDE: the complex64 fast path below (one ID's large slabs); the grouped
+// kernels of a batch leave it out, as their small jobs rarely take it and
+// would pay its registers
+template <class TA, bool WIDE>
 RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
   using RP = RowPair<TA>;
   if (stopped(r.scal)) return;
@@ -302,6 +305,33 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
     c1i = fma(a1.y, xl.x, c1i);
   };
   int64_t j = jb;
+  if constexpr (WIDE && sizeof(TA) == 8) {
+    // complex64, the whole slab inside A and 16-byte pairs allowed (a uniform
+    // test): each column is one unconditional pair load per thread, and 8
+    // columns are in flight at a time.  The products and their order are
+    // those of the general loop below; only the skeleton columns' low-word
+    // terms join the error sums in groups of 8 instead of 4.
+    if (pair && (bx + 1) * AX_ROWS <= m) {
+      for (; j + 8 <= je; j += 8) {
+        double2 a0[8], a1[8], xl[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          ld_stream_pair(a0p + (j + u) * lda, a0[u], a1[u]);
+        bool lo = false;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          xl[u] = xtl[j + u];
+          lo = lo || xl[u].x != 0.0 || xl[u].y != 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc_hi(a0[u], a1[u], xth[j + u]);
+        if (lo) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc_lo(a0[u], a1[u], xl[u]);
+        }
+      }
+    }
+  }
   for (; j + 4 <= je; j += 4) {
     double2 a0[4], a1[4], xl[4];
 #pragma unroll
@@ -543,7 +573,7 @@ enum Step : int {
   ST_W, ST_AHZ4, ST_COUNT
 };
 
-template <class TA, int STEP>
+template <class TA, int STEP, bool WIDE>
 RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
   if constexpr (STEP == ST_X0) x0_body(r, bx);
   if constexpr (STEP == ST_WNORM) wnorm_final_body(r);
@@ -551,7 +581,7 @@ RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
   if constexpr (STEP == ST_XTINIT) xt_init_body(r, bx);
   if constexpr (STEP == ST_PXP) px_partial_body(r, bx);
   if constexpr (STEP == ST_PXF) px_final_body(r, bx);
-  if constexpr (STEP == ST_AX) ax_body<TA>(r, bx, by);
+  if constexpr (STEP == ST_AX) ax_body<TA, WIDE>(r, bx, by);
   if constexpr (STEP == ST_ZF) z_final_body(r, bx);
   if constexpr (STEP == ST_SIGMA) sigma_final_body(r, t);
   if constexpr (STEP == ST_AHZ) ahz_body<TA, 8>(r, bx, by);
@@ -562,14 +592,14 @@ RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
 
 template <class TA, int STEP>
 __global__ __launch_bounds__(256) void step_single(ResJob r, int t) {
-  run_step<TA, STEP>(r, blockIdx.x, blockIdx.y, t);
+  run_step<TA, STEP, true>(r, blockIdx.x, blockIdx.y, t);
 }
 
 template <class TA, int STEP>
 __global__ __launch_bounds__(256) void step_grouped(const ResJob *__restrict__ jobs,
                                                     const int4 *__restrict__ tab, int t) {
   const int4 e = tab[blockIdx.x];
-  run_step<TA, STEP>(jobs[e.x], e.y, e.z, t);
+  run_step<TA, STEP, false>(jobs[e.x], e.y, e.z, t);
 }
 
 // blocks of one step for one job (gx by gy)
