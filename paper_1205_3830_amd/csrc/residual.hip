@@ -260,9 +260,9 @@ struct RowPair<float2> {
 };
 
 // z partials: rows [512 bx, +512) x columns of split by
-// WIDE: the complex64 fast path below (one ID's large slabs); the grouped
-// kernels of a batch leave it out, as their small jobs rarely take it and
-// would pay its registers
+// WIDE: the fast path below (one ID's large slabs); the grouped kernels of a
+// batch leave it out, as their small jobs rarely take it and would pay its
+// registers
 template <class TA, bool WIDE>
 RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
   using RP = RowPair<TA>;
@@ -305,18 +305,23 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
     c1i = fma(a1.y, xl.x, c1i);
   };
   int64_t j = jb;
-  if constexpr (WIDE && sizeof(TA) == 8) {
-    // complex64, the whole slab inside A and 16-byte pairs allowed (a uniform
-    // test): each column is one unconditional pair load per thread, and 8
-    // columns are in flight at a time.  The products and their order are
-    // those of the general loop below; only the skeleton columns' low-word
-    // terms join the error sums in groups of 8 instead of 4.
-    if (pair && (bx + 1) * AX_ROWS <= m) {
+  if constexpr (WIDE) {
+    // the whole slab inside A and, for complex64, 16-byte pairs allowed (a
+    // uniform test): every load is unconditional (one pair load per thread
+    // and column for complex64), and 8 columns are in flight at a time.  The
+    // products and their order are those of the general loop below; only the
+    // skeleton columns' low-word terms join the error sums in groups of 8
+    // instead of 4.
+    if ((sizeof(TA) == 16 || pair) && (bx + 1) * AX_ROWS <= m) {
       for (; j + 8 <= je; j += 8) {
         double2 a0[8], a1[8], xl[8];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-          ld_stream_pair(a0p + (j + u) * lda, a0[u], a1[u]);
+        for (int u = 0; u < 8; ++u) {
+          if constexpr (sizeof(TA) == 8)
+            ld_stream_pair(a0p + (j + u) * lda, a0[u], a1[u]);
+          else
+            RP::load(a0p, a1p, true, true, (j + u) * lda, pair, a0[u], a1[u]);
+        }
         bool lo = false;
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
