@@ -99,6 +99,22 @@ def test_residual_complex64_call_for_call(h, m, n, k, l, q):
     assert np.all(np.abs(host(hist) - r["hist"]) <= 1e-10 * r["hist"])
 
 
+@pytest.mark.parametrize("m,n,pad", [(1600, 300, 2), (1600, 300, 1)])
+def test_residual_complex64_padded_leading_dimension(h, m, n, pad):
+    # three whole 512-row slabs and a ragged one; lda = m + 2 keeps 16-byte
+    # pairs (the whole-slab fast path of the ax pass), lda = m + 1 does not
+    k, l, q = 12, 20, 6
+    A = lowrank64(m, n, k, 1e-3, seed=m + pad)
+    r = oracle.decompose(A.astype(np.complex128), k, l, seed=3, q=q)
+    buf = torch.zeros((n, m + pad), dtype=torch.complex64, device="cuda")
+    buf[:, :m] = torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda")
+    Ad = buf[:, :m].t()                       # m x n, column stride m + pad
+    assert Ad.stride() == (1, m + pad)
+    sigma, hist = rid.rid_residual(h, Ad, torch.from_numpy(r["J"]).cuda(), dev(r["P"]), q, 3)
+    assert abs(float(host(sigma)[0]) - r["sigma"]) <= 1e-10 * r["sigma"]
+    assert np.all(np.abs(host(hist) - r["hist"]) <= 1e-10 * r["hist"])
+
+
 @pytest.mark.parametrize("prec", ["RID_FP32", "RID_BF16X3"])
 @pytest.mark.parametrize("m,n,k,l", [(1000, 500, 20, 30), (2048, 700, 64, 72)])
 def test_decompose_complex64_reduced_precision(h, prec, m, n, k, l):
