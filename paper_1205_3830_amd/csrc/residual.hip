@@ -185,6 +185,8 @@ RID_DEV void px_partial_body(const ResJob &r, int64_t bx) {
   const int64_t j1 = min(r.n, j0 + PX_JC);
   for (int64_t t = threadIdx.x; t < r.k; t += 256) {
     double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+    // unrolled so that several loads are in flight; the sums keep their order
+#pragma unroll 8
     for (int64_t j = j0; j < j1; ++j) {
       const double2 pe = r.P[t + j * r.ldp];
       const double2 xj = r.x[j];
@@ -207,6 +209,8 @@ RID_DEV void px_final_body(const ResJob &r, int64_t bx) {
   const int64_t t = bx * 256 + threadIdx.x;
   if (t >= r.k) return;
   double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+  // unrolled so that several loads are in flight; the sums keep their order
+#pragma unroll 8
   for (int64_t b = 0; b < r.pl.nb_px; ++b) {
     const double *o = r.pxpart + (b * r.k + t) * 4;
     dd_add(sr, cr, o[0], o[1]);
@@ -382,6 +386,8 @@ RID_DEV void z_final_body(const ResJob &r, int64_t bx) {
   double v = 0.0;
   if (i < r.m) {
     double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+    // unrolled so that several loads are in flight; the sums keep their order
+#pragma unroll 8
     for (int64_t s = 0; s < r.pl.S_z; ++s) {
       const double *o = r.zpart + (s * r.m + i) * 4;
       dd_add(sr, cr, o[0], o[1]);
@@ -516,6 +522,8 @@ RID_DEV void u_final_body(const ResJob &r, int64_t bx) {
   const int64_t j = bx * 256 + threadIdx.x;
   if (j >= r.n) return;
   double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+  // unrolled so that several loads are in flight; the sums keep their order
+#pragma unroll 8
   for (int64_t s = 0; s < r.pl.S_u; ++s) {
     const double *o = r.upart + (s * r.n + j) * 4;
     dd_add(sr, cr, o[0], o[1]);
