@@ -73,6 +73,9 @@ def _load():
         lib.orc_sketch_seeded.argtypes = [I64, I64, I64, P, I64, ctypes.c_uint64, P, I64]
         lib.orc_select.argtypes = [I64, I64, I64, P, I64, ctypes.c_double, P, P, I64, P]
         lib.orc_select.restype = ctypes.c_int
+        lib.orc_select_forced.argtypes = [I64, I64, I64, P, I64, ctypes.c_double, P, P, P, I64,
+                                          P, P, P]
+        lib.orc_select_forced.restype = ctypes.c_int
         lib.orc_interp.argtypes = [I64, I64, P, I64, P, P, I64]
         lib.orc_interp.restype = ctypes.c_int
         lib.orc_residual.argtypes = [I64, I64, I64, P, I64, P, P, I64, P, ctypes.c_int, P, P]
@@ -181,6 +184,32 @@ def select(Y, k: int, rank_tol: float = 1e-12):
     gaps = np.zeros(k, dtype=np.float64)
     st = _load().orc_select(l, n, k, _ptr(Y), l, rank_tol, _ptr(J), _ptr(R), k, _ptr(gaps))
     return st, J, R, gaps
+
+
+def select_forced(Y, forced, rank_tol: float = 1e-12):
+    """The greedy selection re-synchronised onto given pivots.
+
+    Step t takes column forced[t] (where >= 0) instead of its own argmax; the
+    step's own choice, its pivot gap and the trailing norm of the column
+    taken relative to the best are recorded first.  Sec. 2 only asks for a
+    permutation that brings the most weighted columns to the front, so where
+    two trailing norms nearly tie either pick is valid; forcing the other
+    side's pick keeps every later step comparable.
+    Returns a dict: status, J (the columns taken), R (k x n, original column
+    order), gaps, argmax (the oracle's own pick per step), ratio.
+    """
+    Y = _cf(Y)
+    l, n = Y.shape
+    forced = np.ascontiguousarray(np.asarray(forced, dtype=np.int64))
+    k = forced.shape[0]
+    J = np.full(k, -1, dtype=np.int64)
+    R = np.zeros((k, n), dtype=np.complex128, order="F")
+    gaps = np.zeros(k, dtype=np.float64)
+    argmax = np.full(k, -1, dtype=np.int64)
+    ratio = np.zeros(k, dtype=np.float64)
+    st = _load().orc_select_forced(l, n, k, _ptr(Y), l, rank_tol, _ptr(forced), _ptr(J),
+                                   _ptr(R), k, _ptr(gaps), _ptr(argmax), _ptr(ratio))
+    return dict(status=st, J=J, R=R, gaps=gaps, argmax=argmax, ratio=ratio)
 
 
 def interp(R, J) -> np.ndarray:

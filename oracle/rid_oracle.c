@@ -229,8 +229,19 @@ static void caxpy_neg(double *w, const double *v, int64_t len, double cr, double
   }
 }
 
-int orc_select(int64_t l, int64_t n, int64_t k, const double *Y, int64_t ldy,
-               double rank_tol, int64_t *J, double *R, int64_t ldr, double *gaps) {
+/* The same selection, optionally re-synchronised onto pivots chosen         */
+/* elsewhere (Sec. 2 allows any permutation that brings the most weighted    */
+/* columns to the front, so at a near-tie either candidate is a valid pick). */
+/* With forced != NULL, step t takes column forced[t] (if >= 0) instead of   */
+/* its own argmax, after recording, for that step:                           */
+/*   argmax[t] = the oracle's own pick (greedy, lowest index on exact ties), */
+/*   gaps[t]   = (best - second best) / best of the oracle's own norms,      */
+/*   ratio[t]  = (trailing norm of the column taken) / best.                 */
+/* A forced index that is out of range or already taken is an argument      */
+/* error.  argmax and ratio may be NULL.                                     */
+int orc_select_forced(int64_t l, int64_t n, int64_t k, const double *Y, int64_t ldy,
+                      double rank_tol, const int64_t *forced, int64_t *J, double *R,
+                      int64_t ldr, double *gaps, int64_t *argmax, double *ratio) {
   if (k < 1 || k > n || k > l || ldy < l || ldr < k) return ORC_ERR_ARG;
   double *res = (double *)malloc(sizeof(double) * 2 * (size_t)l * (size_t)n);
   double *Q = (double *)malloc(sizeof(double) * 2 * (size_t)l * (size_t)k);
@@ -251,11 +262,20 @@ int orc_select(int64_t l, int64_t n, int64_t k, const double *Y, int64_t ldy,
     }
     if (t == 0) nu0 = b1;
     if (gaps) gaps[t] = (b2 < 0.0) ? 1.0 : (b1 > 0.0 ? (b1 - b2) / b1 : 0.0);
-    if (!(b1 > 0.0) || b1 <= rank_tol * nu0) { status = ORC_ERR_RANK; J[t] = best; break; }
-    J[t] = best;
-    picked[best] = 1;
+    if (argmax) argmax[t] = best;
+    int64_t take = best;
+    if (forced && forced[t] >= 0) {
+      take = forced[t];
+      if (take >= n || picked[take]) { status = ORC_ERR_ARG; break; }
+    }
+    if (ratio) ratio[t] = b1 > 0.0 ? nu[take] / b1 : 0.0;
+    if (!(b1 > 0.0) || b1 <= rank_tol * nu0 || !(nu[take] > 0.0)) {
+      status = ORC_ERR_RANK; J[t] = take; break;
+    }
+    J[t] = take;
+    picked[take] = 1;
     double *q = Q + 2 * t * l;
-    memcpy(q, res + 2 * best * l, sizeof(double) * 2 * l);
+    memcpy(q, res + 2 * take * l, sizeof(double) * 2 * l);
     /* second Gram-Schmidt pass against the existing basis */
     for (int64_t s = 0; s < t; ++s) {
       double cr, ci;
@@ -285,6 +305,11 @@ int orc_select(int64_t l, int64_t n, int64_t k, const double *Y, int64_t ldy,
   }
   free(res); free(Q); free(nu); free(picked);
   return status;
+}
+
+int orc_select(int64_t l, int64_t n, int64_t k, const double *Y, int64_t ldy,
+               double rank_tol, int64_t *J, double *R, int64_t ldr, double *gaps) {
+  return orc_select_forced(l, n, k, Y, ldy, rank_tol, NULL, J, R, ldr, gaps, NULL, NULL);
 }
 
 /* ------------------------------------------------------------------------ */

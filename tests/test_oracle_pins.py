@@ -122,6 +122,116 @@ def test_select_matches_bruteforce_tiny(seed):
     assert list(J) == _greedy_bruteforce(Y, k)
 
 
+def test_select_forced_on_its_own_picks_is_the_plain_selection():
+    Y = synth.lowrank(40, 300, 25, 1e-9, seed=21)
+    st, J, R, gaps = oracle.select(Y, 25)
+    r = oracle.select_forced(Y, J)
+    assert st == r["status"] == oracle.OK
+    assert np.array_equal(r["J"], J) and np.array_equal(r["argmax"], J)
+    assert np.array_equal(r["R"], R) and np.array_equal(r["gaps"], gaps)
+    assert np.all(r["ratio"] == 1.0)
+    # -1 entries leave the step free: the same as no forcing at all
+    r2 = oracle.select_forced(Y, np.full(25, -1))
+    assert np.array_equal(r2["J"], J) and np.array_equal(r2["R"], R)
+
+
+def test_select_forced_follows_the_forced_pivots():
+    # forcing step 0 onto another column: that column is taken, and every
+    # later step is the greedy choice among what is left, which equals the
+    # plain selection of Y with the forced column moved out of the way first
+    Y = synth.lowrank(30, 120, 12, 1e-9, seed=22)
+    st, J, R, gaps = oracle.select(Y, 12)
+    f = np.full(12, -1)
+    f[0] = J[1]
+    r = oracle.select_forced(Y, f)
+    assert r["status"] == oracle.OK and r["J"][0] == J[1] and r["argmax"][0] == J[0]
+    nrm = np.linalg.norm(Y, axis=0)
+    assert r["ratio"][0] == pytest.approx(nrm[J[1]] / nrm[J[0]], rel=1e-14)
+    # later picks are greedy on the projection orthogonal to Y(:, J[1])
+    assert list(r["J"]) == [J[1]] + _greedy_bruteforce_after(Y, [int(J[1])], 11)
+    # R is Q^H Y for the forced order: R1 upper triangular, T = lstsq
+    R1 = r["R"][:, r["J"]]
+    assert np.allclose(np.tril(R1, -1), 0, atol=1e-12 * np.abs(R1).max())
+    P = oracle.interp(r["R"], r["J"])
+    others = np.setdiff1d(np.arange(120), r["J"])
+    T = np.linalg.lstsq(Y[:, r["J"]], Y[:, others], rcond=None)[0]
+    assert np.abs(P[:, others] - T).max() <= 1e-10 * max(1, np.abs(T).max())
+    bad = r["J"].copy()
+    bad[3] = bad[2]
+    assert oracle.select_forced(Y, bad)["status"] == oracle.ERR_ARG     # repeated column
+
+
+def _greedy_bruteforce_after(Y, first, k):
+    n = Y.shape[1]
+    J = list(first)
+    for _ in range(k):
+        B = Y[:, J]
+        best, bj = -1.0, -1
+        for j in range(n):
+            if j in J:
+                continue
+            r = Y[:, j] - B @ np.linalg.lstsq(B, Y[:, j], rcond=None)[0]
+            if np.linalg.norm(r) > best * (1 + 1e-12):
+                best, bj = np.linalg.norm(r), j
+        J.append(bj)
+    return J[len(first):]
+
+
+def test_parity_checker_accepts_near_tie_swaps_and_rejects_wrong_picks():
+    # the shared GPU-test check (tests/parity.py) on planted pivot lists: a
+    # near-tie broken the other way passes, a wrong pick at a clear gap fails
+    from parity import check_pivots
+    rng = np.random.default_rng(4)
+    l, n, k = 20, 80, 10
+    Y = (rng.standard_normal((l, n)) + 1j * rng.standard_normal((l, n))) / np.sqrt(2)
+    Y[:, 5] *= 4.0
+    Y[:, 9] = Y[:, 5] * np.exp(0.7j)            # near-tie with column 5 at step 0
+    Y = np.asfortranarray(Y)
+    st, J, R, gaps = oracle.select(Y, k)
+    assert gaps[0] <= 1e-10 and J[0] in (5, 9)
+    other = 9 if J[0] == 5 else 5
+    swapped = oracle.select_forced(Y, np.r_[other, np.full(k - 1, -1)])["J"]
+    r = check_pivots(Y, swapped, 1e-10)
+    assert r["near_ties"] >= 1
+    assert np.array_equal(r["P"][:, swapped], np.eye(k))
+    wrong = J.copy()
+    wrong[3], wrong[4] = J[4], J[3]
+    assert gaps[3] > 1e-6
+    with pytest.raises(AssertionError):
+        check_pivots(Y, wrong, 1e-10)
+
+
+def test_id_error_against_the_best_column_subsets_tiny():
+    # brute force over every k-subset J' on tiny inputs: the best column
+    # subset's error min ||(I - Pi_J') A||_2 bounds the ID's error from below
+    # (the ID's P is one choice of coefficients for its own J), and the ID's
+    # error stays within eq. (3) (eps = 1e-10); the ratio to the optimum is
+    # reported.  A plausible mistake in the selection or the solve (a wrong
+    # pivot, a transposed or conjugated T) pushes the ID above the optimum
+    # by orders of magnitude on these near-low-rank inputs.
+    from itertools import combinations
+    ratios = []
+    for seed in range(6):
+        rng = np.random.default_rng(100 + seed)
+        m, n = int(rng.integers(6, 11)), int(rng.integers(6, 13))
+        k = int(rng.integers(1, 4))
+        A = synth.lowrank(m, n, k, 1e-6, seed=200 + seed)
+        r = oracle.decompose(A, k, min(m, k + 3), seed=seed, q=30)
+        assert r["status"] == oracle.OK
+        err = np.linalg.norm(A - A[:, r["J"]] @ r["P"], 2)
+        best = min(np.linalg.norm(A - A[:, list(c)] @ np.linalg.lstsq(A[:, list(c)], A,
+                                                                       rcond=None)[0], 2)
+                   for c in combinations(range(n), k))
+        s = np.linalg.svd(A, compute_uv=False)
+        assert s[k] <= best * (1 + 1e-9)            # Eckart-Young below the best subset
+        assert best <= err * (1 + 1e-9)
+        assert err <= 50 * np.sqrt(m * n) * (1e10) ** (1.0 / k) * s[k]
+        assert r["sigma"] <= err * (1 + 1e-9)       # the power estimate is from below
+        ratios.append(err / best)
+    print("ID error / best-subset error: %s" % ", ".join("%.3f" % x for x in ratios))
+    assert max(ratios) < 10.0
+
+
 @pytest.mark.parametrize("l,n,k", [(30, 500, 20), (60, 200, 40), (12, 12, 12)])
 def test_select_matches_lapack_zgeqp3(l, n, k):
     A = synth.lowrank(400, n, k, 1e-8, seed=l)
