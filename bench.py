@@ -33,8 +33,12 @@ BF16_PEAK_TFS = 2500.0       # MI355X BF16 matrix (dense)
 
 # sketch product arithmetic by command-line name
 PRECS = {"fp64": lambda rid: rid.RID_FP64, "fp32": lambda rid: rid.RID_FP32,
-         "bf16x3": lambda rid: rid.RID_BF16X3}
+         "bf16x2": lambda rid: rid.RID_BF16X2, "bf16x3": lambda rid: rid.RID_BF16X3}
+# rank tolerance of the QR per sketch arithmetic: above each form's rounding
+# floor (|R_kk| / |R_11| of the workloads is about 1e-2)
+RANK_TOL = {"fp64": 1e-12, "fp32": 1e-5, "bf16x2": 1e-4, "bf16x3": 1e-5}
 DTYPE_TEXT = {"fp64": "f64", "fp32": "f32 sketch products, f64 QR/solve/residual",
+              "bf16x2": "bf16x2-split sketch products (f32 accumulate), f64 QR/solve/residual",
               "bf16x3": "bf16x3-split sketch products (f32 accumulate), f64 QR/solve/residual"}
 
 
@@ -485,13 +489,13 @@ def main() -> int:
                     help="set the noise so that sigma_{k+1} ~ rho ||A||_2 (overrides --noise)")
     ap.add_argument("--dtype", choices=["c128", "c64"], default="c128",
                     help="storage of A")
-    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16x3"], default="fp64",
+    ap.add_argument("--prec", choices=["fp64", "fp32", "bf16x2", "bf16x3"], default="fp64",
                     help="arithmetic of the sketch products (QR, solve, residual stay double)")
     ap.add_argument("--sketch", choices=["gaussian", "srft"], default="gaussian",
                     help="random operator: Gaussian G, or the paper's S F D (four-step DFT "
                          "form when m is a multiple of 8)")
     ap.add_argument("--compare-fp64", action="store_true",
-                    help="with --prec fp32/bf16x3: also run the FP64-products ID on the same A "
+                    help="with --prec fp32/bf16x2/bf16x3: also run the FP64-products ID on the same A "
                          "(same seed) and report J agreement and the P and sigma differences")
     ap.add_argument("--cpu-cols", type=int, default=512)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -579,7 +583,7 @@ def main() -> int:
 
     def step():
         return rid.rid_decompose(h, A, k, l, seed=0, q=q, J=J, P=P, sigma=sigma, prec=prec,
-                                 rank_tol=1e-12 if prec == rid.RID_FP64 else 1e-5)
+                                 rank_tol=RANK_TOL[args.prec])
 
     for i in range(args.warmup):
         step()
@@ -616,10 +620,11 @@ def main() -> int:
                                "avg_launch_ms": kern[name]["avg_ms"]}
     if "sketch" in kern and args.sketch == "gaussian":
         avg = kern["sketch"]["avg_ms"] * 1e-3
-        # the bf16 split form does six bf16 products per real product
-        flops = 8.0 * l * m * n * (6 if args.prec == "bf16x3" else 1)
+        # the bf16 split forms do six (three) bf16 products per real product
+        flops = 8.0 * l * m * n * {"bf16x3": 6, "bf16x2": 3}.get(args.prec, 1)
         ach = flops / avg / 1e12
-        peak = {"fp64": FP64_PEAK_TFS, "fp32": FP32_PEAK_TFS, "bf16x3": BF16_PEAK_TFS}[args.prec]
+        peak = {"fp64": FP64_PEAK_TFS, "fp32": FP32_PEAK_TFS, "bf16x2": BF16_PEAK_TFS,
+                "bf16x3": BF16_PEAK_TFS}[args.prec]
         rooflines["sketch"] = {"bound": "mfma", "achieved": ach, "peak": peak,
                                "unit": "TFLOP/s", "frac": ach / peak,
                                "traffic": _traffic("sketch", "sketch_f64.hip", default_cfg),

@@ -34,10 +34,11 @@
  *    status word of the handle by rid_pivqr; rid_query_status() reads it.
  *    rid_decompose() reads it itself and redraws G with the next seed, as
  *    Sec. 2 prescribes for this failure.
- *  - Arithmetic: `RID_FP64` runs every step in double precision.  The QR,
- *    the triangular solve and every norm and residual accumulation are
- *    double (the residual sums are compensated, i.e. double-double) in every
- *    precision mode; a lower `rid_prec` only changes the sketch product.
+ *  - Arithmetic: `RID_FP64` runs every step in double precision, with the
+ *    residual's sums over A compensated (double-double).  The QR, the
+ *    triangular solve and the norms are double in every precision mode; a
+ *    lower `rid_prec` changes the sketch product, and the residual's sums
+ *    over A become plain double (rid_set_residual chooses otherwise).
  *  - Determinism: no floating-point atomics; a call repeated with the same
  *    inputs on the same device gives bit-identical outputs.
  */
@@ -69,11 +70,16 @@ typedef enum { RID_C128 = 0, RID_C64 = 1 } rid_dtype;
 /* Arithmetic of the sketch product Y = G A (Y itself is always complex128).
  *   RID_FP64   double products and accumulation (either storage type);
  *   RID_FP32   single-precision products, single accumulation;
+ *   RID_BF16X2 each operand split into two bfloat16 terms (16 significant
+ *              bits), the three leading bf16 products per real product on
+ *              the bf16 matrix cores, single accumulation (error near
+ *              2^-16 relative);
  *   RID_BF16X3 each operand split into three bfloat16 terms, the six
- *              leading bf16 products per real product on the bf16 matrix
- *              cores, single accumulation (FP32-level error).  Single IDs
- *              only: batches take RID_FP64 or RID_FP32.                 */
-typedef enum { RID_FP64 = 0, RID_FP32 = 1, RID_BF16X3 = 2 } rid_prec;
+ *              leading bf16 products per real product, single accumulation
+ *              (FP32-level error).
+ * The two bf16 forms are built for single IDs: batches take RID_FP64 or
+ * RID_FP32 and return RID_ERR_UNSUPPORTED for them.                     */
+typedef enum { RID_FP64 = 0, RID_FP32 = 1, RID_BF16X2 = 2, RID_BF16X3 = 3 } rid_prec;
 
 /* ---------------------------------------------------------------- handle */
 
@@ -217,17 +223,44 @@ rid_status rid_interp(rid_handle h, hipStream_t stream, int64_t n, int64_t k, co
 
 /* ---------------------------------------------------------------- step 4 */
 
+/* Accumulation of the residual's passes over A (rid_residual,
+ * rid_decompose, batches).  The O(n k) side steps are compensated in every
+ * kind; norms and the iteration vectors are double.                     */
+typedef enum {
+  RID_RESIDUAL_AUTO = 0, /* by the sketch arithmetic `prec` of the call: DOT2
+                            for RID_FP64, FP64 for the reduced-precision
+                            forms (default)                               */
+  RID_RESIDUAL_DOT2 = 1, /* compensated sums (Ogita-Rump-Oishi Dot2), x~ and
+                            u as double-double: agrees with an exact
+                            iteration to ~1e-10 even where E = A - A(:,J) P
+                            is 1e-10 of A                                  */
+  RID_RESIDUAL_FP64 = 2, /* plain double FMA chains, x~ rounded to double:
+                            relative error about u sqrt(m + n) ||A||_F /
+                            sigma, far below the reduced-precision forms'
+                            own error                                     */
+  RID_RESIDUAL_FP32 = 3  /* single-precision products and sums within each
+                            workgroup's slab, partials combined in double
+                            (a reported variant: error about 2^-24 sqrt(slab)
+                            ||A||_F / sigma)                               */
+} rid_residual_kind;
+
+/* Select the residual accumulation of this handle's later calls.
+ * Errors: INVALID_ARG.                                                   */
+rid_status rid_set_residual(rid_handle h, int kind);
+
 /* Power-iteration estimate of ||E||_2, E = A - A(:, J) P (the error of
  * Table 5), without forming E: E x = A x~ with x~ = x - S_J (P x), and
  * E^H z = u - P^H u_J with u = A^H z.  Start vector x0 = rid_gaussian(seed,
  * stream_id 1) (1 x n), normalised.  Step t = 1..q: z = E x,
  * sigma_t = ||z||_2, and for t < q, x = E^H z / ||E^H z||; if E^H z = 0 the
- * iteration stops and later sigma_t repeat the last value.  All sums over A
- * are compensated (double-double).  Outputs: *sigma (device double) =
- * sigma_q; hist (device, q doubles, or null) = sigma_1..sigma_q.
+ * iteration stops and later sigma_t repeat the last value.  The sums over
+ * A take the handle's residual kind (rid_set_residual); by default they are
+ * compensated (double-double) for prec = RID_FP64 and plain double for the
+ * reduced-precision forms (RID_FP32, RID_BF16X2, RID_BF16X3), whose ID
+ * error is far above plain double rounding.  Outputs: *sigma (device
+ * double) = sigma_q; hist (device, q doubles, or null) = sigma_1..sigma_q.
  * A: m x n (lda >= m) of type `dtype`; P: k x n complex128 (ldp >= k);
- * J: k device indices.  `prec` must be RID_FP64 (the residual is always
- * accumulated in double).  Requires 0 <= k <= n, q >= 1.
+ * J: k device indices.  Requires 0 <= k <= n, k <= 1024, q >= 1.
  * Errors: INVALID_ARG, UNSUPPORTED, NOMEM, HIP.                           */
 rid_status rid_residual(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
                         int64_t m, int64_t n, int64_t k, const void *A, int64_t lda,
@@ -250,6 +283,21 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
                          int64_t lda, uint64_t seed, int q, int max_retries, double rank_tol,
                          int64_t *J, void *P, int64_t ldp, double *sigma,
                          uint64_t *seed_used);
+
+/* As rid_decompose, with a caller-supplied operator G0 (l x m complex128,
+ * row-major, entry (i, p) at G0[i * ldg + p], ldg >= m, 16-byte aligned) in
+ * place of the first draw's: if G0 A has rank < k, the redraws use the
+ * operators of seed + 1, seed + 2, ... (Sec. 2 failure remedy), so
+ * *seed_used = seed + a for the a-th redraw; if the first draw succeeds,
+ * *seed_used = seed and the start vector of the power iteration is that of
+ * seed.  A test hook for the redraw path (G0 rank-deficient on purpose).
+ * Errors: as rid_decompose; INVALID_ARG also for a null G0.              */
+rid_status rid_decompose_explicit(rid_handle h, hipStream_t stream, rid_dtype dtype,
+                                  rid_prec prec, int64_t m, int64_t n, int64_t k, int64_t l,
+                                  const void *A, int64_t lda, const void *G0, int64_t ldg,
+                                  uint64_t seed, int q, int max_retries, double rank_tol,
+                                  int64_t *J, void *P, int64_t ldp, double *sigma,
+                                  uint64_t *seed_used);
 
 /* ---------------------------------------------------------------- SVD */
 

@@ -33,20 +33,26 @@ RID_C128 = 0
 RID_C64 = 1
 RID_FP64 = 0
 RID_FP32 = 1
-RID_BF16X3 = 2
+RID_BF16X2 = 2
+RID_BF16X3 = 3
 
 EXPORTED = ["rid_create", "rid_destroy", "rid_status_string", "rid_last_hip_error",
             "rid_reserve", "rid_gaussian", "rid_sketch", "rid_sketch_explicit", "rid_pivqr",
-            "rid_interp", "rid_residual", "rid_decompose", "rid_query_status", "rid_profile",
+            "rid_interp", "rid_residual", "rid_decompose", "rid_decompose_explicit",
+            "rid_query_status", "rid_profile",
             "rid_profile_read", "rid_set_sketch", "rid_srft_operator", "rid_decompose_batched",
             "rid_server_create", "rid_server_submit", "rid_server_drain", "rid_server_stats",
             "rid_server_destroy", "rid_set_batch_plan", "rid_get_batch_plan", "rid_tune_batched",
-            "rid_set_qr", "rid_svd"]
+            "rid_set_qr", "rid_set_residual", "rid_svd"]
 
 RID_SKETCH_GAUSSIAN = 0
 RID_SKETCH_SRFT = 1
 RID_QR_HOUSEHOLDER = 0
 RID_QR_CGS2 = 1
+RID_RESIDUAL_AUTO = 0
+RID_RESIDUAL_DOT2 = 1
+RID_RESIDUAL_FP64 = 2
+RID_RESIDUAL_FP32 = 3
 
 RID_KERNEL_SKETCH = 0
 RID_KERNEL_AX = 1
@@ -110,6 +116,8 @@ _sig = {
                       _P], _I),
     "rid_decompose": ([_P, _P, _I, _I, _I64, _I64, _I64, _I64, _P, _I64, _U64, _I, _I, _D, _P,
                        _P, _I64, _P, ctypes.POINTER(_U64)], _I),
+    "rid_decompose_explicit": ([_P, _P, _I, _I, _I64, _I64, _I64, _I64, _P, _I64, _P, _I64,
+                                _U64, _I, _I, _D, _P, _P, _I64, _P, ctypes.POINTER(_U64)], _I),
     "rid_query_status": ([_P, _P], _I),
     "rid_profile": ([_P, _I], _I),
     "rid_set_sketch": ([_P, _I], _I),
@@ -122,6 +130,7 @@ _sig = {
     "rid_server_drain": ([_P], _I),
     "rid_set_batch_plan": ([_P, _I64, _I64, _I], _I),
     "rid_set_qr": ([_P, _I], _I),
+    "rid_set_residual": ([_P, _I], _I),
     "rid_svd": ([_P, _P, _I, _I64, _I64, _I64, _P, _I64, _P, _P, _I64, _P, _I64, _P, _P, _I64,
                  ctypes.POINTER(_I)], _I),
     "rid_get_batch_plan": ([_P, ctypes.POINTER(_I64), ctypes.POINTER(_I64), ctypes.POINTER(_I)],
@@ -247,6 +256,12 @@ def rid_gaussian(h, rows: int, cols: int, seed: int, stream_id: int, out=None, s
     return out
 
 
+def rid_set_residual(h, kind: int) -> None:
+    """Choose the accumulation of the residual's passes over A for later
+    rid_residual / rid_decompose / batched calls (RID_RESIDUAL_*)."""
+    _check(_L.rid_set_residual(h, kind), "rid_set_residual")
+
+
 def rid_set_qr(h, kind: int) -> None:
     """Choose the pivoted-QR method (RID_QR_HOUSEHOLDER or RID_QR_CGS2) of
     later rid_pivqr / rid_decompose calls."""
@@ -369,6 +384,34 @@ def rid_decompose(h, A, k: int, l: int, seed: int = 0, q: int = 10, max_retries:
     _check(_L.rid_decompose(h, _stream(stream), _dtype_code(A), prec, m, n, k, l, _ptr(A),
                               lda, seed, q, max_retries, rank_tol, _ptr(J), _ptr(P), ldp,
                               _ptr(sigma), ctypes.byref(used)), "rid_decompose")
+    return J, P, sigma, int(used.value)
+
+
+def rid_decompose_explicit(h, A, G0, k: int, seed: int = 0, q: int = 10,
+                           max_retries: int = 3, rank_tol: float = 1e-12, J=None, P=None,
+                           sigma=None, prec: int = RID_FP64, stream=None):
+    """rid_decompose whose first draw uses the row-major (l, m) operator G0;
+    redraws use the operators of seed + 1, ...  Returns (J, P, sigma,
+    seed_used).  Synchronises."""
+    torch = _torch()
+    m, n = A.shape
+    l = G0.shape[0]
+    lda = _ld_colmajor(A, "A")
+    if G0.dim() != 2 or G0.shape[1] != m or (G0.stride(1) != 1 and m > 1):
+        raise ValueError("G0 must be a row-major (l, m) tensor")
+    ldg = max(G0.stride(0), m, 1)
+    if J is None:
+        J = torch.empty(k, dtype=torch.int64, device="cuda")
+    if P is None:
+        P = _new_colmajor(k, n, torch.complex128)
+    ldp = _ld_colmajor(P, "P")
+    if sigma is None:
+        sigma = torch.zeros(1, dtype=torch.float64, device="cuda")
+    used = _U64(0)
+    _check(_L.rid_decompose_explicit(h, _stream(stream), _dtype_code(A), prec, m, n, k, l,
+                                       _ptr(A), lda, _ptr(G0), ldg, seed, q, max_retries,
+                                       rank_tol, _ptr(J), _ptr(P), ldp, _ptr(sigma),
+                                       ctypes.byref(used)), "rid_decompose_explicit")
     return J, P, sigma, int(used.value)
 
 

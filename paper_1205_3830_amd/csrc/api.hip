@@ -193,7 +193,7 @@ rid_status rid_reserve(rid_handle h, int64_t max_m, int64_t max_n, int64_t max_l
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
   size_t need = 0;
-  for (rid_prec pr : {RID_FP64, RID_FP32}) {
+  for (rid_prec pr : {RID_FP64, RID_FP32, RID_BF16X3}) {
     const size_t sk = bytes_sketch(RID_C128, pr, max_m, max_n, max_l, true);
     const size_t d = std::max(bytes_decomp(RID_C128, pr, max_m, max_n, max_k, max_l, 1,
                                            RID_QR_HOUSEHOLDER, h->sketch_kind),
@@ -241,7 +241,7 @@ static rid_status check_sketch_args(rid_handle h, rid_dtype dtype, rid_prec prec
   if (n > 0 && (!Y || !aligned(Y, 16))) return RID_ERR_INVALID_ARG;
   if (m > 0 && n > 0 && !A) return RID_ERR_INVALID_ARG;
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
-  if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
+  if (!prec_valid(prec)) return RID_ERR_INVALID_ARG;
   if (A && !aligned(A, dtype == RID_C128 ? 16 : 8)) return RID_ERR_INVALID_ARG;
   if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
   if (h->sketch_kind == RID_SKETCH_SRFT && m > 0x7FFFFFFFll) return RID_ERR_UNSUPPORTED;
@@ -342,17 +342,23 @@ rid_status rid_residual(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_p
       (k > 0 && (!J || !P || ldp < k)) || (P && !aligned(P, 16)))
     return RID_ERR_INVALID_ARG;
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
-  if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
+  if (!prec_valid(prec)) return RID_ERR_INVALID_ARG;
   if (!aligned(A, dtype == RID_C128 ? 16 : 8)) return RID_ERR_INVALID_ARG;
-  if (prec != RID_FP64 || k > 1024) return RID_ERR_UNSUPPORTED;
+  if (k > 1024) return RID_ERR_UNSUPPORTED;
   DeviceGuard g(h->device);
   if (g.err != hipSuccess) return fail_hip(h, g.err);
   rid_status s = ensure_ws(h, residual_ws_bytes(m, n, k, q));
   if (s != RID_OK) return s;
   hipError_t e = launch_residual(stream, dtype, m, n, k, A, lda, J,
                                  static_cast<const double2 *>(P), k > 0 ? ldp : 1, q, seed,
-                                 sigma, hist, h->ws, &h->prof);
+                                 sigma, hist, h->ws, &h->prof, res_acc(h->residual_kind, prec));
   return e == hipSuccess ? RID_OK : fail_hip(h, e);
+}
+
+rid_status rid_set_residual(rid_handle h, int kind) {
+  if (!h || kind < RID_RESIDUAL_AUTO || kind > RID_RESIDUAL_FP32) return RID_ERR_INVALID_ARG;
+  h->residual_kind = kind;
+  return RID_OK;
 }
 
 rid_status rid_set_qr(rid_handle h, int kind) {
@@ -403,18 +409,26 @@ rid_status rid_query_status(rid_handle h, hipStream_t stream) {
   return static_cast<rid_status>(v);
 }
 
-rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
-                         int64_t m, int64_t n, int64_t k, int64_t l, const void *A,
-                         int64_t lda, uint64_t seed, int q, int max_retries, double rank_tol,
-                         int64_t *J, void *P, int64_t ldp, double *sigma,
-                         uint64_t *seed_used) {
+}  // extern "C"
+
+namespace {
+
+// The whole ID (Sec. 2).  Draw a = 0, 1, ... uses the operator of seed + a,
+// except that a caller-supplied G0 (l x m, row-major, ldg) replaces the
+// first draw's operator.
+rid_status decompose_impl(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                          int64_t m, int64_t n, int64_t k, int64_t l, const void *A,
+                          int64_t lda, const double2 *G0, int64_t ldg, uint64_t seed, int q,
+                          int max_retries, double rank_tol, int64_t *J, void *P, int64_t ldp,
+                          double *sigma, uint64_t *seed_used) {
   if (!h || k < 1 || k > l || k > n || l > m || q < 1 || max_retries < 0 || lda < m || !A ||
       !J || !P || !sigma || ldp < k || !aligned(P, 16) || !(rank_tol >= 0.0) ||
       !std::isfinite(rank_tol) || n > 0x7FFFFFFFll || l > 0xFFFFFFFFll)
     return RID_ERR_INVALID_ARG;
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
-  if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
+  if (!prec_valid(prec)) return RID_ERR_INVALID_ARG;
   if (!aligned(A, dtype == RID_C128 ? 16 : 8)) return RID_ERR_INVALID_ARG;
+  if (G0 && (ldg < m || !aligned(G0, 16))) return RID_ERR_INVALID_ARG;
   if (!sketch_supported(dtype, prec)) return RID_ERR_UNSUPPORTED;
   if (!pivqr_supported(l) || !interp_supported(k)) return RID_ERR_UNSUPPORTED;
   if (h->sketch_kind == RID_SKETCH_SRFT && m > 0x7FFFFFFFll) return RID_ERR_UNSUPPORTED;
@@ -430,7 +444,10 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
   for (int attempt = 0; attempt <= max_retries; ++attempt) {
     const uint64_t sd = seed + static_cast<uint64_t>(attempt);
     hipError_t e;
-    if (fft) {
+    if (G0 && attempt == 0) {
+      e = launch_sketch(stream, dtype, prec, m, n, l, A, lda, G0, ldg, d.Y, l, d.part,
+                        &h->prof);
+    } else if (fft) {
       e = launch_srft_sketch(stream, dtype, m, n, l, A, lda, sd, d.Y, l, d.scratch, &h->prof);
     } else {
       e = launch_operator(stream, h->sketch_kind, l, m, sd, d.G, m);
@@ -455,13 +472,38 @@ rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_
     if (e == hipSuccess)
       e = launch_residual(stream, dtype, m, n, k, A, lda, d.perm,
                           static_cast<const double2 *>(P), ldp, q, sd, sigma, nullptr, d.scratch,
-                          &h->prof);
+                          &h->prof, res_acc(h->residual_kind, prec));
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
     if (e != hipSuccess) return fail_hip(h, e);
     if (seed_used) *seed_used = sd;
     return RID_OK;
   }
   return RID_ERR_RANK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rid_status rid_decompose(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                         int64_t m, int64_t n, int64_t k, int64_t l, const void *A,
+                         int64_t lda, uint64_t seed, int q, int max_retries, double rank_tol,
+                         int64_t *J, void *P, int64_t ldp, double *sigma,
+                         uint64_t *seed_used) {
+  return decompose_impl(h, stream, dtype, prec, m, n, k, l, A, lda, nullptr, 0, seed, q,
+                        max_retries, rank_tol, J, P, ldp, sigma, seed_used);
+}
+
+rid_status rid_decompose_explicit(rid_handle h, hipStream_t stream, rid_dtype dtype,
+                                  rid_prec prec, int64_t m, int64_t n, int64_t k, int64_t l,
+                                  const void *A, int64_t lda, const void *G0, int64_t ldg,
+                                  uint64_t seed, int q, int max_retries, double rank_tol,
+                                  int64_t *J, void *P, int64_t ldp, double *sigma,
+                                  uint64_t *seed_used) {
+  if (!G0) return RID_ERR_INVALID_ARG;
+  return decompose_impl(h, stream, dtype, prec, m, n, k, l, A, lda,
+                        static_cast<const double2 *>(G0), ldg, seed, q, max_retries, rank_tol, J,
+                        P, ldp, sigma, seed_used);
 }
 
 rid_status rid_svd(rid_handle h, hipStream_t stream, rid_dtype dtype, int64_t m, int64_t n,

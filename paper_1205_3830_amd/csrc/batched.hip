@@ -123,7 +123,8 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   for (int i = 0; i < count; ++i)
     offQr[i] = qc.take_off<char>(pivqr_job_ws_bytes(bj[i].l, bj[i].n));
   GroupedHost res;
-  residual_batch_setup(bj, count, dtype, h->batch_res_block_bytes, h->batch_ahz_cpw, nullptr,
+  const int acc = res_acc(h->residual_kind, prec);
+  residual_batch_setup(bj, count, dtype, h->batch_res_block_bytes, h->batch_ahz_cpw, acc, nullptr,
                        &res);
   const size_t scratch = std::max(std::max(sc.off, qc.off), res.ws_bytes) + 256;
 
@@ -190,7 +191,7 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   char *base = static_cast<char *>(h->ws);
   char *pbase = base + tabbytes;
   char *sbase = pbase + persist;
-  residual_batch_setup(bj, count, dtype, h->batch_res_block_bytes, h->batch_ahz_cpw, sbase,
+  residual_batch_setup(bj, count, dtype, h->batch_res_block_bytes, h->batch_ahz_cpw, acc, sbase,
                        &res);
   int *dstatus = reinterpret_cast<int *>(pbase + offStatus);
   for (int i = 0; i < count; ++i) {
@@ -257,7 +258,7 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
     if (e != hipSuccess) return e;
     e = launch_interp_batch(st, kmax, d_in, d_tin, static_cast<int64_t>(t_in.size()), prof);
     if (e != hipSuccess) return e;
-    return launch_residual_batch(st, dtype, d_res, d_tres, res, q, prof);
+    return launch_residual_batch(st, dtype, d_res, d_tres, res, q, acc, prof);
   };
 
   if (!prof && h->batch_graph && use_graph()) {
@@ -297,7 +298,7 @@ extern "C" rid_status rid_decompose_batched(rid_handle h, hipStream_t stream, ri
       !(rank_tol >= 0.0) || rank_tol > 1.0)
     return RID_ERR_INVALID_ARG;
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
-  if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
+  if (!prec_valid(prec)) return RID_ERR_INVALID_ARG;
   if (!sketch_supported(dtype, prec) || !batch_prec_supported(prec)) return RID_ERR_UNSUPPORTED;
   const size_t align = dtype == RID_C128 ? 16 : 8;
   std::vector<RidBatchJob> bj(count);
@@ -392,7 +393,7 @@ extern "C" rid_status rid_tune_batched(rid_handle h, hipStream_t stream, rid_dty
   constexpr int kCand = 6;
   if (!h || count < 1 || !jobs || q < 1) return RID_ERR_INVALID_ARG;
   if (dtype != RID_C128 && dtype != RID_C64) return RID_ERR_INVALID_ARG;
-  if (prec != RID_FP64 && prec != RID_FP32 && prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
+  if (!prec_valid(prec)) return RID_ERR_INVALID_ARG;
   if (!sketch_supported(dtype, prec) || !batch_prec_supported(prec)) return RID_ERR_UNSUPPORTED;
   const size_t align = dtype == RID_C128 ? 16 : 8;
   std::vector<RidBatchJob> bj(count);

@@ -7,6 +7,15 @@
 // FMA, TwoSum for the running sum, errors collected in a second double) and
 // x~, u and the P-corrections are carried as double-double pairs.
 //
+// The two passes over A take one of three accumulations (RES_*, per job):
+//   RES_DOT2  the compensated sums above (the double-precision ID);
+//   RES_FP64  plain double FMA chains, x~ rounded to double: for the
+//             reduced-precision forms, whose error is far above the
+//             rounding of plain double sums (u sqrt(m + n) ||A||_F / sigma);
+//   RES_FP32  single-precision products and sums within a workgroup's
+//             slab, the partials combined in double (reported variant).
+// The O(n k) side steps stay compensated in every mode.
+//
 // The two passes over A are the HBM-bound kernels of the whole ID; both read
 // A with non-temporal loads (A is touched once per pass):
 //   ax  : z = A x~ ; a workgroup streams a 512-row slab of a range of
@@ -82,6 +91,7 @@ ResPlan plan_res(int64_t m, int64_t n, int64_t k, int64_t target_blocks, int ahz
 // One power-iteration problem: sizes, inputs, plan and workspace.
 struct ResJob {
   int64_t m, n, k, lda, ldp;
+  int acc;   // accumulation of the passes over A (RES_DOT2, RES_FP64, RES_FP32)
   const void *A;
   const int64_t *J;
   const double2 *P;
@@ -267,7 +277,7 @@ struct RowPair<float2> {
 // WIDE: the fast path below (one ID's large slabs); the grouped kernels of a
 // batch leave it out, as their small jobs rarely take it and would pay its
 // registers
-template <class TA, bool WIDE>
+template <class TA, bool WIDE, int ACC>
 RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
   using RP = RowPair<TA>;
   if (stopped(r.scal)) return;
@@ -283,22 +293,48 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
   const double2 *__restrict__ xtl = r.xtl;
   double s0r = 0, c0r = 0, s0i = 0, c0i = 0;
   double s1r = 0, c1r = 0, s1i = 0, c1i = 0;
+  float f0r = 0.0f, f0i = 0.0f, f1r = 0.0f, f1i = 0.0f;
   const TA *a0p = A + (ok0 ? i0 : 0);
   const TA *a1p = A + (ok1 ? i1 : 0);
   // x~ = xh + xl; xl is zero except on the k skeleton columns, so the xl
   // products (which only add to the compensation) are skipped for a group of
-  // columns whose xl are all zero -- a uniform test, no divergence
+  // columns whose xl are all zero -- a uniform test, no divergence.  The
+  // plain modes round x~ to xh and never read xl.
   auto acc_hi = [&](const double2 &a0, const double2 &a1, const double2 &xh) {
-    dot2_acc(s0r, c0r, a0.x, xh.x);
-    dot2_acc(s0r, c0r, -a0.y, xh.y);
-    dot2_acc(s0i, c0i, a0.x, xh.y);
-    dot2_acc(s0i, c0i, a0.y, xh.x);
-    dot2_acc(s1r, c1r, a1.x, xh.x);
-    dot2_acc(s1r, c1r, -a1.y, xh.y);
-    dot2_acc(s1i, c1i, a1.x, xh.y);
-    dot2_acc(s1i, c1i, a1.y, xh.x);
+    if constexpr (ACC == RES_DOT2) {
+      dot2_acc(s0r, c0r, a0.x, xh.x);
+      dot2_acc(s0r, c0r, -a0.y, xh.y);
+      dot2_acc(s0i, c0i, a0.x, xh.y);
+      dot2_acc(s0i, c0i, a0.y, xh.x);
+      dot2_acc(s1r, c1r, a1.x, xh.x);
+      dot2_acc(s1r, c1r, -a1.y, xh.y);
+      dot2_acc(s1i, c1i, a1.x, xh.y);
+      dot2_acc(s1i, c1i, a1.y, xh.x);
+    } else if constexpr (ACC == RES_FP64) {
+      s0r = fma(a0.x, xh.x, s0r);
+      s0r = fma(-a0.y, xh.y, s0r);
+      s0i = fma(a0.x, xh.y, s0i);
+      s0i = fma(a0.y, xh.x, s0i);
+      s1r = fma(a1.x, xh.x, s1r);
+      s1r = fma(-a1.y, xh.y, s1r);
+      s1i = fma(a1.x, xh.y, s1i);
+      s1i = fma(a1.y, xh.x, s1i);
+    } else {
+      const float xr = static_cast<float>(xh.x), xi = static_cast<float>(xh.y);
+      const float a0r = static_cast<float>(a0.x), a0i = static_cast<float>(a0.y);
+      const float a1r = static_cast<float>(a1.x), a1i = static_cast<float>(a1.y);
+      f0r = fmaf(a0r, xr, f0r);
+      f0r = fmaf(-a0i, xi, f0r);
+      f0i = fmaf(a0r, xi, f0i);
+      f0i = fmaf(a0i, xr, f0i);
+      f1r = fmaf(a1r, xr, f1r);
+      f1r = fmaf(-a1i, xi, f1r);
+      f1i = fmaf(a1r, xi, f1i);
+      f1i = fmaf(a1i, xr, f1i);
+    }
   };
   auto acc_lo = [&](const double2 &a0, const double2 &a1, const double2 &xl) {
+    if constexpr (ACC != RES_DOT2) return;
     c0r = fma(a0.x, xl.x, c0r);
     c0r = fma(-a0.y, xl.y, c0r);
     c0i = fma(a0.x, xl.y, c0i);
@@ -327,10 +363,12 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
             RP::load(a0p, a1p, true, true, (j + u) * lda, pair, a0[u], a1[u]);
         }
         bool lo = false;
+        if constexpr (ACC == RES_DOT2) {
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          xl[u] = xtl[j + u];
-          lo = lo || xl[u].x != 0.0 || xl[u].y != 0.0;
+          for (int u = 0; u < 8; ++u) {
+            xl[u] = xtl[j + u];
+            lo = lo || xl[u].x != 0.0 || xl[u].y != 0.0;
+          }
         }
 #pragma unroll
         for (int u = 0; u < 8; ++u) acc_hi(a0[u], a1[u], xth[j + u]);
@@ -346,10 +384,12 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
 #pragma unroll
     for (int u = 0; u < 4; ++u) RP::load(a0p, a1p, ok0, ok1, (j + u) * lda, pair, a0[u], a1[u]);
     bool lo = false;
+    if constexpr (ACC == RES_DOT2) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      xl[u] = xtl[j + u];
-      lo = lo || xl[u].x != 0.0 || xl[u].y != 0.0;
+      for (int u = 0; u < 4; ++u) {
+        xl[u] = xtl[j + u];
+        lo = lo || xl[u].x != 0.0 || xl[u].y != 0.0;
+      }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) acc_hi(a0[u], a1[u], xth[j + u]);
@@ -362,7 +402,13 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
     double2 a0, a1;
     RP::load(a0p, a1p, ok0, ok1, j * lda, pair, a0, a1);
     acc_hi(a0, a1, xth[j]);
-    acc_lo(a0, a1, xtl[j]);
+    if constexpr (ACC == RES_DOT2) acc_lo(a0, a1, xtl[j]);
+  }
+  if constexpr (ACC == RES_FP32) {
+    s0r = f0r;
+    s0i = f0i;
+    s1r = f1r;
+    s1i = f1i;
   }
   double *zp = r.zpart + by * m * 4;
   if (ok0) {
@@ -421,7 +467,7 @@ RID_DEV void sigma_final_body(const ResJob &r, int t) {
 // u partials: columns [32 bx, +32) x rows of split by; z chunk staged in LDS.
 // A lane takes one row per step for complex128 and two adjacent rows (one
 // 16-byte load when aligned) for complex64.
-template <class TA, int AHZ_CPW>
+template <class TA, int AHZ_CPW, int ACC>
 RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
   constexpr int AHZ_COLS = 4 * AHZ_CPW;  // columns per workgroup
   constexpr bool C64 = sizeof(TA) == 8;
@@ -439,20 +485,36 @@ RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
   const int wave = threadIdx.x >> 6;
   const int64_t jb = bx * AHZ_COLS + wave * AHZ_CPW;
   double sr[AHZ_CPW], cr[AHZ_CPW], si[AHZ_CPW], ci[AHZ_CPW];
+  float fr[AHZ_CPW], fi[AHZ_CPW];
   const TA *cp[AHZ_CPW];
   bool cok[AHZ_CPW];
 #pragma unroll
   for (int u = 0; u < AHZ_CPW; ++u) {
     sr[u] = cr[u] = si[u] = ci[u] = 0.0;
+    fr[u] = fi[u] = 0.0f;
     cok[u] = (jb + u) < n;
     cp[u] = A + (cok[u] ? (jb + u) : 0) * lda + r0;
   }
   auto acc = [&](int u, const double2 &a, const double2 &zz) {
     // conj(a) z = (ar zr + ai zi) + i (ar zi - ai zr)
-    dot2_acc(sr[u], cr[u], a.x, zz.x);
-    dot2_acc(sr[u], cr[u], a.y, zz.y);
-    dot2_acc(si[u], ci[u], a.x, zz.y);
-    dot2_acc(si[u], ci[u], -a.y, zz.x);
+    if constexpr (ACC == RES_DOT2) {
+      dot2_acc(sr[u], cr[u], a.x, zz.x);
+      dot2_acc(sr[u], cr[u], a.y, zz.y);
+      dot2_acc(si[u], ci[u], a.x, zz.y);
+      dot2_acc(si[u], ci[u], -a.y, zz.x);
+    } else if constexpr (ACC == RES_FP64) {
+      sr[u] = fma(a.x, zz.x, sr[u]);
+      sr[u] = fma(a.y, zz.y, sr[u]);
+      si[u] = fma(a.x, zz.y, si[u]);
+      si[u] = fma(-a.y, zz.x, si[u]);
+    } else {
+      const float ar = static_cast<float>(a.x), ai = static_cast<float>(a.y);
+      const float zr = static_cast<float>(zz.x), zi = static_cast<float>(zz.y);
+      fr[u] = fmaf(ar, zr, fr[u]);
+      fr[u] = fmaf(ai, zi, fr[u]);
+      fi[u] = fmaf(ar, zi, fi[u]);
+      fi[u] = fmaf(-ai, zr, fi[u]);
+    }
   };
   if (!C64) {
     // software pipelined: the next row's entries are loaded before the
@@ -496,6 +558,13 @@ RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
         acc(u, a0[u], z0);
         acc(u, a1[u], z1);
       }
+    }
+  }
+  if constexpr (ACC == RES_FP32) {
+#pragma unroll
+    for (int u = 0; u < AHZ_CPW; ++u) {
+      sr[u] = fr[u];
+      si[u] = fi[u];
     }
   }
   // value 2u + p of the reduction: column jb + u, real (p = 0) or imaginary part
@@ -586,7 +655,7 @@ enum Step : int {
   ST_W, ST_AHZ4, ST_COUNT
 };
 
-template <class TA, int STEP, bool WIDE>
+template <class TA, int STEP, bool WIDE, int ACC>
 RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
   if constexpr (STEP == ST_X0) x0_body(r, bx);
   if constexpr (STEP == ST_WNORM) wnorm_final_body(r);
@@ -594,25 +663,41 @@ RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
   if constexpr (STEP == ST_XTINIT) xt_init_body(r, bx);
   if constexpr (STEP == ST_PXP) px_partial_body(r, bx);
   if constexpr (STEP == ST_PXF) px_final_body(r, bx);
-  if constexpr (STEP == ST_AX) ax_body<TA, WIDE>(r, bx, by);
+  if constexpr (STEP == ST_AX) ax_body<TA, WIDE, ACC>(r, bx, by);
   if constexpr (STEP == ST_ZF) z_final_body(r, bx);
   if constexpr (STEP == ST_SIGMA) sigma_final_body(r, t);
-  if constexpr (STEP == ST_AHZ) ahz_body<TA, 8>(r, bx, by);
-  if constexpr (STEP == ST_AHZ4) ahz_body<TA, 4>(r, bx, by);
+  if constexpr (STEP == ST_AHZ) ahz_body<TA, 8, ACC>(r, bx, by);
+  if constexpr (STEP == ST_AHZ4) ahz_body<TA, 4, ACC>(r, bx, by);
   if constexpr (STEP == ST_UF) u_final_body(r, bx);
   if constexpr (STEP == ST_W) w_body(r, bx);
 }
 
-template <class TA, int STEP>
+template <class TA, int STEP, int ACC>
 __global__ __launch_bounds__(256) void step_single(ResJob r, int t) {
-  run_step<TA, STEP, true>(r, blockIdx.x, blockIdx.y, t);
+  run_step<TA, STEP, true, ACC>(r, blockIdx.x, blockIdx.y, t);
 }
 
-template <class TA, int STEP>
+template <class TA, int STEP, int ACC>
 __global__ __launch_bounds__(256) void step_grouped(const ResJob *__restrict__ jobs,
                                                     const int4 *__restrict__ tab, int t) {
   const int4 e = tab[blockIdx.x];
-  run_step<TA, STEP, false>(jobs[e.x], e.y, e.z, t);
+  run_step<TA, STEP, false, ACC>(jobs[e.x], e.y, e.z, t);
+}
+
+// The passes over A take the accumulation `acc` (RES_*); every other step
+// has one form.
+constexpr bool step_over_A(int step) {
+  return step == ST_AX || step == ST_AHZ || step == ST_AHZ4;
+}
+
+template <class F>
+void by_acc(int step, int acc, F &&f) {
+  if (!step_over_A(step) || acc == RES_DOT2)
+    f(std::integral_constant<int, RES_DOT2>());
+  else if (acc == RES_FP64)
+    f(std::integral_constant<int, RES_FP64>());
+  else
+    f(std::integral_constant<int, RES_FP32>());
 }
 
 // blocks of one step for one job (gx by gy)
@@ -638,18 +723,22 @@ void launch_single(hipStream_t st, const ResJob &r, int t, RidProf *prof, int ke
   step_grid(STEP, r, gx, gy);
   if (gx * gy == 0) return;
   ProfScope ps(kernel_id >= 0 ? prof : nullptr, st, kernel_id);
-  hipLaunchKernelGGL((step_single<TA, STEP>),
-                     dim3(static_cast<unsigned>(gx), static_cast<unsigned>(gy)), dim3(256), 0, st,
-                     r, t);
+  by_acc(STEP, r.acc, [&](auto C) {
+    hipLaunchKernelGGL((step_single<TA, STEP, decltype(C)::value>),
+                       dim3(static_cast<unsigned>(gx), static_cast<unsigned>(gy)), dim3(256), 0,
+                       st, r, t);
+  });
 }
 
 template <class TA, int STEP>
 void launch_grouped(hipStream_t st, const ResJob *jobs, const int4 *tab, int64_t count, int t,
-                    RidProf *prof, int kernel_id) {
+                    int acc, RidProf *prof, int kernel_id) {
   if (count == 0) return;
   ProfScope ps(kernel_id >= 0 ? prof : nullptr, st, kernel_id);
-  hipLaunchKernelGGL((step_grouped<TA, STEP>), dim3(static_cast<unsigned>(count)), dim3(256), 0,
-                     st, jobs, tab, t);
+  by_acc(STEP, acc, [&](auto C) {
+    hipLaunchKernelGGL((step_grouped<TA, STEP, decltype(C)::value>),
+                       dim3(static_cast<unsigned>(count)), dim3(256), 0, st, jobs, tab, t);
+  });
 }
 
 // The q-step power iteration as a sequence of step launches; L(step, t, id)
@@ -709,12 +798,12 @@ void single_iteration(hipStream_t st, const ResJob &r, int q, RidProf *prof) {
 
 template <class TA>
 void grouped_iteration(hipStream_t st, const ResJob *jobs, const int4 *dtab,
-                       const GroupedHost &gh, int q, RidProf *prof) {
+                       const GroupedHost &gh, int q, int acc, RidProf *prof) {
   power_iteration(
       [&](int step, int t, int id) {
         by_step<TA>(step, [&](auto S) {
           launch_grouped<TA, decltype(S)::value>(st, jobs, dtab + gh.off[step], gh.cnt[step], t,
-                                                 prof, id);
+                                                 acc, prof, id);
         });
       },
       q);
@@ -742,9 +831,10 @@ size_t residual_ws_bytes(int64_t m, int64_t n, int64_t k, int q) {
 hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t k,
                            const void *A, int64_t lda, const int64_t *J, const double2 *P,
                            int64_t ldp, int q, uint64_t seed, double *sigma, double *hist,
-                           void *ws, RidProf *prof) {
+                           void *ws, RidProf *prof, int acc) {
   if (k > RES_KMAX) return hipErrorInvalidValue;
   ResJob r{};
+  r.acc = acc;
   r.m = m;
   r.n = n;
   r.k = k;
@@ -769,13 +859,14 @@ hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n
 
 // ------------------------------------------------------------------ a batch of IDs
 void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, int64_t block_bytes,
-                          int ahz_cpw, void *ws, GroupedHost *out) {
+                          int ahz_cpw, int acc, void *ws, GroupedHost *out) {
   WsCarve c(ws);
   if (block_bytes < 1) block_bytes = 1;
   std::vector<ResJob> jobs(count);
   for (int i = 0; i < count; ++i) {
     ResJob &r = jobs[i];
     r = ResJob{};
+    r.acc = acc;
     r.m = bj[i].m;
     r.n = bj[i].n;
     r.k = bj[i].k;
@@ -813,11 +904,12 @@ void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, int
 }
 
 hipError_t launch_residual_batch(hipStream_t st, rid_dtype dtype, const void *djobs,
-                                 const int4 *dtab, const GroupedHost &gh, int q, RidProf *prof) {
+                                 const int4 *dtab, const GroupedHost &gh, int q, int acc,
+                                 RidProf *prof) {
   const ResJob *jobs = static_cast<const ResJob *>(djobs);
   if (dtype == RID_C64)
-    grouped_iteration<float2>(st, jobs, dtab, gh, q, prof);
+    grouped_iteration<float2>(st, jobs, dtab, gh, q, acc, prof);
   else
-    grouped_iteration<double2>(st, jobs, dtab, gh, q, prof);
+    grouped_iteration<double2>(st, jobs, dtab, gh, q, acc, prof);
   return hipGetLastError();
 }

@@ -66,6 +66,7 @@ struct rid_ctx {
   RidProf prof;
   int sketch_kind = RID_SKETCH_GAUSSIAN;  // operator drawn by rid_sketch / rid_decompose
   int qr_kind = RID_QR_HOUSEHOLDER;       // method of rid_pivqr / rid_decompose
+  int residual_kind = RID_RESIDUAL_AUTO;  // accumulation of the residual (rid_set_residual)
   hipStream_t cap_stream = nullptr;       // stream used to capture batch graphs
   bool batch_graph = true;                // capture batches into a graph (else launch directly)
   // plan of the batched path (rid_set_batch_plan / rid_tune_batched)
@@ -436,10 +437,14 @@ hipError_t launch_sketch_f64(hipStream_t st, int64_t m, int64_t n, int64_t l, co
                              int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
                              int64_t ldy, void *part, RidProf *prof);
 size_t sketch_bf16_ws_bytes(int64_t m, int64_t n, int64_t l);
+// terms: 2 (RID_BF16X2) or 3 (RID_BF16X3) bf16 terms per operand
 template <class TA>
-hipError_t launch_sketch_bf16(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
-                              int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
-                              int64_t ldy, void *ws, RidProf *prof);
+hipError_t launch_sketch_bf16(hipStream_t st, int terms, int64_t m, int64_t n, int64_t l,
+                              const TA *A, int64_t lda, const double2 *G, int64_t ldg,
+                              double2 *Y, int64_t ldy, void *ws, RidProf *prof);
+
+// A product arithmetic this library knows (rid_prec).
+inline bool prec_valid(int prec) { return prec >= RID_FP64 && prec <= RID_BF16X3; }
 size_t sketch_f32_ws_bytes(int64_t m, int64_t n, int64_t l);
 template <class TA>
 hipError_t launch_sketch_f32(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
@@ -481,14 +486,33 @@ hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R,
 
 // Grouped power iteration over a batch: setup on the host (ws == nullptr
 // only sizes the workspace), then one launch per step for all jobs.
+// Accumulation of the residual's passes over A.
+enum ResAcc : int {
+  RES_DOT2 = 0,  // compensated (double-double) sums
+  RES_FP64 = 1,  // plain double FMA chains
+  RES_FP32 = 2   // single-precision products and sums per slab, partials in double
+};
+
+// The accumulation a handle's residual takes for sketch arithmetic `prec`
+// (rid_set_residual; automatic: compensated for RID_FP64, plain double for
+// the reduced-precision forms).
+inline int res_acc(int residual_kind, int prec) {
+  switch (residual_kind) {
+    case RID_RESIDUAL_DOT2: return RES_DOT2;
+    case RID_RESIDUAL_FP64: return RES_FP64;
+    case RID_RESIDUAL_FP32: return RES_FP32;
+    default: return prec == RID_FP64 ? RES_DOT2 : RES_FP64;
+  }
+}
+
 void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, int64_t block_bytes,
-                          int ahz_cpw, void *ws,
-                          GroupedHost *out);
+                          int ahz_cpw, int acc, void *ws, GroupedHost *out);
 hipError_t launch_residual_batch(hipStream_t st, rid_dtype dtype, const void *djobs,
-                                 const int4 *dtab, const GroupedHost &gh, int q, RidProf *prof);
+                                 const int4 *dtab, const GroupedHost &gh, int q, int acc,
+                                 RidProf *prof);
 
 size_t residual_ws_bytes(int64_t m, int64_t n, int64_t k, int q);
 hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int64_t k,
                            const void *A, int64_t lda, const int64_t *J,
                            const double2 *P, int64_t ldp, int q, uint64_t seed,
-                           double *sigma, double *hist, void *ws, RidProf *prof);
+                           double *sigma, double *hist, void *ws, RidProf *prof, int acc);

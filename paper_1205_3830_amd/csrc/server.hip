@@ -247,7 +247,7 @@ rid_status rid_server_submit(rid_server s, const rid_request *req, uint64_t *tic
       r.fill_bytes < 0 || !(r.rank_tol >= 0.0) || r.rank_tol > 1.0 || r.n > 0x7FFFFFFFll)
     return RID_ERR_INVALID_ARG;
   if (r.dtype != RID_C128 && r.dtype != RID_C64) return RID_ERR_INVALID_ARG;
-  if (r.prec != RID_FP64 && r.prec != RID_FP32 && r.prec != RID_BF16X3) return RID_ERR_INVALID_ARG;
+  if (!prec_valid(r.prec)) return RID_ERR_INVALID_ARG;
   if (!sketch_supported(r.dtype, r.prec) || !pivqr_supported(r.l) || !interp_supported(r.k))
     return RID_ERR_UNSUPPORTED;
   const int64_t es = r.dtype == RID_C128 ? 16 : 8;

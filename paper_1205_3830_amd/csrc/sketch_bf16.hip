@@ -1,13 +1,14 @@
 // sketch_bf16.hip -- randomization step Y = G A (Sec. 2) with products on the
 // bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16), each operand split into
-// three bfloat16 terms x = x_h + x_m + x_l (round to nearest at each step,
-// 24 significant bits in all) and the six leading cross products
-//   a_h b_h + a_h b_m + a_m b_h + a_h b_l + a_m b_m + a_l b_h
-// accumulated in FP32 within a K split; the K splits are summed in double
-// into the complex128 Y.  The dropped products are below 2^-24 relative, so
-// the result carries FP32-level error at three times the bf16 MFMA work, not
-// the FP32 MFMA rate.  The pivoted QR, the solve and the residual that
-// follow stay in double.
+// NT bfloat16 terms (round to nearest at each step), accumulated in FP32
+// within a K split; the K splits are summed in double into the complex128 Y.
+//   NT = 3: x = x_h + x_m + x_l (24 significant bits), the six leading cross
+//           products a_h b_h + a_h b_m + a_m b_h + a_h b_l + a_m b_m + a_l b_h;
+//           the dropped ones are below 2^-24 relative: FP32-level error.
+//   NT = 2: x = x_h + x_l (16 significant bits), the three products
+//           a_h b_h + a_h b_l + a_l b_h; the dropped a_l b_l is below 2^-16
+//           relative: error near 2^-16, at half the matrix-core work.
+// The pivoted QR, the solve and the residual that follow stay in double.
 //
 // Real embedding as in the other sketches, on the A side: [Yr Yi] (l x 2n) =
 // [Gr Gi] (l x 2m) Ae (2m x 2n), with the 2 x 2 blocks [[Re a, Im a],
@@ -21,11 +22,11 @@
 // contiguous bytes of a pre-split plane; real column r16 of a tile is part
 // r16 & 1 of complex column r16 >> 1.
 //
-// G is split once per call into three bf16 planes of [Gr Gi] (row-major,
+// G is split once per call into NT bf16 planes of [Gr Gi] (row-major,
 // 2 m_pad columns, zero padding), reused by every column block.  A
 // workgroup (8 waves) owns 128 columns of A -- 2 groups of 8 per wave, so
 // each G operand read from LDS feeds two MFMA sets -- and RT 16-row tiles of
-// Y.  Per K step of 16 complex rows the workgroup stages the three planes'
+// Y.  Per K step of 16 complex rows the workgroup stages the NT planes'
 // slab in LDS (double buffered, one barrier per step; the next slab and the
 // next A entries are loaded into registers while the current step computes).  The
 // staged slab is l rows, half of the 2l rows a G-side embedding stages for
@@ -40,18 +41,23 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 
 constexpr int BF_RT_MAX = 14;  // row tiles of Y per workgroup (LDS: 3 KB per tile)
 
-RID_DEV void split3(double v, __bf16 &h, __bf16 &m, __bf16 &l) {
-  h = static_cast<__bf16>(static_cast<float>(v));
-  const double r1 = v - static_cast<double>(static_cast<float>(h));
-  m = static_cast<__bf16>(static_cast<float>(r1));
-  const double r2 = r1 - static_cast<double>(static_cast<float>(m));
-  l = static_cast<__bf16>(static_cast<float>(r2));
+// The NT leading bf16 terms of v: t[0] = bf16(v), t[s] = bf16 of what the
+// earlier terms leave (each residual formed exactly in double).
+template <int NT>
+RID_DEV void split_terms(double v, __bf16 (&t)[NT]) {
+  double r = v;
+#pragma unroll
+  for (int s = 0; s < NT; ++s) {
+    t[s] = static_cast<__bf16>(static_cast<float>(r));
+    r -= static_cast<double>(static_cast<float>(t[s]));
+  }
 }
 
-// Gs plane p (p = 0, 1, 2 at p * pstride), entry (i, kappa) at i * ldk + kappa:
-// the three bf16 terms of [Gr Gi](i, kappa) -- Re G(i, kappa/2) for even,
+// Gs plane s (s < NT, at s * pstride), entry (i, kappa) at i * ldk + kappa:
+// bf16 term s of [Gr Gi](i, kappa) -- Re G(i, kappa/2) for even,
 // Im G(i, kappa/2) for odd kappa -- for i < rows_pad, kappa < ldk (zero
 // outside l x 2m).  One thread per complex entry (i, p).
+template <int NT>
 __global__ __launch_bounds__(256) void bf16_split_kernel(int64_t l, int64_t m, int64_t rows_pad,
                                                          int64_t mpad,
                                                          const double2 *__restrict__ G,
@@ -66,12 +72,11 @@ __global__ __launch_bounds__(256) void bf16_split_kernel(int64_t l, int64_t m, i
     const double v[2] = {g.x, g.y};
 #pragma unroll
     for (int part = 0; part < 2; ++part) {
-      __bf16 h, mi, lo;
-      split3(v[part], h, mi, lo);
+      __bf16 t[NT];
+      split_terms<NT>(v[part], t);
       const int64_t at = i * ldk + 2 * p + part;
-      Gs[at] = h;
-      Gs[pstride + at] = mi;
-      Gs[2 * pstride + at] = lo;
+#pragma unroll
+      for (int s = 0; s < NT; ++s) Gs[s * pstride + at] = t[s];
     }
   }
 }
@@ -95,32 +100,34 @@ RID_DEV void to_floats(const TA (&a)[4], float (&v)[8]) {
   }
 }
 
-RID_DEV void split_vec(const float (&v)[8], bf8 &h, bf8 &m, bf8 &l) {
+// The NT bf16 terms of eight floats (residuals exact in float).
+template <int NT>
+RID_DEV void split_vec(const float (&v)[8], bf8 (&t)[NT]) {
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    const __bf16 vh = static_cast<__bf16>(v[e]);
-    const float r1 = v[e] - static_cast<float>(vh);
-    const __bf16 vm = static_cast<__bf16>(r1);
-    const float r2 = r1 - static_cast<float>(vm);
-    h[e] = vh;
-    m[e] = vm;
-    l[e] = static_cast<__bf16>(r2);
+    float r = v[e];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+      const __bf16 x = static_cast<__bf16>(r);
+      t[s][e] = x;
+      r -= static_cast<float>(x);
+    }
   }
 }
 
 // Block (bx, by, bz): columns [128 bx, 128 bx + 128), K split by (rows
 // [by pchunk, ...) of A), row tiles [RT bz, RT bz + RT) of Y.
-template <int RT, class TA>
+template <int RT, class TA, int NT>
 RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restrict__ A,
                               int64_t lda, const __bf16 *__restrict__ Gs, int64_t ldk,
                               int64_t pstride, float *__restrict__ out, int64_t ldo,
                               int64_t split_stride, int64_t pchunk, int64_t bx, int64_t by,
                               int64_t bz) {
-  constexpr int NT = 512;
+  constexpr int NTH = 512;
   constexpr int ROWS = 16 * RT;                 // rows of Y (and of the planes) in the slab
-  constexpr int CHUNKS = 3 * ROWS * 4;          // 16-byte pieces of the slab (3 planes)
-  constexpr int PER = (CHUNKS + NT - 1) / NT;   // pieces staged per thread
-  __shared__ uint4 gsl[2][3][ROWS][4];          // [buffer][plane][row][k-group of 8]
+  constexpr int CHUNKS = NT * ROWS * 4;         // 16-byte pieces of the slab (NT planes)
+  constexpr int PER = (CHUNKS + NTH - 1) / NTH; // pieces staged per thread
+  __shared__ uint4 gsl[2][NT][ROWS][4];         // [buffer][plane][row][k-group of 8]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -150,7 +157,7 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
   auto load_slab = [&](int64_t p0) {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      const int e = tid + NT * r;
+      const int e = tid + NTH * r;
       uint4 v = make_uint4(0u, 0u, 0u, 0u);
       if (e < CHUNKS && p0 < pend) {
         const int plane = e / (ROWS * 4);
@@ -168,7 +175,7 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
   auto store_slab = [&](int b) {
 #pragma unroll
     for (int r = 0; r < PER; ++r) {
-      const int e = tid + NT * r;
+      const int e = tid + NTH * r;
       if (e < CHUNKS) {
         const int plane = e / (ROWS * 4);
         const int rem = e - plane * ROWS * 4;
@@ -199,8 +206,8 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
       for (int g = 0; g < 2; ++g) load_a(Acol[g], p0 + 16 + 4 * q, pend, ok[g], an[g]);
     }
     // B operand: k-index 2p (e = 0) carries [Re a, Im a] for parts c = 0, 1;
-    // k-index 2p+1 carries [-Im a, Re a]; then its three bf16 terms
-    bf8 bh[2], bm[2], bl[2];
+    // k-index 2p+1 carries [-Im a, Re a]; then its NT bf16 terms
+    bf8 bt[2][NT];
 #pragma unroll
     for (int g = 0; g < 2; ++g) {
       float bv[8];
@@ -209,36 +216,44 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
         bv[2 * u] = c ? av[g][2 * u + 1] : av[g][2 * u];
         bv[2 * u + 1] = c ? av[g][2 * u] : -av[g][2 * u + 1];
       }
-      split_vec(bv, bh[g], bm[g], bl[g]);
+      split_vec<NT>(bv, bt[g]);
     }
-    // tiles in groups of TG: each of the six products sweeps TG tiles x 2
-    // column groups, so consecutive MFMAs use 2 TG different accumulators
-    // (no back-to-back dependence); smallest products first
+    // tiles in groups of TG: each product sweeps TG tiles x 2 column groups,
+    // so consecutive MFMAs use 2 TG different accumulators (no back-to-back
+    // dependence); smallest products first
     constexpr int TG = 4;
 #pragma unroll
     for (int t0 = 0; t0 < RT; t0 += TG) {
-      bf8 ah[TG], am[TG], al[TG];
+      bf8 at[NT][TG];
 #pragma unroll
       for (int u = 0; u < TG; ++u) {
         if (t0 + u < RT) {
-          ah[u] = __builtin_bit_cast(bf8, gsl[b][0][16 * (t0 + u) + r16][q]);
-          am[u] = __builtin_bit_cast(bf8, gsl[b][1][16 * (t0 + u) + r16][q]);
-          al[u] = __builtin_bit_cast(bf8, gsl[b][2][16 * (t0 + u) + r16][q]);
+#pragma unroll
+          for (int s = 0; s < NT; ++s)
+            at[s][u] = __builtin_bit_cast(bf8, gsl[b][s][16 * (t0 + u) + r16][q]);
         }
       }
-#define RID_BF_PRODUCT(AX, BX)                                                        \
+      // products of G's term SA and A's term SB, orders summing to <= NT - 1
+#define RID_BF_PRODUCT(SA, SB)                                                        \
   _Pragma("unroll") for (int u = 0; u < TG; ++u) {                                   \
     if (t0 + u < RT) {                                                               \
       _Pragma("unroll") for (int g = 0; g < 2; ++g) acc[g][t0 + u] =                 \
-          __builtin_amdgcn_mfma_f32_16x16x32_bf16(AX[u], BX[g], acc[g][t0 + u], 0, 0, 0); \
+          __builtin_amdgcn_mfma_f32_16x16x32_bf16(at[SA][u], bt[g][SB], acc[g][t0 + u], \
+                                                  0, 0, 0);                          \
     }                                                                                \
   }
-      RID_BF_PRODUCT(al, bh)
-      RID_BF_PRODUCT(am, bm)
-      RID_BF_PRODUCT(ah, bl)
-      RID_BF_PRODUCT(am, bh)
-      RID_BF_PRODUCT(ah, bm)
-      RID_BF_PRODUCT(ah, bh)
+      if constexpr (NT == 3) {
+        RID_BF_PRODUCT(2, 0)
+        RID_BF_PRODUCT(1, 1)
+        RID_BF_PRODUCT(0, 2)
+        RID_BF_PRODUCT(1, 0)
+        RID_BF_PRODUCT(0, 1)
+        RID_BF_PRODUCT(0, 0)
+      } else {
+        RID_BF_PRODUCT(1, 0)
+        RID_BF_PRODUCT(0, 1)
+        RID_BF_PRODUCT(0, 0)
+      }
 #undef RID_BF_PRODUCT
     }
     if (more) {
@@ -265,13 +280,13 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
   }
 }
 
-template <int RT, class TA>
+template <int RT, class TA, int NT>
 __global__ __launch_bounds__(512) void sketch_bf16_kernel(
     int64_t m, int64_t n, int64_t l, const TA *__restrict__ A, int64_t lda,
     const __bf16 *__restrict__ Gs, int64_t ldk, int64_t pstride, float *__restrict__ out,
     int64_t ldo, int64_t split_stride, int64_t pchunk) {
-  sketch_bf16_body<RT, TA>(m, n, l, A, lda, Gs, ldk, pstride, out, ldo, split_stride, pchunk,
-                           blockIdx.x, blockIdx.y, blockIdx.z);
+  sketch_bf16_body<RT, TA, NT>(m, n, l, A, lda, Gs, ldk, pstride, out, ldo, split_stride,
+                               pchunk, blockIdx.x, blockIdx.y, blockIdx.z);
 }
 
 // Y(mu, j) = sum over splits (in order, in double) of part[s](mu, j).
@@ -326,29 +341,19 @@ BfPlan plan_bf16(int64_t m, int64_t n, int64_t l) {
   return p;
 }
 
-template <int RT, class TA>
+template <int RT, class TA, int NT>
 void launch_bf16_rt(hipStream_t st, const BfPlan &p, int64_t m, int64_t n, int64_t l,
                     const TA *A, int64_t lda, const __bf16 *Gs, float *part) {
   dim3 grid(static_cast<unsigned>(p.nbx), static_cast<unsigned>(p.S),
             static_cast<unsigned>(p.nbz));
-  hipLaunchKernelGGL((sketch_bf16_kernel<RT, TA>), grid, dim3(512), 0, st, m, n, l, A, lda, Gs,
-                     p.ldk, p.pstride, part, 2 * l, 2 * l * n, p.pchunk);
+  hipLaunchKernelGGL((sketch_bf16_kernel<RT, TA, NT>), grid, dim3(512), 0, st, m, n, l, A, lda,
+                     Gs, p.ldk, p.pstride, part, 2 * l, 2 * l * n, p.pchunk);
 }
 
-}  // namespace
-
-size_t sketch_bf16_ws_bytes(int64_t m, int64_t n, int64_t l) {
-  const BfPlan p = plan_bf16(m, n, l);
-  WsCarve c(nullptr);
-  c.take<__bf16>(3 * size_t(p.pstride));
-  c.take<float>(size_t(p.S) * size_t(2 * l) * size_t(n));
-  return c.off;
-}
-
-template <class TA>
-hipError_t launch_sketch_bf16(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
-                              int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
-                              int64_t ldy, void *ws, RidProf *prof) {
+template <class TA, int NT>
+hipError_t launch_bf16_terms(hipStream_t st, int64_t m, int64_t n, int64_t l, const TA *A,
+                             int64_t lda, const double2 *G, int64_t ldg, double2 *Y,
+                             int64_t ldy, void *ws, RidProf *prof) {
   if (n == 0 || l == 0) return hipSuccess;
   if (m == 0) return launch_zero(st, l, n, Y, ldy);
   const BfPlan p = plan_bf16(m, n, l);
@@ -359,14 +364,14 @@ hipError_t launch_sketch_bf16(hipStream_t st, int64_t m, int64_t n, int64_t l, c
     const int64_t total = p.rows_pad * p.mpad;
     int64_t blocks = (total + 255) / 256;
     if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(bf16_split_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st,
-                       l, m, p.rows_pad, p.mpad, G, ldg, Gs, p.ldk, p.pstride);
+    hipLaunchKernelGGL((bf16_split_kernel<NT>), dim3(static_cast<unsigned>(blocks)), dim3(256),
+                       0, st, l, m, p.rows_pad, p.mpad, G, ldg, Gs, p.ldk, p.pstride);
   }
   ProfScope ps(prof, st, RID_KERNEL_SKETCH);
   switch (p.RT) {
 #define RID_BF_CASE(X)                                               \
   case X:                                                            \
-    launch_bf16_rt<X, TA>(st, p, m, n, l, A, lda, Gs, part);         \
+    launch_bf16_rt<X, TA, NT>(st, p, m, n, l, A, lda, Gs, part);     \
     break;
     RID_BF_CASE(1) RID_BF_CASE(2) RID_BF_CASE(3) RID_BF_CASE(4) RID_BF_CASE(5) RID_BF_CASE(6)
     RID_BF_CASE(7) RID_BF_CASE(8) RID_BF_CASE(9) RID_BF_CASE(10) RID_BF_CASE(11)
@@ -386,9 +391,30 @@ hipError_t launch_sketch_bf16(hipStream_t st, int64_t m, int64_t n, int64_t l, c
   return hipGetLastError();
 }
 
-template hipError_t launch_sketch_bf16<double2>(hipStream_t, int64_t, int64_t, int64_t,
+}  // namespace
+
+size_t sketch_bf16_ws_bytes(int64_t m, int64_t n, int64_t l) {
+  const BfPlan p = plan_bf16(m, n, l);
+  WsCarve c(nullptr);
+  c.take<__bf16>(3 * size_t(p.pstride));
+  c.take<float>(size_t(p.S) * size_t(2 * l) * size_t(n));
+  return c.off;
+}
+
+template <class TA>
+hipError_t launch_sketch_bf16(hipStream_t st, int terms, int64_t m, int64_t n, int64_t l,
+                              const TA *A, int64_t lda, const double2 *G, int64_t ldg,
+                              double2 *Y, int64_t ldy, void *ws, RidProf *prof) {
+  if (terms == 2)
+    return launch_bf16_terms<TA, 2>(st, m, n, l, A, lda, G, ldg, Y, ldy, ws, prof);
+  if (terms == 3)
+    return launch_bf16_terms<TA, 3>(st, m, n, l, A, lda, G, ldg, Y, ldy, ws, prof);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_sketch_bf16<double2>(hipStream_t, int, int64_t, int64_t, int64_t,
                                                 const double2 *, int64_t, const double2 *,
                                                 int64_t, double2 *, int64_t, void *, RidProf *);
-template hipError_t launch_sketch_bf16<float2>(hipStream_t, int64_t, int64_t, int64_t,
+template hipError_t launch_sketch_bf16<float2>(hipStream_t, int, int64_t, int64_t, int64_t,
                                                const float2 *, int64_t, const double2 *,
                                                int64_t, double2 *, int64_t, void *, RidProf *);

@@ -348,24 +348,25 @@ int sketch_pick_mt(int64_t l) {
 
 bool sketch_supported(rid_dtype dtype, rid_prec prec) {
   return (dtype == RID_C128 || dtype == RID_C64) &&
-         (prec == RID_FP64 || prec == RID_FP32 || prec == RID_BF16X3);
+         prec_valid(prec);
 }
 
 size_t sketch_ws_bytes(rid_dtype dtype, rid_prec prec, int64_t m, int64_t n, int64_t l) {
   (void)dtype;
-  if (prec == RID_BF16X3) return sketch_bf16_ws_bytes(m, n, l);
+  if (prec == RID_BF16X2 || prec == RID_BF16X3) return sketch_bf16_ws_bytes(m, n, l);
   return prec == RID_FP32 ? sketch_f32_ws_bytes(m, n, l) : sketch_f64_ws_bytes(m, n, l);
 }
 
 hipError_t launch_sketch(hipStream_t st, rid_dtype dtype, rid_prec prec, int64_t m, int64_t n,
                          int64_t l, const void *A, int64_t lda, const double2 *G, int64_t ldg,
                          double2 *Y, int64_t ldy, void *part, RidProf *prof) {
-  if (prec == RID_BF16X3) {
+  if (prec == RID_BF16X2 || prec == RID_BF16X3) {
+    const int terms = prec == RID_BF16X2 ? 2 : 3;
     if (dtype == RID_C64)
-      return launch_sketch_bf16(st, m, n, l, static_cast<const float2 *>(A), lda, G, ldg, Y, ldy,
-                                part, prof);
-    return launch_sketch_bf16(st, m, n, l, static_cast<const double2 *>(A), lda, G, ldg, Y, ldy,
-                              part, prof);
+      return launch_sketch_bf16(st, terms, m, n, l, static_cast<const float2 *>(A), lda, G, ldg,
+                                Y, ldy, part, prof);
+    return launch_sketch_bf16(st, terms, m, n, l, static_cast<const double2 *>(A), lda, G, ldg,
+                              Y, ldy, part, prof);
   }
   if (prec == RID_FP32) {
     if (dtype == RID_C64)

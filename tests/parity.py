@@ -87,3 +87,38 @@ def check_decompose(A, Y, J, P, sigma, seed, q, tau=1e-10, ptol=1e-10, ref=None,
         assert s_ref / sigma_factor <= sigma <= sigma_factor * s_ref, (sigma, s_ref)
     r["sigma_ref"] = s_ref
     return r
+
+
+# unit roundoff of the residual's sums over A, by accumulation kind
+ACC_U = {"fp64": 2.0 ** -53, "fp32": 2.0 ** -24}
+
+
+def plain_sigma_tol(A, P, acc):
+    """Bound on |sigma_gpu - sigma_exact| for plain (uncompensated) sums over
+    A: each entry of z = A x~ (and of u = A^H z) is a sum whose rounding error
+    is about u sqrt(terms) |a_i| |x~|, so ||dz|| <~ u sqrt(m + n) ||A||_F
+    ||x~||, with ||x~|| <= 1 + ||P||_2 for a unit x; a direction error of x
+    moves the next sigma by the same order.  Factor 10 on top."""
+    Ac = np.asarray(A).astype(np.complex128)
+    m, n = Ac.shape
+    p2 = np.linalg.norm(np.asarray(P), 2) if np.asarray(P).size else 0.0
+    return 10 * ACC_U[acc] * np.sqrt(m + n) * np.linalg.norm(Ac) * (1 + p2)
+
+
+def check_sigma_call_for_call(A, J, P, sigma, seed, q, acc="dot2", hist=None):
+    """The GPU's sigma is the power estimate of ||A - A(:,J) P|| for its own
+    J and P: the oracle's iteration (binary128) on the same (A, J, P, start
+    vector, q).  Compensated sums ("dot2") agree to 1e-10 relative; plain
+    double ("fp64") or single ("fp32") sums to plain_sigma_tol.  With hist,
+    every step is checked.  Returns the oracle's sigma."""
+    n = np.asarray(A).shape[1]
+    s_ref, h_ref = oracle.residual(A, J, P, oracle.start_vector(n, seed), q)
+    if acc == "dot2":
+        tol = 1e-10 * s_ref + 1e-300
+        htol = 1e-10 * h_ref
+    else:
+        tol = htol = plain_sigma_tol(A, P, acc)
+    assert abs(sigma - s_ref) <= tol, (sigma, s_ref, tol)
+    if hist is not None:
+        assert np.all(np.abs(np.asarray(hist) - h_ref) <= htol), (hist, h_ref, htol)
+    return s_ref

@@ -14,7 +14,7 @@ import pytest
 
 import oracle
 import synth
-from parity import check_decompose
+from parity import check_decompose, check_sigma_call_for_call
 
 pytestmark = pytest.mark.gpu
 
@@ -161,7 +161,13 @@ def test_autotuner_picks_candidates_and_keeps_parity(h):
 # The batched workload itself: 512 jobs drawn as the benchmark draws them
 # (m log-uniform in [256, 4096], n in [128, 2048], k in [8, 64], l = k + 8,
 # A = X W + 1e-7 N stored complex64), run as one batch; a seeded sample of
-# 16 jobs is checked against the oracle on the same stored values.
+# 16 jobs is checked against the oracle on the same stored values.  With
+# FP32 sketch products J and P keep their reduced-precision bars, but at this
+# noise level (ID error about 1e-6 of ||A||) the FP32-level change of P moves
+# ||A - A(:,J) P|| by more than the error itself, so sigma is held to the
+# end-to-end bound in ||dP|| and, call for call, to the oracle's iteration
+# on the batch's own J and P (plain double sums over A with FP32 products:
+# within u sqrt(m + n) ||A||_F (1 + ||P||) times 10).
 @pytest.mark.parametrize("prec", ["RID_FP64", "RID_FP32"])
 def test_batch_of_the_512_job_workload_sampled_against_oracle(h, prec):
     import bench
@@ -188,5 +194,8 @@ def test_batch_of_the_512_job_workload_sampled_against_oracle(h, prec):
         if p == rid.RID_FP64:
             check_decompose(A, r["Y"], Jb, Pb, sb, used[i], q, ref=r)
         else:
-            check_decompose(A, r["Y"], Jb, Pb, sb, used[i], q, tau=1e-4, ptol=1e-3, ref=r,
-                            sigma_factor=2.0)
+            c = check_decompose(A, r["Y"], Jb, Pb, sb, used[i], q, tau=1e-4, ptol=1e-3, ref=r)
+            # FP32 products: the residual's sums over A are plain double
+            check_sigma_call_for_call(A, Jb, Pb, sb, used[i], q, acc="fp64")
+            print("job %d %dx%d k=%d: sigma FP32 / FP64 oracle = %.2f" % (
+                i, m, n, k, sb / c["sigma_ref"]))

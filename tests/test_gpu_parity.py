@@ -343,6 +343,87 @@ def test_decompose_rank_deficient_fails_every_draw(h):
     assert ei.value.status == rid.RID_ERR_RANK
 
 
+def test_decompose_redraws_after_a_rank_deficient_first_operator(h):
+    # Sec. 2: when rank(Y) < k the randomization is drawn again.  The first
+    # operator G0 = B C has rank k - 1, so G0 A has rank k - 1 and the QR
+    # stops at step k - 1; the redraw with seed + 1 succeeds and gives the
+    # oracle's ID of that seed.
+    m, n, k, l = 600, 300, 12, 20
+    A = _lowrank(m, n, k, 1e-10, seed=31)
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((l, k - 1)) + 1j * rng.standard_normal((l, k - 1))
+    C = rng.standard_normal((k - 1, m)) + 1j * rng.standard_normal((k - 1, m))
+    G0 = np.ascontiguousarray(B @ C)
+    r0 = oracle.decompose(A, k, l, seed=5, q=6, G=G0)
+    assert r0["status"] == oracle.ERR_RANK                   # the oracle agrees G0 fails
+    G0d = torch.from_numpy(G0).cuda()
+    J, P, sigma, used = rid.rid_decompose_explicit(h, dev(A), G0d, k, seed=5, q=6)
+    assert used == 6
+    r = oracle.decompose(A, k, l, seed=6, q=6, max_retries=0)
+    assert r["status"] == oracle.OK
+    check_decompose(A, r["Y"], host(J), host(P), float(host(sigma)[0]), 6, 6, ref=r)
+    with pytest.raises(rid.RidError) as ei:                   # no redraw allowed
+        rid.rid_decompose_explicit(h, dev(A), G0d, k, seed=5, q=6, max_retries=0)
+    assert ei.value.status == rid.RID_ERR_RANK
+    # a full-rank explicit first operator is used as given
+    G1 = oracle.sketch_operator(l, m, seed=77)
+    J, P, sigma, used = rid.rid_decompose_explicit(h, dev(A), torch.from_numpy(G1).cuda(), k,
+                                                   seed=5, q=6)
+    assert used == 5
+    r1 = oracle.decompose(A, k, l, seed=5, q=6, G=G1)
+    check_decompose(A, r1["Y"], host(J), host(P), float(host(sigma)[0]), 5, 6, ref=r1)
+
+
+def test_misaligned_pointers_and_short_leading_dimensions_rejected(h):
+    # through the raw C entry points: argument errors come back before any
+    # launch, so nothing is read through the bad pointers
+    import ctypes
+    lib = rid.load()
+    Pv = ctypes.c_void_p
+    m, n, k, l = 50, 20, 3, 5
+    A = dev(_lowrank(m, n, k, 1e-10, seed=1))
+    J = torch.zeros(k, dtype=torch.int64, device="cuda")
+    P = torch.zeros((n, k), dtype=torch.complex128, device="cuda").t()
+    Y = torch.zeros((n, l), dtype=torch.complex128, device="cuda").t()
+    sig = torch.zeros(1, dtype=torch.float64, device="cuda")
+    a, p = A.data_ptr(), P.data_ptr()
+    C128, C64, F64 = rid.RID_C128, rid.RID_C64, rid.RID_FP64
+    INV = rid.RID_ERR_INVALID_ARG
+
+    def dec(Ap, lda, Pp, ldp, dt=C128):
+        return lib.rid_decompose(h, None, dt, F64, m, n, k, l, Pv(Ap), lda, 0, 4, 1, 1e-12,
+                                 Pv(J.data_ptr()), Pv(Pp), ldp, Pv(sig.data_ptr()), None)
+
+    assert dec(a + 8, m, p, k) == INV           # complex128 A must be 16-byte aligned
+    assert dec(a + 4, m, p, k, C64) == INV      # complex64 A 8-byte aligned
+    assert dec(a, m - 1, p, k) == INV           # lda < m
+    assert dec(a, m, p + 8, k) == INV           # P 16-byte aligned
+    assert dec(a, m, p, k - 1) == INV           # ldp < k
+    assert lib.rid_sketch(h, None, C128, F64, m, n, l, Pv(a + 8), m, 0, Pv(Y.data_ptr()),
+                          l) == INV
+    assert lib.rid_sketch(h, None, C128, F64, m, n, l, Pv(a), m - 1, 0, Pv(Y.data_ptr()),
+                          l) == INV
+    assert lib.rid_sketch(h, None, C128, F64, m, n, l, Pv(a), m, 0, Pv(Y.data_ptr() + 8),
+                          l) == INV
+    assert lib.rid_sketch(h, None, C128, F64, m, n, l, Pv(a), m, 0, Pv(Y.data_ptr()),
+                          l - 1) == INV
+    assert lib.rid_pivqr(h, None, l, n, k, Pv(Y.data_ptr() + 8), l, Pv(J.data_ptr()), None,
+                         1e-12) == INV
+    assert lib.rid_pivqr(h, None, l, n, k, Pv(Y.data_ptr()), l - 1, Pv(J.data_ptr()), None,
+                         1e-12) == INV
+    assert lib.rid_interp(h, None, n, k, Pv(Y.data_ptr()), k - 1, Pv(J.data_ptr()), Pv(p),
+                          k) == INV
+    assert lib.rid_interp(h, None, n, k, Pv(Y.data_ptr()), l, Pv(J.data_ptr()), Pv(p + 8),
+                          k) == INV
+    assert lib.rid_residual(h, None, C128, F64, m, n, k, Pv(a + 8), m, Pv(J.data_ptr()),
+                            Pv(p), k, 4, 0, Pv(sig.data_ptr()), None) == INV
+    assert lib.rid_residual(h, None, C128, F64, m, n, k, Pv(a), m - 1, Pv(J.data_ptr()),
+                            Pv(p), k, 4, 0, Pv(sig.data_ptr()), None) == INV
+    # the handle still works afterwards
+    J2, P2, s2, _ = rid.rid_decompose(h, A, k, l, seed=0, q=4)
+    assert rid.rid_query_status(h) == rid.RID_OK
+
+
 def test_decompose_is_deterministic_and_scale_equivariant(h):
     A = _lowrank(700, 300, 15, 1e-9, seed=7)
     J1, P1, s1, _ = rid.rid_decompose(h, dev(A), 15, 25, seed=1, q=5)
