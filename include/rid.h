@@ -209,6 +209,31 @@ rid_status rid_sketch_explicit(rid_handle h, hipStream_t stream, rid_dtype dtype
 rid_status rid_pivqr(rid_handle h, hipStream_t stream, int64_t l, int64_t n, int64_t k,
                      void *Y, int64_t ldy, int64_t *perm, double *gaps, double rank_tol);
 
+/* Bytes of the device scratch array that rid_pivqr_static uses. */
+#define RID_STATIC_SCRATCH_BYTES (32 << 20)
+
+/* rid_pivqr without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, kernels and results
+ * (bit for bit) as rid_pivqr; the QR's scratch (per-workgroup pivot
+ * candidates and column copies, per-column pivot steps, the panel
+ * reflectors, and with RID_QR_CGS2 the Gram-Schmidt basis) lives in a
+ * file-scope device array of RID_STATIC_SCRATCH_BYTES, one per device, held
+ * until the process ends and located by rid_create.  The QR of an l x n Y
+ * needs about 2 ceil(n / 64) (16 l + 24) + 4 n + 64 l bytes (plus
+ * 16 (l k + k n) with RID_QR_CGS2): with Householder up to about 300000
+ * columns at l = 208 and 33000 at l = 2000.  Larger problems return
+ * RID_ERR_NOMEM before any launch.
+ * Every call on a device shares that device's array, and the array keeps
+ * what the last call left (every kernel initialises what it reads):
+ * calls that overlap on one device -- on different streams or from
+ * different threads or handles -- race and must be ordered by the caller.
+ * Profiling (rid_profile) does not record these calls.
+ * Errors: INVALID_ARG, UNSUPPORTED, NOMEM (problem beyond the array), HIP. */
+rid_status rid_pivqr_static(rid_handle h, hipStream_t stream, int64_t l, int64_t n, int64_t k,
+                            void *Y, int64_t ldy, int64_t *perm, double *gaps,
+                            double rank_tol);
+
 /* ---------------------------------------------------------------- step 3 */
 
 /* Interpolation matrix (Sec. 2): with R1 = R(:, J) upper triangular and R2

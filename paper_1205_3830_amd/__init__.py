@@ -38,7 +38,7 @@ RID_BF16X3 = 3
 
 EXPORTED = ["rid_create", "rid_destroy", "rid_status_string", "rid_last_hip_error",
             "rid_reserve", "rid_gaussian", "rid_sketch", "rid_sketch_explicit", "rid_pivqr",
-            "rid_interp", "rid_residual", "rid_decompose", "rid_decompose_explicit",
+            "rid_pivqr_static", "rid_interp", "rid_residual", "rid_decompose", "rid_decompose_explicit",
             "rid_query_status", "rid_profile",
             "rid_profile_read", "rid_set_sketch", "rid_srft_operator", "rid_decompose_batched",
             "rid_server_create", "rid_server_submit", "rid_server_drain", "rid_server_stats",
@@ -111,6 +111,7 @@ _sig = {
     "rid_sketch_explicit": ([_P, _P, _I, _I, _I64, _I64, _I64, _P, _I64, _P, _I64, _P, _I64],
                             _I),
     "rid_pivqr": ([_P, _P, _I64, _I64, _I64, _P, _I64, _P, _P, _D], _I),
+    "rid_pivqr_static": ([_P, _P, _I64, _I64, _I64, _P, _I64, _P, _P, _D], _I),
     "rid_interp": ([_P, _P, _I64, _I64, _P, _I64, _P, _P, _I64], _I),
     "rid_residual": ([_P, _P, _I, _I, _I64, _I64, _I64, _P, _I64, _P, _P, _I64, _I, _U64, _P,
                       _P], _I),
@@ -331,6 +332,21 @@ def rid_pivqr(h, Y, k: int, perm=None, gaps=None, rank_tol: float = 1e-12, strea
         gaps = torch.empty(k, dtype=torch.float64, device="cuda")
     _check(_L.rid_pivqr(h, _stream(stream), l, n, k, _ptr(Y), ldy, _ptr(perm), _ptr(gaps),
                           rank_tol), "rid_pivqr")
+    return perm, gaps
+
+
+def rid_pivqr_static(h, Y, k: int, perm=None, gaps=None, rank_tol: float = 1e-12, stream=None):
+    """rid_pivqr with its scratch in the library's static device array (no
+    device allocation inside the call); returns (perm, gaps)."""
+    torch = _torch()
+    l, n = Y.shape
+    ldy = _ld_colmajor(Y, "Y")
+    if perm is None:
+        perm = torch.empty(n, dtype=torch.int64, device="cuda")
+    if gaps is None:
+        gaps = torch.empty(k, dtype=torch.float64, device="cuda")
+    _check(_L.rid_pivqr_static(h, _stream(stream), l, n, k, _ptr(Y), ldy, _ptr(perm),
+                                 _ptr(gaps), rank_tol), "rid_pivqr_static")
     return perm, gaps
 
 

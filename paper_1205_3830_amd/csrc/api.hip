@@ -3,11 +3,50 @@
 // steps of the randomized ID (Sec. 2), including the redraw on rank(Y) < k.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <new>
 
 #include "rid_internal.hpp"
 
+// Device scratch of rid_pivqr_static: a file-scope array, one copy on each
+// device the library runs on, held until the process ends.  Host code never
+// uses the array's name as an address: rid_create looks its device address
+// up once per device (scratch_setup) and the entry point passes that.
+static __device__ __align__(256) char scratch[RID_STATIC_SCRATCH_BYTES];
+
 namespace {
+
+constexpr int RID_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[RID_MAX_DEVICES];
+hipError_t g_scratch_err[RID_MAX_DEVICES];
+bool g_scratch_done[RID_MAX_DEVICES];
+
+// With `device` current: the device address of `scratch` on it, looked up
+// once per device.
+void scratch_setup(int device) {
+  if (device < 0 || device >= RID_MAX_DEVICES) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_done[device]) return;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+  if (e != hipSuccess) (void)hipGetLastError();
+  g_scratch_done[device] = true;
+}
+
+// The scratch address of `device` (null if its lookup failed; *err then
+// holds the HIP error).
+void *scratch_of(int device, hipError_t *err) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= RID_MAX_DEVICES || !g_scratch_done[device]) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  *err = g_scratch_err[device];
+  return g_scratch_ptr[device];
+}
 
 // Makes the handle's device current for the duration of a call.
 struct DeviceGuard {
@@ -169,6 +208,7 @@ rid_status rid_create(rid_handle *h, int device) {
     delete c;
     return RID_ERR_HIP;
   }
+  scratch_setup(device);
   *h = c;
   return RID_OK;
 }
@@ -316,6 +356,26 @@ rid_status rid_pivqr(rid_handle h, hipStream_t stream, int64_t l, int64_t n, int
   if (s != RID_OK) return s;
   hipError_t e = launch_pivqr(stream, l, n, k, static_cast<double2 *>(Y), ldy, perm, gaps,
                               rank_tol, h->ws, h->d_status, &h->prof, h->qr_kind);
+  return e == hipSuccess ? RID_OK : fail_hip(h, e);
+}
+
+rid_status rid_pivqr_static(rid_handle h, hipStream_t stream, int64_t l, int64_t n, int64_t k,
+                            void *Y, int64_t ldy, int64_t *perm, double *gaps,
+                            double rank_tol) {
+  if (!h || k < 1 || k > l || k > n || ldy < l || !Y || !perm || !aligned(Y, 16) ||
+      !(rank_tol >= 0.0) || !std::isfinite(rank_tol) || n > 0x7FFFFFFFll)
+    return RID_ERR_INVALID_ARG;
+  if (!pivqr_supported(l)) return RID_ERR_UNSUPPORTED;
+  if (h->qr_kind == RID_QR_CGS2 && k > 1024) return RID_ERR_UNSUPPORTED;
+  if (pivqr_ws_bytes(l, n, k, h->qr_kind) > size_t(RID_STATIC_SCRATCH_BYTES))
+    return RID_ERR_NOMEM;
+  DeviceGuard g(h->device);
+  if (g.err != hipSuccess) return fail_hip(h, g.err);
+  hipError_t e = hipSuccess;
+  void *ws = scratch_of(h->device, &e);
+  if (!ws) return fail_hip(h, e);
+  e = launch_pivqr(stream, l, n, k, static_cast<double2 *>(Y), ldy, perm, gaps, rank_tol, ws,
+                   h->d_status, nullptr, h->qr_kind);
   return e == hipSuccess ? RID_OK : fail_hip(h, e);
 }
 
