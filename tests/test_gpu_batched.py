@@ -118,6 +118,37 @@ def test_batch_graph_and_direct_launch_agree_bitwise(h, monkeypatch):
             assert torch.equal(a[2][i], res[2][i])
 
 
+def test_batch_qr_one_launch_equals_per_step_launches(h, monkeypatch):
+    # the QR of a batch as one launch per pivot step over all jobs (default)
+    # and as one launch with a workgroup per job (RID_BATCH_QR=jobs): the
+    # same arithmetic, so J, P and sigma agree bit for bit; jobs of 1 to 4
+    # rows per lane, n from below one column block to several, and a
+    # rank-deficient job
+    jobs = make_jobs(9, 8, mmax=2500, nmax=1500)
+    bad = synth.lowrank(300, 130, 3, 0.0, seed=19)       # rank 3 < k = 6
+    jobs.insert(4, (bad, 6, 10, 5))
+    jobs.append((synth.lowrank(600, 40, 30, 1e-9, seed=21), 30, 200, 3))   # l = 200: 4 rows/lane
+    As = [dev(A) for A, _, _, _ in jobs]
+    args = ([j[1] for j in jobs], [j[2] for j in jobs], [j[3] for j in jobs])
+    a = rid.rid_decompose_batched(h, As, *args, q=4, max_retries=0, raise_on_rank=False)
+    monkeypatch.setenv("RID_BATCH_QR", "jobs")
+    b = rid.rid_decompose_batched(h, As, *args, q=4, max_retries=0, raise_on_rank=False)
+    assert a[3] == b[3] and a[3][4] == rid.RID_ERR_RANK
+    assert sum(st == 0 for st in a[3]) == len(jobs) - 1
+    for i in range(len(jobs)):
+        if a[3][i] != 0:
+            continue
+        assert torch.equal(a[0][i], b[0][i]), i
+        assert torch.equal(a[1][i], b[1][i]), i
+        assert torch.equal(a[2][i], b[2][i]), i
+    # and against the oracle on the batch's pivots
+    for i in (0, len(jobs) - 1):
+        A, k, l, s = jobs[i]
+        r = oracle.decompose(A, k, l, seed=s, q=4)
+        check_decompose(A, r["Y"], host(a[0][i]), host(a[1][i]), float(host(a[2][i])[0]), s, 4,
+                        ref=r)
+
+
 def test_batch_invalid_job_rejected(h):
     A = dev(synth.lowrank(50, 20, 3, 0.0, seed=1))
     with pytest.raises(rid.RidError) as ei:
