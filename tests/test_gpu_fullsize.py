@@ -1,7 +1,8 @@
 """Parity at the full benchmark sizes, in the launch configuration bench.py
 times: A = X W + 1e-12 N, complex128, q = 10, at m = 131072, n = 16384,
-k = 100, l = 108 (34.4 GB on the device) and at the square case
-m = n = 32768, k = 200, l = 208 (17.2 GB).
+k = 100, l = 108 (34.4 GB on the device), at the square case
+m = n = 32768, k = 200, l = 208 (17.2 GB), and at the served workload's big
+job m = 262144, n = 16384, k = 64, l = 72 (68.7 GB).
 
 The oracle cannot redo a 34 GB ID in seconds, so this checks
   * sampled columns of Y against the oracle, one column at a time;
@@ -30,18 +31,20 @@ rid = pytest.importorskip("paper_1205_3830_amd")
 
 Q, NOISE = 10, 1e-12
 # the two shapes of the large workload: 131072 x 16384, k = 100, l = 108, and
-# the square case 32768 x 32768, k = 200, l = 208
-SHAPES = [(131072, 16384, 100, 108), (32768, 32768, 200, 208)]
+# the square case 32768 x 32768, k = 200, l = 208; and the served workload's
+# big job, 262144 x 16384, k = 64, l = 72 (68.7 GB)
+SHAPES = [(131072, 16384, 100, 108), (32768, 32768, 200, 208), (262144, 16384, 64, 72)]
 
 
-@pytest.fixture(scope="module", params=SHAPES, ids=["131072x16384", "32768x32768"])
+@pytest.fixture(scope="module", params=SHAPES,
+                ids=["131072x16384", "32768x32768", "262144x16384"])
 def big(request):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     M, N, K, L = request.param
     free, _ = torch.cuda.mem_get_info()
-    if free < 60e9:
-        pytest.skip("needs ~40 GB of free device memory")
+    if free < 16.0 * M * N * 1.3 + 20e9:
+        pytest.skip("needs %.0f GB of free device memory" % ((16.0 * M * N * 1.3 + 20e9) / 1e9))
     A = synth.lowrank_device(M, N, K, NOISE, seed=0).t()
     h = rid.rid_create(0)
     rid.rid_reserve(h, M, N, L, K)

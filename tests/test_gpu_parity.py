@@ -74,13 +74,21 @@ SKETCH_CASES = [
 ]
 
 
+def _check_Y(Y, ref, tol=1e-12):
+    """||dY||_F <= tol ||Y||_F, and column by column ||dY(:,j)|| <= tol ||Y(:,j)||
+    (the summation order of each column's l sums differs between the two)."""
+    assert np.linalg.norm(Y - ref) <= tol * np.linalg.norm(ref)
+    dcol = np.linalg.norm(Y - ref, axis=0)
+    assert np.all(dcol <= tol * np.linalg.norm(ref, axis=0) + 1e-300), dcol.max()
+
+
 @pytest.mark.parametrize("m,n,l", SKETCH_CASES)
 def test_sketch_explicit_matches_oracle(h, m, n, l):
     A = _lowrank(m, n, min(8, m, n), 1e-6, seed=m + n)
     G = oracle.sketch_operator(l, m, seed=1)
     Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda()))
     ref = oracle.sketch(A, G)
-    assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
+    _check_Y(Y, ref)
 
 
 # Every row tiling of the FP64 sketch (1 to 14 tiles of 16 rows of Y, each
@@ -98,7 +106,7 @@ def test_sketch_every_row_tiling_matches_oracle(h, l, dt):
     G = oracle.sketch_operator(l, m, seed=l + 1)
     Y = host(rid.rid_sketch_explicit(h, dev(A), torch.from_numpy(G).cuda()))
     ref = oracle.sketch(A.astype(np.complex128), G)
-    assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
+    _check_Y(Y, ref)
 
 
 @pytest.mark.parametrize("m,n,l,seed", [(1000, 500, 30, 0), (333, 77, 20, 9)])
