@@ -323,7 +323,7 @@ def serving_result(args, torch, rid, synth) -> dict:
     print("serving trace: %d requests (%d big)" % (len(trace), n_big), file=sys.stderr, flush=True)
     served = run_trace(rid, synth, torch, trace, args.q, big_lanes=args.big_lanes,
                        batch_lanes=args.batch_lanes, max_batch=512, prec=prec)
-    print("served: %s" % json.dumps(served), file=sys.stderr, flush=True)
+    print("served: %.1f IDs/s" % served["ids_per_s"], file=sys.stderr, flush=True)
     base = None
     if not args.no_baseline:
         base = run_trace(rid, synth, torch, trace, args.q, big_lanes=0, batch_lanes=1,
@@ -753,7 +753,7 @@ def forms_result(args, torch, rid, synth, fp64_line) -> dict:
     plain FP64 line: complex64 storage of the same shape at rho = 1e-6 with
     FP64, FP32, BF16x2 and BF16x3 sketch products; the 512-job batch with
     FP64 and FP32 products; a 2-second served trace against the plain FP64
-    path one request at a time.  Details go to stderr."""
+    path one request at a time."""
     import copy
     ms64 = fp64_line["ms_per_step"]
 
@@ -775,7 +775,8 @@ def forms_result(args, torch, rid, synth, fp64_line) -> dict:
         pa.prec = p
         pa.compare_fp64 = p != "fp64"
         rec = single_result(pa, torch, rid, synth, A=A)
-        print("forms: precision %s: %s" % (p, json.dumps(rec)), file=sys.stderr, flush=True)
+        print("forms: precision %s: %.2f ms per ID" % (p, rec["ms_per_step"]), file=sys.stderr,
+              flush=True)
         row = {"ms": round(rec["ms_per_step"], 3), "ids_per_s": round(rec["ids_per_s"], 3),
                "A_GB_per_s": round(rec["value"], 1),
                "speedup_vs_plain_fp64": round(ms64 / rec["ms_per_step"], 3),
@@ -798,7 +799,8 @@ def forms_result(args, torch, rid, synth, fp64_line) -> dict:
         ba.prec = p
         print("forms: batched %s" % p, file=sys.stderr, flush=True)
         rec = batched_result(ba, torch, rid, synth)
-        print("forms: batched %s: %s" % (p, json.dumps(rec)), file=sys.stderr, flush=True)
+        print("forms: batched %s: %.2f ms per batch" % (p, rec["ms_per_step"]), file=sys.stderr,
+              flush=True)
         single = rec["single_fp64_one_at_a_time"] or {}
         batch_rows[p] = {"ms": round(rec["ms_per_step"], 3), "ids_per_s": round(rec["ids_per_s"], 1),
                          "A_GB_per_s": round(rec["value"], 1),
@@ -812,7 +814,7 @@ def forms_result(args, torch, rid, synth, fp64_line) -> dict:
     sa.duration, sa.rate, sa.prec, sa.no_baseline = 2.0, 200.0, "fp64", False
     print("forms: serving", file=sys.stderr, flush=True)
     rec = serving_result(sa, torch, rid, synth)
-    print("forms: serving: %s" % json.dumps(rec), file=sys.stderr, flush=True)
+    print("forms: serving: %.1f IDs/s" % rec["value"], file=sys.stderr, flush=True)
     sv, base = rec["served"], rec["plain_fp64_one_at_a_time"] or {}
 
     def lat(x, key):
