@@ -98,6 +98,7 @@ struct ResJob {
   uint64_t seed;
   double *sigma, *hist;
   int pair;  // complex64 A: adjacent entries may be read as one 16-byte load
+  int al16;  // complex64 A with a 16-byte aligned base (any lda)
   ResPlan pl;
   double2 *x, *xth, *xtl, *z, *uh, *ul;
   double *pxpart, *zpart, *upart, *zn_part, *wn_part, *scal;
@@ -425,6 +426,138 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
   }
 }
 
+// z partials for complex64 A with a 16-byte aligned base and plain sums:
+// every entry arrives in a 16-byte load of two adjacent rows, whatever the
+// parity of lda.  Column j starts on a 16-byte boundary when j lda is even
+// (slab starts are even rows); there the thread's rows (i0, i0 + 1) are one
+// pair, and their sums go to the first and third words of the rows' partial
+// entries.  When j lda is odd (lda odd, j odd) the aligned pairs are
+// (i0 - 1, i0): their sums go to the second and fourth words (unused by
+// plain sums otherwise), so the slab's rows shifted by one are summed
+// without any exchange between threads -- row 512 bx - 1 by this slab's
+// thread 0, the row before it by the previous slab.  The z reduction adds
+// all four words.  Every thread makes one 16-byte load per column.  Rows
+// past m are loaded from 16-byte granules that hold a row of the column (so
+// never from an unmapped page) and zeroed.  With lda odd this needs
+// m % 512 != 0 (so that the last slab's thread reaches row m - 1); the
+// caller takes the general loop otherwise.
+template <int ACC>
+RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
+  static_assert(ACC != RES_DOT2, "plain sums only");
+  using Acc = typename std::conditional<ACC == RES_FP32, float, double>::type;
+  // no early test of the stop flag: a stopped job's partials are computed
+  // but never read (the z reduction tests it), and the A loads start sooner
+  const float2 *A = static_cast<const float2 *>(r.A);
+  const int64_t m = r.m, lda = r.lda;
+  const int t = threadIdx.x;
+  const int64_t i0 = bx * AX_ROWS + 2 * t;
+  const bool ok0 = i0 < m, ok1 = i0 + 1 < m;
+  const bool okm = i0 >= 1 && i0 - 1 < m;  // row i0 - 1 of a shifted pair
+  const bool odd = (lda & 1) != 0;
+  // a wave whose rows (shifted ones included) all lie past m has no loads
+  const bool live = bx * AX_ROWS + 128 * (t >> 6) - 1 < m;
+  // pair starts: unshifted (i0, or row 0 past m); shifted (i0 - 1, or row
+  // -1 past m: the previous column's last stored entry, as j >= 1 there)
+  const int64_t pu = ok0 ? i0 : 0;
+  const int64_t ps = (i0 - 1 < m) ? i0 - 1 : -1;
+  const int64_t jb = by * r.pl.cpz;
+  const int64_t je = live ? min(r.n, jb + r.pl.cpz) : jb;
+  const double2 *__restrict__ xth = r.xth;
+  Acc s0r = 0, s0i = 0, s1r = 0, s1i = 0;  // rows i0, i0 + 1 (unshifted columns)
+  Acc smr = 0, smi = 0, snr = 0, sni = 0;  // rows i0 - 1, i0 (shifted columns)
+  const double2 zero2 = make_double2(0.0, 0.0);
+  // a x for one entry into (sr, si); x~ is rounded to its high word
+  auto fma_c = [&](Acc &sr, Acc &si, const double2 &a, const double2 &xh) {
+    if constexpr (ACC == RES_FP64) {
+      sr = fma(a.x, xh.x, sr);
+      sr = fma(-a.y, xh.y, sr);
+      si = fma(a.x, xh.y, si);
+      si = fma(a.y, xh.x, si);
+    } else {
+      const float ar = static_cast<float>(a.x), ai = static_cast<float>(a.y);
+      const float xr = static_cast<float>(xh.x), xi = static_cast<float>(xh.y);
+      sr = fmaf(ar, xr, sr);
+      sr = fmaf(-ai, xi, sr);
+      si = fmaf(ar, xi, si);
+      si = fmaf(ai, xr, si);
+    }
+  };
+  auto unshifted = [&](const double2 &a0, const double2 &a1, const double2 &xh) {
+    fma_c(s0r, s0i, ok0 ? a0 : zero2, xh);
+    fma_c(s1r, s1i, ok1 ? a1 : zero2, xh);
+  };
+  auto shifted = [&](const double2 &b0, const double2 &b1, const double2 &xh) {
+    fma_c(smr, smi, okm ? b0 : zero2, xh);
+    fma_c(snr, sni, ok0 ? b1 : zero2, xh);
+  };
+  int64_t j = jb;
+  if (odd) {
+    // j lda odd exactly for odd j: a group of 8 from an even column holds
+    // four unshifted (even u) and four shifted (odd u) columns
+    if ((j & 1) && j < je) {
+      double2 b0, b1;
+      ld_stream_pair(A + j * lda + ps, b0, b1);
+      shifted(b0, b1, xth[j]);
+      ++j;
+    }
+    for (; j + 8 <= je; j += 8) {
+      double2 a0[8], a1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ld_stream_pair(A + (j + u) * lda + ((u & 1) ? ps : pu), a0[u], a1[u]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        if (u & 1)
+          shifted(a0[u], a1[u], xth[j + u]);
+        else
+          unshifted(a0[u], a1[u], xth[j + u]);
+      }
+    }
+    for (; j < je; ++j) {
+      double2 a0, a1;
+      const bool sh = (j & 1) != 0;
+      ld_stream_pair(A + j * lda + (sh ? ps : pu), a0, a1);
+      if (sh)
+        shifted(a0, a1, xth[j]);
+      else
+        unshifted(a0, a1, xth[j]);
+    }
+  } else {
+    for (; j + 8 <= je; j += 8) {
+      double2 a0[8], a1[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ld_stream_pair(A + (j + u) * lda + pu, a0[u], a1[u]);
+#pragma unroll
+      for (int u = 0; u < 8; ++u) unshifted(a0[u], a1[u], xth[j + u]);
+    }
+    for (; j < je; ++j) {
+      double2 a0, a1;
+      ld_stream_pair(A + j * lda + pu, a0, a1);
+      unshifted(a0, a1, xth[j]);
+    }
+  }
+  // words 0 and 2 of rows i0, i0 + 1; words 1 and 3 of rows i0 - 1, i0
+  // (zero for lda even)
+  double *zp = r.zpart + by * m * 4;
+  if (ok0) {
+    zp[i0 * 4 + 0] = static_cast<double>(s0r);
+    zp[i0 * 4 + 1] = static_cast<double>(snr);
+    zp[i0 * 4 + 2] = static_cast<double>(s0i);
+    zp[i0 * 4 + 3] = static_cast<double>(sni);
+  }
+  if (ok1) {
+    zp[(i0 + 1) * 4 + 0] = static_cast<double>(s1r);
+    zp[(i0 + 1) * 4 + 2] = static_cast<double>(s1i);
+    if (!odd) {
+      zp[(i0 + 1) * 4 + 1] = 0.0;
+      zp[(i0 + 1) * 4 + 3] = 0.0;
+    }
+  }
+  if (odd && okm) {
+    zp[(i0 - 1) * 4 + 1] = static_cast<double>(smr);
+    zp[(i0 - 1) * 4 + 3] = static_cast<double>(smi);
+  }
+}
+
 RID_DEV void z_final_body(const ResJob &r, int64_t bx) {
   __shared__ double sh[4];
   if (stopped(r.scal)) return;
@@ -538,29 +671,68 @@ RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
     }
   } else {
     int i0 = 2 * lane;
+    bool done = false;
     if constexpr (ACC != RES_DOT2) {
-      // plain sums: the whole 128-row groups of the chunk with one
-      // unconditional 16-byte pair load per column (a column past n reads
-      // column 0 of the job and is left out of the sums by a uniform test)
-      if (pair) {
-        const int full = rows & ~127;
-        for (; i0 < full; i0 += 128) {
+      // plain sums, 16-byte aligned A: every entry arrives in a 16-byte load
+      // of two adjacent rows, whatever the parity of lda.  Column u's chunk
+      // is shifted (sh = 1) when it starts 8 bytes past a 16-byte boundary;
+      // its aligned pairs are then rows (1, 2), (3, 4), ... and lane 0 reads
+      // row 0 alone.  A column past n reads column 0 of the job and is left
+      // out of the sums by a uniform test.  G whole 128-row groups (at
+      // either shift), then one group with rows past the chunk zeroed:
+      // their loads stay in 16-byte granules that hold a row of the chunk.
+      if (r.al16 && rows >= 2) {
+        const float2 *cf[AHZ_CPW];
+        int sh[AHZ_CPW];
+        bool any = false;
+#pragma unroll
+        for (int u = 0; u < AHZ_CPW; ++u) {
+          cf[u] = reinterpret_cast<const float2 *>(cp[u]);
+          sh[u] = static_cast<int>((cp[u] - A) & 1);
+          any = any || sh[u] != 0;
+        }
+        const int G = any ? (rows - 1) >> 7 : rows >> 7;
+        for (int g = 0; g < G; ++g, i0 += 128) {
           double2 a0[AHZ_CPW], a1[AHZ_CPW];
 #pragma unroll
-          for (int u = 0; u < AHZ_CPW; ++u)
-            ld_stream_pair(reinterpret_cast<const float2 *>(cp[u]) + i0, a0[u], a1[u]);
+          for (int u = 0; u < AHZ_CPW; ++u) ld_stream_pair(cf[u] + i0 + sh[u], a0[u], a1[u]);
           const double2 z0 = zs[i0], z1 = zs[i0 + 1];
+          const double2 z2 = any ? zs[i0 + 2] : z1;
 #pragma unroll
           for (int u = 0; u < AHZ_CPW; ++u) {
             if (cok[u]) {
-              acc(u, a0[u], z0);
-              acc(u, a1[u], z1);
+              acc(u, a0[u], sh[u] ? z1 : z0);
+              acc(u, a1[u], sh[u] ? z2 : z1);
             }
           }
         }
+        {
+          double2 a0[AHZ_CPW], a1[AHZ_CPW];
+          int f[AHZ_CPW];
+#pragma unroll
+          for (int u = 0; u < AHZ_CPW; ++u) {
+            f[u] = i0 + sh[u];
+            ld_stream_pair(cf[u] + (f[u] < rows ? f[u] : sh[u]), a0[u], a1[u]);
+          }
+#pragma unroll
+          for (int u = 0; u < AHZ_CPW; ++u) {
+            if (cok[u]) {
+              const double2 zero = make_double2(0.0, 0.0);
+              const bool v0 = f[u] < rows, v1 = f[u] + 1 < rows;
+              acc(u, v0 ? a0[u] : zero, zs[v0 ? f[u] : 0]);
+              acc(u, v1 ? a1[u] : zero, zs[v1 ? f[u] + 1 : 0]);
+            }
+          }
+        }
+        if (lane == 0) {
+#pragma unroll
+          for (int u = 0; u < AHZ_CPW; ++u)
+            if (cok[u] && sh[u]) acc(u, ld_stream(cp[u]), zs[0]);
+        }
+        done = true;
       }
     }
-    for (int i = i0; i < rows; i += 128) {
+    for (int i = i0; !done && i < rows; i += 128) {
       const bool two = i + 1 < rows;
       const double2 z0 = zs[i];
       const double2 z1 = two ? zs[i + 1] : make_double2(0.0, 0.0);
@@ -686,7 +858,15 @@ RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
   if constexpr (STEP == ST_XTINIT) xt_init_body(r, bx);
   if constexpr (STEP == ST_PXP) px_partial_body(r, bx);
   if constexpr (STEP == ST_PXF) px_final_body(r, bx);
-  if constexpr (STEP == ST_AX) ax_body<TA, WIDE, ACC>(r, bx, by);
+  if constexpr (STEP == ST_AX) {
+    if constexpr (sizeof(TA) == 8 && ACC != RES_DOT2) {
+      if (r.al16 && r.m >= 2 && ((r.lda & 1) == 0 || r.m % AX_ROWS != 0)) {
+        ax_c64_paired<ACC>(r, bx, by);
+        return;
+      }
+    }
+    ax_body<TA, WIDE, ACC>(r, bx, by);
+  }
   if constexpr (STEP == ST_ZF) z_final_body(r, bx);
   if constexpr (STEP == ST_SIGMA) sigma_final_body(r, t);
   if constexpr (STEP == ST_AHZ) ahz_body<TA, 8, ACC>(r, bx, by);
@@ -835,6 +1015,10 @@ void grouped_iteration(hipStream_t st, const ResJob *jobs, const int4 *dtab,
       q);
 }
 
+bool al16_ok(rid_dtype dtype, const void *A) {
+  return dtype == RID_C64 && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
+}
+
 bool pair_ok(rid_dtype dtype, const void *A, int64_t lda) {
   return dtype == RID_C64 && (reinterpret_cast<uintptr_t>(A) % 16 == 0) && (lda % 2 == 0);
 }
@@ -873,6 +1057,7 @@ hipError_t launch_residual(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n
   r.sigma = sigma;
   r.hist = hist;
   r.pair = pair_ok(dtype, A, lda) ? 1 : 0;
+  r.al16 = al16_ok(dtype, A) ? 1 : 0;
   r.pl = plan_res(m, n, k, 2048, dtype == RID_C64 ? 4 : 8);
   WsCarve c(ws);
   carve_res(c, r);
@@ -905,6 +1090,7 @@ void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, int
     r.sigma = bj[i].sigma;
     r.hist = nullptr;
     r.pair = pair_ok(dtype, bj[i].A, bj[i].lda) ? 1 : 0;
+    r.al16 = al16_ok(dtype, bj[i].A) ? 1 : 0;
     // a job's own passes need few workgroups (the batch fills the device):
     // about one ax workgroup per block_bytes of A
     const int64_t abytes = r.m * r.n * (dtype == RID_C64 ? 8 : 16);

@@ -131,10 +131,14 @@ def test_residual_complex64_call_for_call(h, m, n, k, l, q):
 # and q: compensated sums within 1e-10, plain double and single sums within
 # their derived bound (tests/parity.py: plain_sigma_tol).  Both storage
 # types; the whole-slab fast path of the ax pass (1600 rows) and a ragged
-# slab (1000 rows); rho 1e-3 and 1e-6.
+# slab (1000 rows); rho 1e-3 and 1e-6.  Odd m (so odd lda): complex64
+# columns alternate between 16-byte aligned and shifted pairs, with a ragged
+# slab (1001), whole slabs and one row (1537), a second ahz chunk of one row
+# (2049) and of 553 rows (2601).
 @pytest.mark.parametrize("kind", ["RID_RESIDUAL_DOT2", "RID_RESIDUAL_FP64", "RID_RESIDUAL_FP32"])
 @pytest.mark.parametrize("dt", [np.complex64, np.complex128])
-@pytest.mark.parametrize("m,n,rho", [(1000, 500, 1e-3), (1600, 300, 1e-6)])
+@pytest.mark.parametrize("m,n,rho", [(1000, 500, 1e-3), (1600, 300, 1e-6), (1001, 301, 1e-3),
+                                     (1537, 300, 1e-6), (2049, 200, 1e-3), (2601, 151, 1e-6)])
 def test_residual_accumulation_kinds_call_for_call(h, kind, dt, m, n, rho):
     k, l, q = 20, 30, 6
     A = lowrank64(m, n, k, rho, seed=m + 1).astype(dt)
@@ -176,20 +180,36 @@ def test_residual_follows_the_form_by_default(h):
     assert ei.value.status == rid.RID_ERR_INVALID_ARG
 
 
-@pytest.mark.parametrize("m,n,pad", [(1600, 300, 2), (1600, 300, 1)])
-def test_residual_complex64_padded_leading_dimension(h, m, n, pad):
-    # three whole 512-row slabs and a ragged one; lda = m + 2 keeps 16-byte
-    # pairs (the whole-slab fast path of the ax pass), lda = m + 1 does not
+@pytest.mark.parametrize("kind", ["RID_RESIDUAL_DOT2", "RID_RESIDUAL_FP64", "RID_RESIDUAL_FP32"])
+@pytest.mark.parametrize("m,n,pad,offset", [(1600, 300, 2, 0), (1600, 300, 1, 0),
+                                            (1600, 300, 3, 0), (1601, 300, 0, 1),
+                                            (1600, 300, 2, 1), (1024, 300, 1, 0)])
+def test_residual_complex64_padded_leading_dimension(h, kind, m, n, pad, offset):
+    # three whole 512-row slabs and a ragged one (or two whole slabs, which
+    # with an odd lda take the general loop); lda = m + pad, even or odd
+    # (odd: every other column starts 8 bytes past a 16-byte boundary); with
+    # offset 1 the matrix starts one entry into its buffer, so its base is
+    # not 16-byte aligned and no pair loads are taken
     k, l, q = 12, 20, 6
     A = lowrank64(m, n, k, 1e-3, seed=m + pad)
-    r = oracle.decompose(A.astype(np.complex128), k, l, seed=3, q=q)
-    buf = torch.zeros((n, m + pad), dtype=torch.complex64, device="cuda")
+    A128 = A.astype(np.complex128)
+    r = oracle.decompose(A128, k, l, seed=3, q=q)
+    ld = m + pad
+    flat = torch.zeros(offset + ld * n, dtype=torch.complex64, device="cuda")
+    buf = flat[offset:].view(n, ld)
     buf[:, :m] = torch.from_numpy(np.ascontiguousarray(A.T)).to("cuda")
     Ad = buf[:, :m].t()                       # m x n, column stride m + pad
-    assert Ad.stride() == (1, m + pad)
-    sigma, hist = rid.rid_residual(h, Ad, torch.from_numpy(r["J"]).cuda(), dev(r["P"]), q, 3)
-    assert abs(float(host(sigma)[0]) - r["sigma"]) <= 1e-10 * r["sigma"]
-    assert np.all(np.abs(host(hist) - r["hist"]) <= 1e-10 * r["hist"])
+    assert Ad.stride() == (1, ld)
+    assert (Ad.data_ptr() % 16 == 0) == (offset == 0)
+    rid.rid_set_residual(h, getattr(rid, kind))
+    try:
+        sigma, hist = rid.rid_residual(h, Ad, torch.from_numpy(r["J"]).cuda(), dev(r["P"]), q, 3)
+    finally:
+        rid.rid_set_residual(h, rid.RID_RESIDUAL_AUTO)
+    acc = {"RID_RESIDUAL_DOT2": "dot2", "RID_RESIDUAL_FP64": "fp64",
+           "RID_RESIDUAL_FP32": "fp32"}[kind]
+    check_sigma_call_for_call(A128, r["J"], r["P"], float(host(sigma)[0]), 3, q, acc=acc,
+                              hist=host(hist))
 
 
 # per form: (pivot-gap tolerance tau_J, P bar relative to max(1, max|P|),
