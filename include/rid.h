@@ -442,9 +442,11 @@ rid_status rid_tune_batched(rid_handle h, hipStream_t stream, rid_dtype dtype, r
 /* ---------------------------------------------------------------- serving */
 
 /* A request loop on one device with continuous batching: requests arrive at
- * any time (rid_server_submit); each is admitted as soon as its device
- * footprint fits the memory budget beside the jobs already admitted, and
- * admitted jobs run while others are still running.  Jobs whose A has fewer
+ * any time (rid_server_submit); each is admitted as soon as its data and the
+ * workspace its lane must add for it fit the memory budget beside the data
+ * of the jobs already admitted and the workspaces the lanes hold (a lane
+ * keeps its workspace between jobs; when a group cannot fit, idle lanes free
+ * theirs), and admitted jobs run while others are still running.  Jobs whose A has fewer
  * than big_bytes bytes are grouped, per (dtype, prec, q, max_retries,
  * rank_tol), into batches of up to max_batch that run as one
  * rid_decompose_batched call (one job alone: rid_decompose); larger jobs run
@@ -456,7 +458,8 @@ rid_status rid_tune_batched(rid_handle h, hipStream_t stream, rid_dtype dtype, r
 typedef struct rid_server_ctx *rid_server;
 
 typedef struct {
-  int64_t hbm_budget; /* device bytes that admitted jobs may hold at once */
+  int64_t hbm_budget; /* device bytes that admitted jobs' data and the lanes'
+                         workspaces may hold at once */
   int64_t big_bytes;  /* A of at least this many bytes: a big job */
   int big_lanes;      /* big jobs running at once (0: big jobs are batched too) */
   int batch_lanes;    /* batches running at once (>= 1) */
@@ -486,9 +489,9 @@ typedef int (*rid_admit_fn)(void *ctx, uint64_t ticket, hipStream_t stream, rid_
 typedef void (*rid_done_fn)(void *ctx, uint64_t ticket, int status, uint64_t seed_used,
                             const double *times);
 
-/* Start the lanes on `device`.  A job's footprint is bytes(A) + fill_bytes
- * + its outputs + the workspace of rid_decompose for its shape.  Errors:
- * INVALID_ARG, HIP, NOMEM.                                               */
+/* Start the lanes on `device`.  A job's data is bytes(A) + fill_bytes + its
+ * outputs; its footprint is that + the workspace of rid_decompose for its
+ * shape.  Errors: INVALID_ARG, HIP, NOMEM.                                */
 rid_status rid_server_create(rid_server *s, int device, const rid_server_config *cfg,
                              rid_admit_fn admit, rid_done_fn done, void *ctx);
 
@@ -500,7 +503,8 @@ rid_status rid_server_submit(rid_server s, const rid_request *req, uint64_t *tic
 /* Block until every submitted job is done.                               */
 rid_status rid_server_drain(rid_server s);
 
-/* Peak admitted footprint (bytes), jobs completed, and batches run so far
+/* Peak of the counted bytes (admitted data, reserved workspace growth and
+ * the workspaces the lanes hold), jobs completed, and batches run so far
  * (host out-pointers; any may be null).                                   */
 rid_status rid_server_stats(rid_server s, int64_t *peak_bytes, int64_t *completed,
                             int64_t *batches);

@@ -140,11 +140,29 @@ size_t bytes_decomp(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, 
 
 thread_local bool rid_tl_short_blocks = false;
 
+size_t ws_grow_bytes(const rid_ctx *h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return 0;
+  const size_t exact = (bytes + 4095) & ~size_t(4095);
+  const size_t want = h->ws_bytes + h->ws_bytes / 2;
+  return (want < exact) ? exact : ((want + 4095) & ~size_t(4095));
+}
+
+size_t ws_held_bytes(const rid_ctx *h) { return h->ws_bytes + h->retired_bytes; }
+
+void release_ws(rid_handle h) {
+  DeviceGuard g(h->device);
+  if (h->ws) (void)hipFree(h->ws);
+  for (void *p : h->retired) (void)hipFree(p);
+  h->ws = nullptr;
+  h->ws_bytes = 0;
+  h->retired.clear();
+  h->retired_bytes = 0;
+}
+
 hipError_t grow_ws(rid_handle h, size_t bytes) {
   if (bytes <= h->ws_bytes) return hipSuccess;
   const size_t exact = (bytes + 4095) & ~size_t(4095);
-  size_t want = h->ws_bytes + h->ws_bytes / 2;
-  want = (want < exact) ? exact : ((want + 4095) & ~size_t(4095));
+  size_t want = ws_grow_bytes(h, bytes);
   void *p = nullptr;
   hipError_t e = hipMalloc(&p, want);
   if (e != hipSuccess && want > exact) {
@@ -156,7 +174,10 @@ hipError_t grow_ws(rid_handle h, size_t bytes) {
     (void)hipGetLastError();
     return e;
   }
-  if (h->ws) h->retired.push_back(h->ws);
+  if (h->ws) {
+    h->retired.push_back(h->ws);
+    h->retired_bytes += h->ws_bytes;
+  }
   h->ws = p;
   h->ws_bytes = want;
   return hipSuccess;

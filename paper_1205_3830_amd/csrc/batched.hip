@@ -93,10 +93,11 @@ bool batch_job_supported(const RidBatchJob &j) {
 }
 
 // Runs one batch (each job once, with the seeds in bj); writes per-job
-// status (host).  ws: device workspace of batch_ws_bytes(...) bytes.
-hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
-                     const RidBatchJob *bj, int count, int q, double rank_tol, int *status,
-                     RidProf *prof) {
+// status (host).  With need_only non-null it only plans: the workspace size
+// goes there and nothing touches the device.
+static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dtype,
+                                 rid_prec prec, const RidBatchJob *bj, int count, int q,
+                                 double rank_tol, int *status, RidProf *prof, size_t *need_only) {
   // ---- plans and workspace layout
   std::vector<SketchJob> sk(count);
   std::vector<OpJob> op(count);
@@ -202,6 +203,10 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
     tabbytes = (probe.bytes.size() + 255) & ~size_t(255);
   }
   const size_t total = tabbytes + persist + scratch + 256;
+  if (need_only) {
+    *need_only = total;
+    return hipSuccess;
+  }
   // the residual descriptors need the final scratch base: set it up now
   hipError_t err = hipSuccess;
   {
@@ -312,6 +317,19 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
   err = hipMemcpyAsync(status, dstatus, sizeof(int) * count, hipMemcpyDeviceToHost, stream);
   if (err == hipSuccess) err = hipStreamSynchronize(stream);
   return err;
+}
+
+hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
+                     const RidBatchJob *bj, int count, int q, double rank_tol, int *status,
+                     RidProf *prof) {
+  return run_batch_impl(h, stream, dtype, prec, bj, count, q, rank_tol, status, prof, nullptr);
+}
+
+size_t batch_ws_need(rid_handle h, rid_dtype dtype, rid_prec prec, const RidBatchJob *bj,
+                     int count, int q) {
+  size_t need = 0;
+  (void)run_batch_impl(h, nullptr, dtype, prec, bj, count, q, 0.0, nullptr, nullptr, &need);
+  return need;
 }
 
 extern "C" rid_status rid_decompose_batched(rid_handle h, hipStream_t stream, rid_dtype dtype,

@@ -63,6 +63,7 @@ struct rid_ctx {
   void *ws = nullptr;       // grow-only workspace
   size_t ws_bytes = 0;
   std::vector<void *> retired;  // superseded workspaces, freed by rid_destroy
+  size_t retired_bytes = 0;     // their total size
   RidProf prof;
   int sketch_kind = RID_SKETCH_GAUSSIAN;  // operator drawn by rid_sketch / rid_decompose
   int qr_kind = RID_QR_HOUSEHOLDER;       // method of rid_pivqr / rid_decompose
@@ -418,6 +419,15 @@ bool batch_prec_supported(rid_prec prec);
 // work still in flight may use it, and growing never waits for the device
 // (hipFree would wait for every stream, other callers' included).
 hipError_t grow_ws(rid_handle h, size_t bytes);
+// The bytes grow_ws(h, bytes) would allocate (0 when the workspace is large
+// enough already); at most that, as grow_ws may fall back to the exact size.
+size_t ws_grow_bytes(const rid_ctx *h, size_t bytes);
+// Device memory the handle's workspaces hold: the current one and the
+// superseded ones.
+size_t ws_held_bytes(const rid_ctx *h);
+// Free the handle's workspaces (hipFree: waits for the whole device).  Only
+// for a handle with no work in flight; the next call grows it again.
+void release_ws(rid_handle h);
 // Device workspace rid_decompose needs for one ID of this shape.
 size_t decomp_ws_bytes(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t k, int64_t l,
                        int q);
@@ -425,6 +435,11 @@ size_t decomp_ws_bytes(rid_dtype dt, rid_prec pr, int64_t m, int64_t n, int64_t 
 hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec prec,
                      const RidBatchJob *bj, int count, int q, double rank_tol, int *status,
                      RidProf *prof = nullptr);
+// The workspace bytes run_batch needs for these jobs under the handle's plan
+// (host planning only: no device call; the jobs' A, lda and outputs are not
+// read).  A subset of the jobs needs no more.
+size_t batch_ws_need(rid_handle h, rid_dtype dtype, rid_prec prec, const RidBatchJob *bj,
+                     int count, int q);
 
 // Grouped interpolation (k <= 256): tab entries (job, column quad).
 hipError_t launch_interp_batch(hipStream_t st, int kmax, const InterpJob *djobs,

@@ -3,18 +3,28 @@
 // caller would (rid_decompose_batched for a batch, rid_decompose for a job
 // alone), each lane on its own handle and non-blocking stream.
 //
-// Admission is by device footprint: a request waits in its class queue
-// (small or big) until bytes(A) + fill scratch + outputs + the workspace
-// of its shape fit the budget beside the jobs already admitted.  A batch
-// lane takes the oldest small request and every later queued small request
-// with the same (dtype, prec, q, max_retries, rank_tol) that still fits, up
-// to max_batch, so requests that arrived while the previous batch ran join
-// the next one.  Big lanes take one big request each.  All lanes run at
-// once, so a long big job does not hold up the small ones: lane threads use
-// the short-workgroup plans (a workgroup of a big ID frees its CU slots
-// within about a millisecond), and a lane never synchronises the whole
-// device (workspaces grow without freeing, streams are non-blocking, and
-// lanes launch batches directly rather than capturing graphs).
+// Admission is by device footprint.  The budget covers the data of the
+// admitted requests (bytes(A) + fill scratch + outputs) and every device
+// workspace the lanes hold: a lane's handle keeps its workspace, and the
+// superseded ones, between requests, and all of it stays counted while it
+// is held.  A group is admitted on a lane when its data plus the workspace
+// the lane would allocate for it (exact: the single-ID workspace for a job
+// alone, the batch planner's figure for a batch) fits beside what is
+// counted already.  A batch lane takes the oldest small request and every
+// later queued small request with the same (dtype, prec, q, max_retries,
+// rank_tol) that still fits, up to max_batch, so requests that arrived while
+// the previous batch ran join the next one; big lanes take one big request
+// each.  When a lane's group does not fit, every idle lane that holds a
+// workspace frees it (hipFree, which waits for the device: this happens
+// only when the budget is short); a request whose data and workspace exceed
+// the budget alone is refused at submission, so a waiting group fits once
+// the work ahead of it is done and the idle lanes have let go.  All lanes
+// run at once, so a long big job does not hold up the small ones: lane
+// threads use the short-workgroup plans (a workgroup of a big ID frees its
+// CU slots within about a millisecond), and otherwise a lane never
+// synchronises the whole device (workspaces grow without freeing, streams
+// are non-blocking, and lanes launch batches directly rather than capturing
+// graphs).
 #include <chrono>
 #include <cmath>
 #include <condition_variable>
@@ -30,8 +40,9 @@ namespace {
 struct SrvJob {
   uint64_t ticket;
   rid_request req;
-  int64_t footprint;
-  double t[4];  // arrival, admission, A in place, done
+  int64_t data;       // bytes(A) + fill scratch + outputs
+  int64_t footprint;  // data + the workspace of the job run alone
+  double t[4];        // arrival, admission, A in place, done
 };
 
 bool same_group(const rid_request &a, const rid_request &b) {
@@ -53,7 +64,9 @@ struct rid_server_ctx {
   std::condition_variable cv;       // queue or budget changed
   std::condition_variable idle_cv;  // a job finished
   std::deque<SrvJob> small_q, big_q;
+  // admitted data + reserved workspace growth + workspace the lanes hold
   int64_t committed = 0, peak = 0;
+  int blocked = 0;  // lanes whose next group does not fit
   int64_t pending = 0;  // submitted, not yet done
   int64_t completed = 0, batches = 0;
   uint64_t next_ticket = 1;
@@ -63,6 +76,8 @@ struct rid_server_ctx {
     rid_handle h = nullptr;
     hipStream_t st = nullptr;
     bool big = false;
+    int64_t held = 0;      // workspace bytes the handle holds (counted)
+    int64_t reserved = 0;  // workspace growth reserved for the running group
   };
   std::vector<Lane> lanes;
   std::vector<std::thread> threads;
@@ -70,20 +85,26 @@ struct rid_server_ctx {
   double now() const {
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   }
-  bool fits(int64_t fp) const { return committed + fp <= cfg.hbm_budget; }
+  bool fits(int64_t bytes) const { return committed + bytes <= cfg.hbm_budget; }
 };
 
 namespace {
 
-void finish(rid_server s, std::vector<SrvJob> &jobs, const std::vector<int> &status,
-            const std::vector<uint64_t> &used) {
+void finish(rid_server s, rid_server_ctx::Lane &ln, std::vector<SrvJob> &jobs,
+            const std::vector<int> &status, const std::vector<uint64_t> &used) {
   const double t = s->now();
   for (size_t i = 0; i < jobs.size(); ++i) {
     jobs[i].t[3] = t;
     if (s->done) s->done(s->user, jobs[i].ticket, status[i], used[i], jobs[i].t);
   }
   std::lock_guard<std::mutex> lk(s->mu);
-  for (const SrvJob &j : jobs) s->committed -= j.footprint;
+  for (const SrvJob &j : jobs) s->committed -= j.data;
+  // the reservation becomes what the handle now holds (at most as much)
+  const int64_t held = static_cast<int64_t>(ws_held_bytes(ln.h));
+  s->committed += held - ln.held - ln.reserved;
+  ln.held = held;
+  ln.reserved = 0;
+  if (s->committed > s->peak) s->peak = s->committed;
   s->pending -= static_cast<int64_t>(jobs.size());
   s->completed += static_cast<int64_t>(jobs.size());
   s->cv.notify_all();
@@ -147,7 +168,78 @@ void run_group(rid_server s, rid_server_ctx::Lane &ln, std::vector<SrvJob> &jobs
     std::lock_guard<std::mutex> lk(s->mu);
     ++s->batches;
   }
-  finish(s, jobs, status, used);
+  finish(s, ln, jobs, status, used);
+}
+
+// Workspace a lane's handle needs for one request alone (rid_decompose),
+// with the lanes' short-workgroup plans whatever the calling thread.
+size_t single_need(const rid_request &r) {
+  const bool prev = rid_tl_short_blocks;
+  rid_tl_short_blocks = true;
+  const size_t ws = decomp_ws_bytes(r.dtype, r.prec, r.m, r.n, r.k, r.l, r.q);
+  rid_tl_short_blocks = prev;
+  return ws;
+}
+
+int64_t data_of(const rid_request &r) {
+  const int64_t es = r.dtype == RID_C128 ? 16 : 8;
+  return r.m * r.n * es + r.fill_bytes + r.k * r.n * 16 + r.k * 8 + 8;
+}
+
+// Workspace growth of lane ln for a group: a group that the fill callbacks
+// reduce to one job runs alone, a larger one as a batch (whose subsets need
+// no more), so the reservation covers both.  Host planning only.
+int64_t group_growth(const rid_server_ctx::Lane &ln, const std::vector<const SrvJob *> &g) {
+  size_t need = 0;
+  for (const SrvJob *j : g) need = std::max(need, single_need(j->req));
+  if (g.size() > 1) {
+    std::vector<RidBatchJob> bj;
+    for (const SrvJob *j : g) {
+      const rid_request &r = j->req;
+      bj.push_back(RidBatchJob{r.m, r.n, r.k, r.l, r.m, r.k, nullptr, r.seed, nullptr, nullptr,
+                               nullptr});
+    }
+    const rid_request &r0 = g[0]->req;
+    need = std::max(need, batch_ws_need(ln.h, r0.dtype, r0.prec, bj.data(),
+                                        static_cast<int>(bj.size()), r0.q));
+  }
+  return static_cast<int64_t>(ws_grow_bytes(ln.h, need));
+}
+
+// Under the lock: the next group of queue q for lane ln if it fits (then it
+// leaves the queue and is counted), else false.  The group is the oldest
+// request and later ones of its kind, while their data fit; then halved
+// until data and workspace growth fit together.
+bool take_group(rid_server s, rid_server_ctx::Lane &ln, std::deque<SrvJob> &q,
+                std::vector<SrvJob> &group) {
+  const int cap = ln.big ? 1 : s->cfg.max_batch;
+  const rid_request key = q.front().req;
+  std::vector<std::deque<SrvJob>::iterator> pick;
+  int64_t data = 0;
+  for (auto it = q.begin(); it != q.end() && static_cast<int>(pick.size()) < cap; ++it) {
+    if (!same_group(key, it->req)) continue;
+    if (!s->fits(data + it->data)) break;  // keep arrival order within a group
+    pick.push_back(it);
+    data += it->data;
+  }
+  while (!pick.empty()) {
+    std::vector<const SrvJob *> g;
+    for (auto it : pick) g.push_back(&*it);
+    const int64_t growth = group_growth(ln, g);
+    if (s->fits(data + growth)) {
+      s->committed += data + growth;
+      ln.reserved = growth;
+      if (s->committed > s->peak) s->peak = s->committed;
+      for (auto it : pick) group.push_back(*it);
+      for (auto r = pick.rbegin(); r != pick.rend(); ++r) q.erase(*r);
+      return true;
+    }
+    if (pick.size() == 1) break;
+    const size_t keep = pick.size() / 2;
+    for (size_t i = keep; i < pick.size(); ++i) data -= pick[i]->data;
+    pick.resize(keep);
+  }
+  return false;
 }
 
 void lane_main(rid_server s, int id) {
@@ -159,35 +251,42 @@ void lane_main(rid_server s, int id) {
     {
       std::unique_lock<std::mutex> lk(s->mu);
       std::deque<SrvJob> &q = ln.big ? s->big_q : s->small_q;
-      s->cv.wait(lk, [&] { return (!q.empty() && s->fits(q.front().footprint)) || (s->stop && q.empty()); });
-      if (q.empty()) return;  // stop with nothing left
-      const int cap = ln.big ? 1 : s->cfg.max_batch;
-      const rid_request key = q.front().req;
-      for (auto it = q.begin(); it != q.end() && static_cast<int>(group.size()) < cap;) {
-        if (!same_group(key, it->req)) {
-          ++it;
+      bool waiting = false;  // counted in s->blocked
+      for (;;) {
+        if (!q.empty() && take_group(s, ln, q, group)) break;
+        const bool stuck = !q.empty();
+        if (stuck != waiting) {
+          s->blocked += stuck ? 1 : -1;
+          waiting = stuck;
+          s->cv.notify_all();
+        }
+        if (q.empty() && s->stop) return;  // stop with nothing left
+        if (s->blocked > 0 && ln.held > 0) {
+          // an idle lane lets its workspace go while some group cannot fit
+          const int64_t held = ln.held;
+          lk.unlock();
+          release_ws(ln.h);
+          lk.lock();
+          s->committed -= held;
+          ln.held = 0;
+          s->cv.notify_all();
           continue;
         }
-        if (!s->fits(it->footprint)) break;  // keep arrival order within a group
-        s->committed += it->footprint;
-        group.push_back(*it);
-        it = q.erase(it);
+        s->cv.wait(lk);
       }
-      if (s->committed > s->peak) s->peak = s->committed;
+      if (waiting) {
+        --s->blocked;
+        s->cv.notify_all();
+      }
     }
     run_group(s, ln, group);
   }
 }
 
-// sized with the lanes' short-workgroup plans, whatever the calling thread
+// The footprint of a request run alone on a lane that holds nothing.
 int64_t footprint_of(const rid_request &r) {
-  const int64_t es = r.dtype == RID_C128 ? 16 : 8;
-  const bool prev = rid_tl_short_blocks;
-  rid_tl_short_blocks = true;
-  const int64_t ws =
-      static_cast<int64_t>(decomp_ws_bytes(r.dtype, r.prec, r.m, r.n, r.k, r.l, r.q));
-  rid_tl_short_blocks = prev;
-  return r.m * r.n * es + r.fill_bytes + r.k * r.n * 16 + r.k * 8 + 8 + ws;
+  const size_t ws = single_need(r);
+  return data_of(r) + static_cast<int64_t>((ws + 4095) & ~size_t(4095));
 }
 
 }  // namespace
@@ -258,6 +357,7 @@ rid_status rid_server_submit(rid_server s, const rid_request *req, uint64_t *tic
   }
   SrvJob j{};
   j.req = r;
+  j.data = data_of(r);
   j.footprint = footprint_of(r);
   if (j.footprint > s->cfg.hbm_budget) return RID_ERR_NOMEM;
   {

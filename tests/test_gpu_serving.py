@@ -13,6 +13,9 @@ admission by device footprint.
   big job is still running (their work overlaps on the device).
 * A failing fill callback fails only its own job; a request larger than the
   budget is refused at submission.
+* The lanes' workspaces stay counted while held: a request that fits the
+  budget only if an idle lane gives its workspace up waits for that, and
+  then runs.
 """
 import threading
 
@@ -174,5 +177,57 @@ def test_failures_are_per_request(h):
         assert srv.result(bad)["status"] == rid.RID_ERR_INVALID_ARG
         assert "on purpose" in srv.result(bad)["error"]
         assert all(srv.result(t)["status"] == 0 for t in ok)
+    finally:
+        srv.close()
+
+
+def _footprint(m, n, k, l, dtype, q):
+    """The smallest budget that accepts the request at submission (its data
+    and its workspace alone), by bisection on the submit-time refusal."""
+    def refuse(ticket, req):
+        raise RuntimeError("probe only")
+
+    def accepted(budget):
+        srv = rid.RidServer(refuse, hbm_budget=budget, big_lanes=0, batch_lanes=1, max_batch=1)
+        try:
+            srv.submit(m, n, k, l, dtype=dtype, seed=0, q=q)
+            return True
+        except rid.RidError as e:
+            assert e.status == rid.RID_ERR_NOMEM
+            return False
+        finally:
+            srv.close()
+
+    es = 16 if dtype == rid.RID_C128 else 8
+    lo, hi = m * n * es + k * n * 16, m * n * es + (1 << 34)   # refused, accepted
+    assert not accepted(lo) and accepted(hi)
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if accepted(mid):
+            hi = mid
+        else:
+            lo = mid
+    return hi
+
+
+def test_admission_counts_held_workspaces(h):
+    # Job 2 fits the budget only with every lane's workspace let go: after
+    # job 1, its lane holds job 1's workspace (more than 1 MiB), so job 2
+    # waits until that idle lane frees it, then runs.
+    inp = Inputs()
+    j1 = (16384, 4096, 16, 24)
+    j2 = (32768, 4096, 16, 24)
+    f2 = _footprint(*j2, rid.RID_C128, 3)
+    budget = f2 + (1 << 20)
+    srv = rid.RidServer(inp.fill, hbm_budget=budget, big_bytes=1 << 20, big_lanes=2,
+                        batch_lanes=1, max_batch=8)
+    try:
+        t1 = srv.submit(*j1, dtype=rid.RID_C128, seed=1, q=3, rank=16, noise=1e-10, gen_seed=31)
+        t2 = srv.submit(*j2, dtype=rid.RID_C128, seed=2, q=3, rank=16, noise=1e-10, gen_seed=32)
+        srv.drain()
+        r1, r2 = srv.result(t1), srv.result(t2)
+        assert r1["status"] == 0 and r2["status"] == 0
+        assert r2["times"][1] >= r1["times"][3]            # admitted after job 1 was done
+        assert 0 < srv.stats()["peak_bytes"] <= budget
     finally:
         srv.close()
