@@ -49,7 +49,10 @@ constexpr int PX_JC = 256;     // columns per workgroup of the P x partials
 constexpr int RES_KMAX = 1024; // LDS holds u_J for k <= RES_KMAX
 
 struct ResPlan {
-  int64_t nb_ax;   // ax row blocks
+  int64_t nb_ax;   // ax row blocks (ax_h rows each)
+  int ax_h;        // rows per ax row block: 512, or 256 / 128 for the paired complex64
+                   // body, whose workgroup then takes 512 / ax_h column splits
+  int64_t nb_axy;  // ax grid y: column splits / (512 / ax_h), rounded up
   int64_t S_z;     // ax column splits
   int64_t cpz;     // columns per ax split
   int64_t S_u;     // ahz row splits
@@ -77,6 +80,8 @@ ResPlan plan_res(int64_t m, int64_t n, int64_t k, int64_t target_blocks, int ahz
   if ((n + p.cpz - 1) / p.cpz > 65535) p.cpz = (n + 65534) / 65535;  // grid y
   p.S_z = (n + p.cpz - 1) / p.cpz;
   if (p.S_z < 1) p.S_z = 1;
+  p.ax_h = AX_ROWS;
+  p.nb_axy = p.S_z;
   p.rpu = AHZ_RS;
   p.S_u = (m + p.rpu - 1) / p.rpu;
   if (p.S_u < 1) p.S_u = 1;
@@ -86,6 +91,16 @@ ResPlan plan_res(int64_t m, int64_t n, int64_t k, int64_t target_blocks, int ahz
   p.nb_n = (n + 255) / 256;
   p.nb_m = (m + 255) / 256;
   return p;
+}
+
+// Row blocks of h rows for the ax pass (h = 128, 256 or 512): the column
+// splits stay as planned, a workgroup takes 512 / h of them, so a workgroup
+// still covers about the same bytes of A.
+void set_ax_rows(ResPlan &p, int64_t m, int h) {
+  p.ax_h = h;
+  p.nb_ax = (m + h - 1) / h;
+  const int64_t g = AX_ROWS / h;
+  p.nb_axy = (p.S_z + g - 1) / g;
 }
 
 // One power-iteration problem: sizes, inputs, plan and workspace.
@@ -438,9 +453,11 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
 // thread 0, the row before it by the previous slab.  The z reduction adds
 // all four words.  Every thread makes one 16-byte load per column.  Rows
 // past m are loaded from 16-byte granules that hold a row of the column (so
-// never from an unmapped page) and zeroed.  With lda odd this needs
-// m % 512 != 0 (so that the last slab's thread reaches row m - 1); the
-// caller takes the general loop otherwise.
+// never from an unmapped page) and zeroed.  Row blocks are ax_h rows: 512
+// (the general layout), or 256 / 128 for a short or ragged m, where the
+// workgroup's thread groups take separate column splits.  With lda odd this
+// needs m % ax_h != 0 (so that the last block's thread reaches row m - 1);
+// the caller takes the general loop otherwise.
 template <int ACC>
 RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
   static_assert(ACC != RES_DOT2, "plain sums only");
@@ -450,17 +467,24 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
   const float2 *A = static_cast<const float2 *>(r.A);
   const int64_t m = r.m, lda = r.lda;
   const int t = threadIdx.x;
-  const int64_t i0 = bx * AX_ROWS + 2 * t;
+  // the workgroup's threads form 512 / h groups of h / 2 threads; group g
+  // takes rows [h bx, h bx + h) of column split by (512 / h) + g
+  const int h = r.pl.ax_h;
+  const int half = h >> 1;
+  const int tg = t % half;
+  const int64_t split = by * (AX_ROWS / h) + t / half;
+  const int64_t i0 = bx * h + 2 * tg;
   const bool ok0 = i0 < m, ok1 = i0 + 1 < m;
   const bool okm = i0 >= 1 && i0 - 1 < m;  // row i0 - 1 of a shifted pair
   const bool odd = (lda & 1) != 0;
-  // a wave whose rows (shifted ones included) all lie past m has no loads
-  const bool live = bx * AX_ROWS + 128 * (t >> 6) - 1 < m;
+  // a wave whose rows (shifted ones included) all lie past m, or whose
+  // split lies past the last one, has no loads
+  const bool live = bx * h + 128 * (tg >> 6) - 1 < m && split < r.pl.S_z;
   // pair starts: unshifted (i0, or row 0 past m); shifted (i0 - 1, or row
   // -1 past m: the previous column's last stored entry, as j >= 1 there)
   const int64_t pu = ok0 ? i0 : 0;
   const int64_t ps = (i0 - 1 < m) ? i0 - 1 : -1;
-  const int64_t jb = by * r.pl.cpz;
+  const int64_t jb = split * r.pl.cpz;
   const int64_t je = live ? min(r.n, jb + r.pl.cpz) : jb;
   const double2 *__restrict__ xth = r.xth;
   Acc s0r = 0, s0i = 0, s1r = 0, s1i = 0;  // rows i0, i0 + 1 (unshifted columns)
@@ -537,7 +561,8 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
   }
   // words 0 and 2 of rows i0, i0 + 1; words 1 and 3 of rows i0 - 1, i0
   // (zero for lda even)
-  double *zp = r.zpart + by * m * 4;
+  if (split >= r.pl.S_z) return;
+  double *zp = r.zpart + split * m * 4;
   if (ok0) {
     zp[i0 * 4 + 0] = static_cast<double>(s0r);
     zp[i0 * 4 + 1] = static_cast<double>(snr);
@@ -860,7 +885,7 @@ RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
   if constexpr (STEP == ST_PXF) px_final_body(r, bx);
   if constexpr (STEP == ST_AX) {
     if constexpr (sizeof(TA) == 8 && ACC != RES_DOT2) {
-      if (r.al16 && r.m >= 2 && ((r.lda & 1) == 0 || r.m % AX_ROWS != 0)) {
+      if (r.al16 && r.m >= 2 && ((r.lda & 1) == 0 || r.m % r.pl.ax_h != 0)) {
         ax_c64_paired<ACC>(r, bx, by);
         return;
       }
@@ -915,7 +940,7 @@ void step_grid(int step, const ResJob &r, int64_t &gx, int64_t &gy) {
     case ST_WNORM: case ST_SIGMA: gx = 1; break;
     case ST_PXP: gx = r.k > 0 ? p.nb_px : 0; break;
     case ST_PXF: gx = r.k > 0 ? p.nb_k : 0; break;
-    case ST_AX: gx = p.nb_ax; gy = p.S_z; break;
+    case ST_AX: gx = p.nb_ax; gy = p.nb_axy; break;
     case ST_ZF: gx = p.nb_m; break;
     case ST_AHZ: gx = p.ahz_cpw == 8 ? p.nb_ahz : 0; gy = p.S_u; break;
     case ST_AHZ4: gx = p.ahz_cpw == 4 ? p.nb_ahz : 0; gy = p.S_u; break;
@@ -1015,6 +1040,23 @@ void grouped_iteration(hipStream_t st, const ResJob *jobs, const int4 *dtab,
       q);
 }
 
+// Rows per ax block for the paired complex64 body of a batch job: the one
+// of 512, 256, 128 that pads m least (the larger on a tie), among those it
+// can take (an odd lda needs m % h != 0).
+int pick_ax_rows(int64_t m, int64_t lda) {
+  int best = 0;
+  int64_t pad = 0;
+  for (int h = AX_ROWS; h >= 128; h >>= 1) {
+    if ((lda & 1) && m % h == 0) continue;
+    const int64_t p = (m + h - 1) / h * h - m;
+    if (best == 0 || p < pad) {
+      best = h;
+      pad = p;
+    }
+  }
+  return best ? best : AX_ROWS;
+}
+
 bool al16_ok(rid_dtype dtype, const void *A) {
   return dtype == RID_C64 && (reinterpret_cast<uintptr_t>(A) % 16 == 0);
 }
@@ -1096,6 +1138,8 @@ void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, int
     const int64_t abytes = r.m * r.n * (dtype == RID_C64 ? 8 : 16);
     r.pl = plan_res(r.m, r.n, r.k,
                     std::min<int64_t>(2048, std::max<int64_t>(1, abytes / block_bytes)), ahz_cpw);
+    if (dtype == RID_C64 && acc != RES_DOT2 && r.al16 && r.m >= 2)
+      set_ax_rows(r.pl, r.m, pick_ax_rows(r.m, r.lda));
     carve_res(c, r);
   }
   out->ws_bytes = c.off + 256;
