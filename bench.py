@@ -432,16 +432,33 @@ def bench_sweep(args, torch, rid, synth) -> int:
     return 0
 
 
+QR_SHAPES = [(108, 16384, 100), (200, 16384, 100), (800, 16384, 400), (2000, 65536, 1000),
+             (800, 1 << 18, 400), (2000, 1 << 18, 1000)]
+
+
 def bench_qr(args, torch, rid, synth) -> int:
     """The two pivoted-QR methods on the same sketches (l x n, first k
-    pivots): Householder against CGS2, Sec. 3.2's comparison."""
-    shapes = [(108, 16384, 100), (200, 16384, 100), (800, 16384, 400), (2000, 65536, 1000)]
+    pivots): Householder against CGS2, Sec. 3.2's comparison.  The last two
+    shapes are the Y of the sweep's k = 400 and k = 1000 rows at n = 2^18
+    (the panel form)."""
+    idx = range(len(QR_SHAPES)) if args.shapes == "all" else [int(x) for x in args.shapes.split(",")]
+    kinds = [("householder", rid.RID_QR_HOUSEHOLDER), ("cgs2", rid.RID_QR_CGS2)]
+    if args.qr_kinds != "both":
+        kinds = [kd for kd in kinds if kd[0] == args.qr_kinds]
+    if args.copy_calibration:
+        src = torch.ones(1 << 27, dtype=torch.float64, device="cuda")   # 1 GiB
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     h = rid.rid_create(0)
     rows = []
-    for l, n, k in shapes:
+    for i in idx:
+        l, n, k = QR_SHAPES[i]
         Y0 = synth.lowrank_device(l, n, k, 1e-10, seed=l).t()   # l x n, column-major
         res = {}
-        for name, kind in (("householder", rid.RID_QR_HOUSEHOLDER), ("cgs2", rid.RID_QR_CGS2)):
+        for name, kind in kinds:
             rid.rid_set_qr(h, kind)
             Y = Y0.clone()
             rid.rid_pivqr(h, Y, k)                                 # warm-up
@@ -457,11 +474,15 @@ def bench_qr(args, torch, rid, synth) -> int:
                 ms, _ = rid.rid_profile_read(h, rid.RID_KERNEL_PIVQR)
                 best = ms if best is None else min(best, ms)
             res[name] = {"ms": best, "J": perm[:k].cpu()}
-        same = bool(torch.equal(res["householder"]["J"], res["cgs2"]["J"]))
-        rows.append({"l": l, "n": n, "k": k, "householder_ms": res["householder"]["ms"],
-                     "cgs2_ms": res["cgs2"]["ms"],
-                     "cgs2_over_householder": res["cgs2"]["ms"] / res["householder"]["ms"],
-                     "same_J": same})
+        row = {"l": l, "n": n, "k": k}
+        for name in res:
+            row[name + "_ms"] = res[name]["ms"]
+        if len(res) == 2:
+            row["cgs2_over_householder"] = res["cgs2"]["ms"] / res["householder"]["ms"]
+            row["same_J"] = bool(torch.equal(res["householder"]["J"], res["cgs2"]["J"]))
+        rows.append(row)
+        del Y0, Y
+        torch.cuda.empty_cache()
         print(json.dumps(rows[-1]), file=sys.stderr, flush=True)
     rid.rid_set_qr(h, rid.RID_QR_HOUSEHOLDER)
     rid.rid_destroy(h)
@@ -542,8 +563,11 @@ def main() -> int:
                          "sweep: the paper's Table 1 shapes (l = 2k, A = B P) with per-phase "
                          "times; qr: Householder against CGS2 pivoted QR; svd: the SVD built "
                          "on the ID")
+    ap.add_argument("--qr-kinds", choices=["both", "householder", "cgs2"], default="both",
+                    help="qr: the QR methods to time")
     ap.add_argument("--shapes", default="all",
-                    help="sweep: comma-separated indices into the Table 1 shapes, or all")
+                    help="sweep (qr): comma-separated indices into the Table 1 shapes "
+                         "(QR_SHAPES), or all")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: requests per second")
     ap.add_argument("--duration", type=float, default=4.0,
                     help="serving: seconds of arrivals")

@@ -109,6 +109,14 @@ RID_DEV double2 buf_ld(__amdgpu_buffer_rsrc_t r, int off) {
 RID_DEV void buf_st(__amdgpu_buffer_rsrc_t r, int off, double2 v) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
 }
+// The same with the non-temporal hint (cache policy bit 1): for a Y far
+// beyond the caches, which every step streams once.
+RID_DEV double2 buf_ld_nt(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2));
+}
+RID_DEV void buf_st_nt(__amdgpu_buffer_rsrc_t r, int off, double2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 2);
+}
 
 // A value that is the same in every lane but that the compiler cannot see
 // as such (read from LDS), made explicitly uniform.
@@ -121,32 +129,68 @@ RID_DEV double uniform_f64(double v) {
   return __builtin_bit_cast(double, uniform_i64(__builtin_bit_cast(int64_t, v)));
 }
 
+// Independent FMA chains per lane sum: row h of a lane goes to chain h % NC,
+// and the chains are added pairwise at the end.  With one wave per SIMD (the
+// large-l steps) nothing else hides a chain's latency, so four overlapping
+// chains of RR/4 terms replace one of RR.
+template <int RR>
+constexpr int lane_chains() {
+  return RR < 4 ? RR : 4;
+}
+template <int NC>
+RID_DEV double add_chains(const double (&c)[NC]) {
+  if constexpr (NC == 4) return (c[0] + c[1]) + (c[2] + c[3]);
+  if constexpr (NC == 3) return (c[0] + c[1]) + c[2];
+  if constexpr (NC == 2) return c[0] + c[1];
+  return c[0];
+}
+
+// Sum of |y_h|^2 over the lane's RR rows, row 0 only when `first`.
+template <int RR>
+RID_DEV double rows_norm2(const double2 (&y)[RR], bool first) {
+  constexpr int NC = lane_chains<RR>();
+  double c[NC];
+#pragma unroll
+  for (int i = 0; i < NC; ++i) c[i] = 0.0;
+#pragma unroll
+  for (int h = 0; h < RR; ++h) {
+    const double2 q = (h > 0 || first) ? y[h] : make_double2(0.0, 0.0);
+    c[h % NC] = fma(q.x, q.x, c[h % NC]);
+    c[h % NC] = fma(q.y, q.y, c[h % NC]);
+  }
+  return add_chains<NC>(c);
+}
+
 // y_b -= conj(tau) (v^H y_b) v for CB columns over the lane's RR rows, with
 // one LDS read of v per row for all of them; bit b of zmask gives column b a
-// zero coefficient (it is left as it is).  Sums and updates are plain FMA
-// chains, the same for every column.
+// zero coefficient (it is left as it is).  Sums (in lane_chains chains) and
+// updates are plain FMA chains, the same for every column.
 template <int RR, int CB>
 RID_DEV void apply_reflector(double2 (&y)[CB][RR], const double2 *vl, double2 tau, int lane,
                          unsigned zmask) {
-  double dr[CB], di[CB];
+  constexpr int NC = lane_chains<RR>();
+  double pr[CB][NC], pi[CB][NC];
 #pragma unroll
-  for (int b = 0; b < CB; ++b) dr[b] = di[b] = 0.0;
+  for (int b = 0; b < CB; ++b)
+#pragma unroll
+    for (int i = 0; i < NC; ++i) pr[b][i] = pi[b][i] = 0.0;
 #pragma unroll
   for (int h = 0; h < RR; ++h) {
     const double2 v = vl[lane + 64 * h];
 #pragma unroll
     for (int b = 0; b < CB; ++b) {
-      dr[b] = fma(v.x, y[b][h].x, dr[b]);
-      dr[b] = fma(v.y, y[b][h].y, dr[b]);
-      di[b] = fma(v.x, y[b][h].y, di[b]);
-      di[b] = fma(-v.y, y[b][h].x, di[b]);
+      double &r = pr[b][h % NC], &i = pi[b][h % NC];
+      r = fma(v.x, y[b][h].x, r);
+      r = fma(v.y, y[b][h].y, r);
+      i = fma(v.x, y[b][h].y, i);
+      i = fma(-v.y, y[b][h].x, i);
     }
   }
-  double cr[CB], ci[CB];
+  double dr[CB], di[CB], cr[CB], ci[CB];
 #pragma unroll
   for (int b = 0; b < CB; ++b) {
-    dr[b] = wave_sum(dr[b]);
-    di[b] = wave_sum(di[b]);
+    dr[b] = wave_sum(add_chains<NC>(pr[b]));
+    di[b] = wave_sum(add_chains<NC>(pi[b]));
     const bool z = (zmask >> b) & 1u;
     cr[b] = z ? 0.0 : tau.x * dr[b] + tau.y * di[b];
     ci[b] = z ? 0.0 : tau.x * di[b] - tau.y * dr[b];
@@ -331,15 +375,7 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
       const bool below = lane >= t - r0;
       double ss[CB];
 #pragma unroll
-      for (int b = 0; b < CB; ++b) {
-        ss[b] = 0.0;
-#pragma unroll
-        for (int h = 0; h < RR; ++h) {
-          const double2 q = (h > 0 || below) ? y[b][h] : make_double2(0.0, 0.0);
-          ss[b] = fma(q.x, q.x, ss[b]);
-          ss[b] = fma(q.y, q.y, ss[b]);
-        }
-      }
+      for (int b = 0; b < CB; ++b) ss[b] = rows_norm2<RR>(y[b], below);
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
         const double nrm = sqrt(wave_sum(ss[b]));
@@ -390,12 +426,19 @@ struct PanelWs {
   double2 *tau;  // [QP_NB]
 };
 
+// A workgroup takes the column blocks slot, slot + G, ... (G = gridDim.x,
+// sized to the workgroups the device holds at once), so the per-step work
+// of a workgroup -- merging the previous step's candidates, building the
+// reflector, staging the pending reflectors -- is done once for all of its
+// blocks, and it publishes one candidate (its best column) in slot `slot`.
+// nbk: column blocks; gprev: candidate slots the previous step wrote.
 template <int RR, int CB>
 __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, int64_t l,
                                                           int64_t n, int64_t k, double2 *Y,
                                                           int64_t ldy, int64_t *perm,
                                                           double *gaps, double rank_tol,
-                                                          PivWs w, PanelWs pw, int *status) {
+                                                          PivWs w, PanelWs pw, int *status,
+                                                          int64_t nbk, int64_t gprev) {
   __shared__ double2 vl[QP_NB][64 * RR];
   __shared__ double2 taus[QP_NB];
   __shared__ Cand red[256];
@@ -409,11 +452,10 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
   // uniform in the wave; read as such, so that buffer resources built from
   // it stay in scalar registers
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t bx = blockIdx.x;
-  const int64_t nb = gridDim.x;
-  const int64_t cbeg = bx * PQ_COLS;
-  const int64_t rd = ((t - 1) & 1) * nb;  // candidates of step t-1
-  const int64_t wrb = (t & 1) * nb;       // candidates of step t
+  const int64_t slot = blockIdx.x;
+  const int64_t G = gridDim.x;
+  const int64_t rd = ((t - 1) & 1) * nbk;  // candidates of step t-1
+  const int64_t wrb = (t & 1) * nbk;       // candidates of step t
   int64_t jstar = -1;
   double beta = 0.0;
   // the pending reflectors a .. t-2, rows relative to a
@@ -428,7 +470,7 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
   if (t > 0) {
     // ---- pivot of step t-1 (as in the plain kernel)
     Cand cd = cand_empty();
-    for (int64_t b = tid; b < nb; b += 256) {
+    for (int64_t b = tid; b < gprev; b += 256) {
       Cand x{w.cnorm[rd + b], w.cidx[rd + b], w.cnorm2[rd + b], 0};
       if (x.v1 < 0.0) x = cand_empty();
       cd = cand_merge(cd, x);
@@ -447,7 +489,7 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
     const double nu1 = best.v1;
     const double nu0 = (t == 1) ? nu1 : *w.nu0;
     const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
-    if (bx == 0 && tid == 0) {
+    if (slot == 0 && tid == 0) {
       perm[t - 1] = best.i1;
       if (gaps) gaps[t - 1] = (best.v2 < 0.0) ? 1.0 : (nu1 - best.v2) / nu1;
       if (t == 1) *w.nu0 = nu1;
@@ -460,7 +502,8 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
     const int sl = (t - 1) % QP_NB;
     if (wave == 0) {
       const int64_t r0 = t - 1;
-      const double2 *x = w.ccol + (rd + jstar / PQ_COLS) * l;
+      // the copy sits in the slot of the workgroup that took j*'s block
+      const double2 *x = w.ccol + (rd + (jstar / PQ_COLS) % gprev) * l;
       double2 xv[RR];
       double ss = 0.0;
 #pragma unroll
@@ -496,15 +539,15 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
                                        : make_double2(xv[h].x * scale.x - xv[h].y * scale.y,
                                                       xv[h].x * scale.y + xv[h].y * scale.x);
           vl[sl][row - a] = v;
-          if (bx == 0) pw.V[sl * l + row] = v;
+          if (slot == 0) pw.V[sl * l + row] = v;
         }
       }
-      if (bx == 0)
+      if (slot == 0)
         for (int64_t row = lane; row < r0; row += 64) pw.V[sl * l + row] = make_double2(0.0, 0.0);
       if (lane == 0) {
         taus[sl] = tau;
         beta_s = beta;
-        if (bx == 0) pw.tau[sl] = tau;
+        if (slot == 0) pw.tau[sl] = tau;
       }
     }
     __syncthreads();
@@ -520,85 +563,80 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
   // coefficient for reflector t-1).  A column slice is rows a .. l-1 through
   // a range-checked buffer resource: rows past l load as zeros (and stay
   // zero, as do the reflectors there) and are never stored.
-  const int64_t jw = cbeg + wave * 16;
-  // picked-step marks of the wave's 16 columns, read at once: bit c is set
-  // for an unpicked column (the pivot of step t-1 included)
-  const bool inr = lane < 16 && jw + lane < n;
-  const uint64_t open = __ballot(inr && w.pstep[inr ? jw + lane : 0] < 0);
   const int nbytes = static_cast<int>((l - a) * 16);
   const int lo = lane * 16;
   Cand wc = cand_empty();
-  for (int c0 = 0; c0 < 16; c0 += CB) {
-    double2 y[CB][RR];
-    __amdgpu_buffer_rsrc_t rs[CB];
-    bool live[CB];
-    unsigned zmask = 0;
-#pragma unroll
-    for (int b = 0; b < CB; ++b) {
-      const int64_t j = jw + c0 + b;
-      live[b] = (open >> (c0 + b)) & 1;
-      if (j == jstar) zmask |= 1u << b;
-      rs[b] = buf_rsrc(live[b] ? Y + j * ldy + a : Y, live[b] ? nbytes : 0);
-#pragma unroll
-      for (int h = 0; h < RR; ++h) y[b][h] = buf_ld(rs[b], lo + 1024 * h);
-    }
-    for (int s = a; s < t; ++s)
-      apply_reflector<RR, CB>(y, vl[s % QP_NB], taus[s % QP_NB], lane, (s == t - 1) ? zmask : 0u);
-#pragma unroll
-    for (int b = 0; b < CB; ++b) {
-      if (!live[b]) continue;
-      if ((zmask >> b) & 1u) {
-        // rows a .. t-2: its entries of R; beta at row t-1; zeros below
-#pragma unroll
-        for (int h = 0; h < RR; ++h) {
-          const int64_t row = a + lane + 64 * h;
-          const double2 v = (row < t - 1) ? y[b][h]
-                                          : ((row == t - 1) ? make_double2(beta, 0.0)
-                                                            : make_double2(0.0, 0.0));
-          buf_st(rs[b], lo + 1024 * h, v);
-        }
-        if (lane == 0) w.pstep[jw + c0 + b] = t - 1;
-      } else if (wr) {
-#pragma unroll
-        for (int h = 0; h < RR; ++h) buf_st(rs[b], lo + 1024 * h, y[b][h]);
-      }
-    }
-    if (t < k) {
-      // rows t .. l-1: all but rows a .. t-1, which sit in slot 0
-      const bool below = lane >= t - a;
-      double ss[CB];
+  for (int64_t bx = slot; bx < nbk; bx += G) {
+    const int64_t jw = bx * PQ_COLS + wave * 16;
+    // picked-step marks of the wave's 16 columns, read at once: bit c is set
+    // for an unpicked column (the pivot of step t-1 included)
+    const bool inr = lane < 16 && jw + lane < n;
+    const uint64_t open = __ballot(inr && w.pstep[inr ? jw + lane : 0] < 0);
+    for (int c0 = 0; c0 < 16; c0 += CB) {
+      double2 y[CB][RR];
+      __amdgpu_buffer_rsrc_t rs[CB];
+      bool live[CB];
+      unsigned zmask = 0;
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
-        ss[b] = 0.0;
+        const int64_t j = jw + c0 + b;
+        live[b] = (open >> (c0 + b)) & 1;
+        if (j == jstar) zmask |= 1u << b;
+        rs[b] = buf_rsrc(live[b] ? Y + j * ldy + a : Y, live[b] ? nbytes : 0);
 #pragma unroll
-        for (int h = 0; h < RR; ++h) {
-          const double2 q = (h > 0 || below) ? y[b][h] : make_double2(0.0, 0.0);
-          ss[b] = fma(q.x, q.x, ss[b]);
-          ss[b] = fma(q.y, q.y, ss[b]);
-        }
+        for (int h = 0; h < RR; ++h) y[b][h] = buf_ld_nt(rs[b], lo + 1024 * h);
       }
+      for (int s = a; s < t; ++s)
+        apply_reflector<RR, CB>(y, vl[s % QP_NB], taus[s % QP_NB], lane,
+                                (s == t - 1) ? zmask : 0u);
 #pragma unroll
       for (int b = 0; b < CB; ++b) {
-        const double nrm = sqrt(wave_sum(ss[b]));
-        if (live[b] && !((zmask >> b) & 1u))
-          wc = cand_merge(wc, Cand{nrm, jw + c0 + b, -1.0, wave});
+        if (!live[b]) continue;
+        if ((zmask >> b) & 1u) {
+          // rows a .. t-2: its entries of R; beta at row t-1; zeros below
+#pragma unroll
+          for (int h = 0; h < RR; ++h) {
+            const int64_t row = a + lane + 64 * h;
+            const double2 v = (row < t - 1) ? y[b][h]
+                                            : ((row == t - 1) ? make_double2(beta, 0.0)
+                                                              : make_double2(0.0, 0.0));
+            buf_st_nt(rs[b], lo + 1024 * h, v);
+          }
+          if (lane == 0) w.pstep[jw + c0 + b] = t - 1;
+        } else if (wr) {
+#pragma unroll
+          for (int h = 0; h < RR; ++h) buf_st_nt(rs[b], lo + 1024 * h, y[b][h]);
+        }
+      }
+      if (t < k) {
+        // rows t .. l-1: all but rows a .. t-1, which sit in slot 0
+        const bool below = lane >= t - a;
+        double ss[CB];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) ss[b] = rows_norm2<RR>(y[b], below);
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+          const double nrm = sqrt(wave_sum(ss[b]));
+          if (live[b] && !((zmask >> b) & 1u))
+            wc = cand_merge(wc, Cand{nrm, jw + c0 + b, -1.0, wave});
+        }
       }
     }
   }
   if (t >= k) return;
 
-  // ---- block-level candidate, merged in wave order
+  // ---- workgroup-level candidate, merged in wave order
   if (lane == 0) red[wave] = wc;
   __syncthreads();
   Cand bc = cand_empty();
   for (int wv = 0; wv < 4; ++wv) bc = cand_merge(bc, red[wv]);
   if (tid == 0) {
-    w.cnorm[wrb + bx] = bc.v1;
-    w.cnorm2[wrb + bx] = bc.v2;
-    w.cidx[wrb + bx] = bc.i1;
+    w.cnorm[wrb + slot] = bc.v1;
+    w.cnorm2[wrb + slot] = bc.v2;
+    w.cidx[wrb + slot] = bc.i1;
   }
   if (bc.src < 0) return;
-  double2 *dst = w.ccol + (wrb + bx) * l;
+  double2 *dst = w.ccol + (wrb + slot) * l;
   if (wr || t == a) {
     // Y holds the column as of this step (written above, or nothing pending)
     const double2 *src = Y + bc.i1 * ldy;
@@ -741,15 +779,7 @@ RID_DEV void pivqr_job_body(const PivJob &jb, double2 *v_s, Cand *red, double2 &
         const bool below = lane >= t - r0;
         double ss[CB];
 #pragma unroll
-        for (int b = 0; b < CB; ++b) {
-          ss[b] = 0.0;
-#pragma unroll
-          for (int h = 0; h < RR; ++h) {
-            const double2 q = (h > 0 || below) ? y[b][h] : make_double2(0.0, 0.0);
-            ss[b] = fma(q.x, q.x, ss[b]);
-            ss[b] = fma(q.y, q.y, ss[b]);
-          }
-        }
+        for (int b = 0; b < CB; ++b) ss[b] = rows_norm2<RR>(y[b], below);
 #pragma unroll
         for (int b = 0; b < CB; ++b) {
           const double nrm = sqrt(wave_sum(ss[b]));
@@ -1235,6 +1265,16 @@ int pick_rr(int64_t l) {
   return 0;
 }
 
+// The panel form's steps run at one wave per SIMD from 16 rows per lane up,
+// so it also takes 20 and 28 rows per lane: fewer registers and
+// instructions on rows past l.
+int pick_rr_panel(int64_t l) {
+  static const int opts[] = {1, 2, 3, 4, 6, 8, 12, 16, 20, 24, 28, 32};
+  for (int o : opts)
+    if (64 * o >= l) return o;
+  return 0;
+}
+
 template <class F>
 void with_rr(int rr, F &&f) {
   switch (rr) {
@@ -1246,7 +1286,9 @@ void with_rr(int rr, F &&f) {
     case 8: f(std::integral_constant<int, 8>()); break;
     case 12: f(std::integral_constant<int, 12>()); break;
     case 16: f(std::integral_constant<int, 16>()); break;
+    case 20: f(std::integral_constant<int, 20>()); break;
     case 24: f(std::integral_constant<int, 24>()); break;
+    case 28: f(std::integral_constant<int, 28>()); break;
     case 32: f(std::integral_constant<int, 32>()); break;
     default: break;
   }
@@ -1279,7 +1321,8 @@ void launch_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y, i
 }
 
 // The panel form for a Y that does not fit the last-level cache; the
-// environment variable RID_QR_PANEL=1 (=0) forces (forbids) it.
+// environment variable RID_QR_PANEL=1 (=0) forces (forbids) it, and
+// RID_QR_PANEL_GROUPS caps its workgroups per step.
 bool pivqr_panel_wanted(int64_t l, int64_t n) {
   const char *e = std::getenv("RID_QR_PANEL");
   if (e && e[0] == '1') return true;
@@ -1288,19 +1331,52 @@ bool pivqr_panel_wanted(int64_t l, int64_t n) {
 }
 
 // rows a .. l-1 are in play at step t; RR is picked per launch as above
+// Workgroups of the panel kernel at RR that the device holds at once (its
+// occupancy times the compute units), found once per RR and device.
+template <int RR>
+int64_t panel_resident() {
+  static int64_t cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 0;
+  if (cached[dev] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per_cu, reinterpret_cast<const void *>(&pivqr_panel_kernel<RR, 1>), 256, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      return 0;
+    }
+    cached[dev] = int64_t(per_cu > 0 ? per_cu : 1) * int64_t(cus > 0 ? cus : 1);
+  }
+  return cached[dev];
+}
+
 void launch_panel_steps(hipStream_t st, int64_t l, int64_t n, int64_t k, double2 *Y,
                         int64_t ldy, int64_t *perm, double *gaps, double rank_tol,
                         const PivWs &w, const PanelWs &pw, int *status) {
-  const unsigned nb = static_cast<unsigned>((n + PQ_COLS - 1) / PQ_COLS);
-  int a = 0;  // first reflector not yet written into Y
+  const int64_t nbk = (n + PQ_COLS - 1) / PQ_COLS;
+  // RID_QR_PANEL_GROUPS=g caps the workgroups per step (each then takes more
+  // column blocks); the results do not depend on it
+  const char *ge = std::getenv("RID_QR_PANEL_GROUPS");
+  const int64_t groups_cap = ge ? std::atoll(ge) : 0;
+  int a = 0;          // first reflector not yet written into Y
+  int64_t gprev = 0;  // candidate slots of the previous step
   for (int t = 0; t <= k; ++t) {
     const int wr = (t > 0 && (t - a >= QP_NB || t == k)) ? 1 : 0;
-    with_rr(pick_rr(l - a), [&](auto R) {
+    with_rr(pick_rr_panel(l - a), [&](auto R) {
       constexpr int RR = decltype(R)::value;
+      // as many workgroups as fit at once (each loops over column blocks),
+      // never more than there are blocks
+      const int64_t res = panel_resident<RR>();
+      int64_t g = (res > 0 && res < nbk) ? res : nbk;
+      if (groups_cap > 0 && groups_cap < g) g = groups_cap;
       // one column at a time: two (CB = 2) gained under 2% at RR = 24 and
       // lost at RR <= 16, where their registers cost occupancy
-      hipLaunchKernelGGL((pivqr_panel_kernel<RR, 1>), dim3(nb), dim3(256), 0, st, t, a, wr, l,
-                         n, k, Y, ldy, perm, gaps, rank_tol, w, pw, status);
+      hipLaunchKernelGGL((pivqr_panel_kernel<RR, 1>), dim3(static_cast<unsigned>(g)), dim3(256),
+                         0, st, t, a, wr, l, n, k, Y, ldy, perm, gaps, rank_tol, w, pw, status,
+                         nbk, gprev);
+      gprev = g;
     });
     if (wr) a = t;
   }

@@ -137,18 +137,24 @@ def test_sketch_leading_dimensions(h):
 PIVQR_CASES = [(30, 500, 20), (108, 2000, 100), (12, 12, 12), (40, 9, 9), (8, 300, 1),
                (200, 700, 150), (65, 100, 64),
                # large l (16 and 32 rows per lane) and k > 256 (R1^-1 then one GEMM)
-               (600, 700, 300), (2000, 400, 100), (1024, 1100, 1000)]
+               (600, 700, 300), (2000, 400, 100), (1024, 1100, 1000),
+               # the panel form through 28, 24 and 20 rows per lane
+               (1700, 700, 600)]
 
 
 # both forms of the Householder steps: "plain" rewrites the trailing rows every
 # step; "panel" keeps up to 4 reflectors pending and writes every 4th step
-# (chosen by size for a Y beyond the last-level cache, forced here)
-QR_FORMS = ["plain", "panel"]
+# (chosen by size for a Y beyond the last-level cache, forced here).  The
+# panel form's workgroups each take every G-th column block; "panel3" caps
+# them at 3, so that each takes several blocks (as at the sweep's sizes).
+QR_FORMS = ["plain", "panel", "panel3"]
 
 
 @pytest.fixture
 def qr_form(request, monkeypatch):
-    monkeypatch.setenv("RID_QR_PANEL", "1" if request.param == "panel" else "0")
+    monkeypatch.setenv("RID_QR_PANEL", "0" if request.param == "plain" else "1")
+    if request.param == "panel3":
+        monkeypatch.setenv("RID_QR_PANEL_GROUPS", "3")
     return request.param
 
 
@@ -195,14 +201,16 @@ def near_tie_sketch(l, n, pairs, seed):
 NEAR_TIE_PAIRS = [(3, 40), (11, 10), (90, 25), (7, 150), (60, 61)]
 
 
-@pytest.mark.parametrize("kind", ["householder", "panel", "cgs2"])
+@pytest.mark.parametrize("kind", ["householder", "panel", "panel3", "cgs2"])
 def test_pivqr_near_ties_are_valid_picks(h, monkeypatch, kind):
     # every pair meets a near-tie; the oracle is forced onto the GPU's picks,
     # the picks are checked for validity there and for equality elsewhere,
     # and P is compared entry by entry on the GPU's pivots
     l, n, k = 30, 200, 20
     Y = near_tie_sketch(l, n, NEAR_TIE_PAIRS, seed=12)
-    monkeypatch.setenv("RID_QR_PANEL", "1" if kind == "panel" else "0")
+    monkeypatch.setenv("RID_QR_PANEL", "1" if kind.startswith("panel") else "0")
+    if kind == "panel3":
+        monkeypatch.setenv("RID_QR_PANEL_GROUPS", "3")
     rid.rid_set_qr(h, rid.RID_QR_CGS2 if kind == "cgs2" else rid.RID_QR_HOUSEHOLDER)
     try:
         Yd = dev(Y)
