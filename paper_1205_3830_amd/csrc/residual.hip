@@ -458,9 +458,13 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
 // workgroup's thread groups take separate column splits.  With lda odd this
 // needs m % ax_h != 0 (so that the last block's thread reaches row m - 1);
 // the caller takes the general loop otherwise.
+//
+// Compensated sums (RES_DOT2) use all four words for the rows' sums and
+// their errors, so they take this body for an even lda only (every column
+// unshifted); the low words of x~ join the error sums as in the general
+// loop.
 template <int ACC>
 RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
-  static_assert(ACC != RES_DOT2, "plain sums only");
   using Acc = typename std::conditional<ACC == RES_FP32, float, double>::type;
   // no early test of the stop flag: a stopped job's partials are computed
   // but never read (the z reduction tests it), and the A loads start sooner
@@ -492,7 +496,7 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
   const double2 zero2 = make_double2(0.0, 0.0);
   // a x for one entry into (sr, si); x~ is rounded to its high word
   auto fma_c = [&](Acc &sr, Acc &si, const double2 &a, const double2 &xh) {
-    if constexpr (ACC == RES_FP64) {
+    if constexpr (ACC != RES_FP32) {
       sr = fma(a.x, xh.x, sr);
       sr = fma(-a.y, xh.y, sr);
       si = fma(a.x, xh.y, si);
@@ -506,6 +510,73 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
       si = fmaf(ai, xr, si);
     }
   };
+  if constexpr (ACC == RES_DOT2) {
+    // lda even: one pair (i0, i0 + 1) per column; Dot2 sums of a x~_hi,
+    // plain sums of a x~_lo into the errors where x~_lo is non-zero
+    double c0r = 0, c0i = 0, c1r = 0, c1i = 0;
+    const double2 *__restrict__ xtl = r.xtl;
+    auto hi = [&](const double2 &a0, const double2 &a1, const double2 &xh) {
+      const double2 p0 = ok0 ? a0 : zero2, p1 = ok1 ? a1 : zero2;
+      dot2_acc(s0r, c0r, p0.x, xh.x);
+      dot2_acc(s0r, c0r, -p0.y, xh.y);
+      dot2_acc(s0i, c0i, p0.x, xh.y);
+      dot2_acc(s0i, c0i, p0.y, xh.x);
+      dot2_acc(s1r, c1r, p1.x, xh.x);
+      dot2_acc(s1r, c1r, -p1.y, xh.y);
+      dot2_acc(s1i, c1i, p1.x, xh.y);
+      dot2_acc(s1i, c1i, p1.y, xh.x);
+    };
+    auto lo = [&](const double2 &a0, const double2 &a1, const double2 &xl) {
+      const double2 p0 = ok0 ? a0 : zero2, p1 = ok1 ? a1 : zero2;
+      c0r = fma(p0.x, xl.x, c0r);
+      c0r = fma(-p0.y, xl.y, c0r);
+      c0i = fma(p0.x, xl.y, c0i);
+      c0i = fma(p0.y, xl.x, c0i);
+      c1r = fma(p1.x, xl.x, c1r);
+      c1r = fma(-p1.y, xl.y, c1r);
+      c1i = fma(p1.x, xl.y, c1i);
+      c1i = fma(p1.y, xl.x, c1i);
+    };
+    int64_t j = jb;
+    for (; j + 8 <= je; j += 8) {
+      double2 a0[8], a1[8], xl[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) ld_stream_pair(A + (j + u) * lda + pu, a0[u], a1[u]);
+      bool any = false;
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        xl[u] = xtl[j + u];
+        any = any || xl[u].x != 0.0 || xl[u].y != 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) hi(a0[u], a1[u], xth[j + u]);
+      if (any) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) lo(a0[u], a1[u], xl[u]);
+      }
+    }
+    for (; j < je; ++j) {
+      double2 a0, a1;
+      ld_stream_pair(A + j * lda + pu, a0, a1);
+      hi(a0, a1, xth[j]);
+      lo(a0, a1, xtl[j]);
+    }
+    if (split >= r.pl.S_z) return;
+    double *zp = r.zpart + split * m * 4;
+    if (ok0) {
+      zp[i0 * 4 + 0] = s0r;
+      zp[i0 * 4 + 1] = c0r;
+      zp[i0 * 4 + 2] = s0i;
+      zp[i0 * 4 + 3] = c0i;
+    }
+    if (ok1) {
+      zp[(i0 + 1) * 4 + 0] = s1r;
+      zp[(i0 + 1) * 4 + 1] = c1r;
+      zp[(i0 + 1) * 4 + 2] = s1i;
+      zp[(i0 + 1) * 4 + 3] = c1i;
+    }
+    return;
+  }
   auto unshifted = [&](const double2 &a0, const double2 &a1, const double2 &xh) {
     fma_c(s0r, s0i, ok0 ? a0 : zero2, xh);
     fma_c(s1r, s1i, ok1 ? a1 : zero2, xh);
@@ -697,8 +768,8 @@ RID_DEV void ahz_body(const ResJob &r, int64_t bx, int64_t by) {
   } else {
     int i0 = 2 * lane;
     bool done = false;
-    if constexpr (ACC != RES_DOT2) {
-      // plain sums, 16-byte aligned A: every entry arrives in a 16-byte load
+    {
+      // 16-byte aligned A: every entry arrives in a 16-byte load
       // of two adjacent rows, whatever the parity of lda.  Column u's chunk
       // is shifted (sh = 1) when it starts 8 bytes past a 16-byte boundary;
       // its aligned pairs are then rows (1, 2), (3, 4), ... and lane 0 reads
@@ -884,8 +955,12 @@ RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
   if constexpr (STEP == ST_PXP) px_partial_body(r, bx);
   if constexpr (STEP == ST_PXF) px_final_body(r, bx);
   if constexpr (STEP == ST_AX) {
-    if constexpr (sizeof(TA) == 8 && ACC != RES_DOT2) {
-      if (r.al16 && r.m >= 2 && ((r.lda & 1) == 0 || r.m % r.pl.ax_h != 0)) {
+    // complex64: the paired body with plain sums at any lda, and with
+    // compensated sums at an even lda in a batch (one ID keeps the
+    // whole-slab fast path below)
+    if constexpr (sizeof(TA) == 8 && (ACC != RES_DOT2 || !WIDE)) {
+      const bool even = (r.lda & 1) == 0;
+      if (r.al16 && r.m >= 2 && (even || (ACC != RES_DOT2 && r.m % r.pl.ax_h != 0))) {
         ax_c64_paired<ACC>(r, bx, by);
         return;
       }
@@ -1138,7 +1213,7 @@ void residual_batch_setup(const RidBatchJob *bj, int count, rid_dtype dtype, int
     const int64_t abytes = r.m * r.n * (dtype == RID_C64 ? 8 : 16);
     r.pl = plan_res(r.m, r.n, r.k,
                     std::min<int64_t>(2048, std::max<int64_t>(1, abytes / block_bytes)), ahz_cpw);
-    if (dtype == RID_C64 && acc != RES_DOT2 && r.al16 && r.m >= 2)
+    if (dtype == RID_C64 && r.al16 && r.m >= 2 && (acc != RES_DOT2 || (r.lda & 1) == 0))
       set_ax_rows(r.pl, r.m, pick_ax_rows(r.m, r.lda));
     carve_res(c, r);
   }

@@ -224,6 +224,8 @@ def test_batch_of_the_512_job_workload_sampled_against_oracle(h, prec):
         Jb, Pb, sb = host(Js[i]), host(Ps[i]), float(host(sig[i])[0])
         if p == rid.RID_FP64:
             check_decompose(A, r["Y"], Jb, Pb, sb, used[i], q, ref=r)
+            # compensated sums over A (odd and even m: both complex64 loops)
+            check_sigma_call_for_call(A, Jb, Pb, sb, used[i], q, acc="dot2")
         else:
             c = check_decompose(A, r["Y"], Jb, Pb, sb, used[i], q, tau=1e-4, ptol=1e-3, ref=r)
             # FP32 products: the residual's sums over A are plain double
