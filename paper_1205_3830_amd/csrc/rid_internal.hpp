@@ -230,9 +230,51 @@ RID_DEV void dd_norm(double s, double c, double &hi, double &lo) {
   lo = c - (hi - s);
 }
 
+// The value of lane (lane op CTRL) for a DPP lane pattern CTRL, as two
+// 32-bit DPP moves: a VALU operation, where a shuffle goes through the LDS
+// unit and waits for it.
+template <int CTRL>
+RID_DEV double dpp_f64(double v) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_update_dpp(0u, static_cast<unsigned>(u), CTRL, 0xF, 0xF,
+                                                  false);
+  const unsigned hi = __builtin_amdgcn_update_dpp(0u, static_cast<unsigned>(u >> 32), CTRL, 0xF,
+                                                  0xF, false);
+  return __longlong_as_double((static_cast<unsigned long long>(hi) << 32) | lo);
+}
+
+// v plus the value of lane ^ 32 (W = 32) or lane ^ 16 (W = 16), with the
+// gfx950 lane-swap instructions.  Swapping a register with its own copy
+// leaves, in each lane, its own value in one of the two and the partner's
+// in the other; their sum is the same bits either way round.
+template <int W>
+RID_DEV double swap_add(double v) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = static_cast<unsigned>(u), hi = static_cast<unsigned>(u >> 32);
+  const auto a = (W == 32) ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
+                           : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto b = (W == 32) ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
+                           : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double x = __longlong_as_double((static_cast<unsigned long long>(b[0]) << 32) | a[0]);
+  const double y = __longlong_as_double((static_cast<unsigned long long>(b[1]) << 32) | a[1]);
+  return x + y;
+}
+
+// Sum over the 64 lanes of a wave (all active), every lane getting the same
+// bits: the butterfly over lane bits 5, 4, ..., 0, each level adding the
+// partner lane's value.  Bits 5 and 4 go through the lane-swap instructions
+// and bit 3 through a rotation of each 16-lane row by 8 (the same exchange).
+// From there on a lane's value depends only on its lane index mod 8, mod 4,
+// mod 2, so a row rotation by 4 and the quad patterns [2,3,0,1], [1,0,3,2]
+// read a lane that holds the partner's value.  Nothing goes through the LDS
+// unit, which the wave's other work keeps busy.
 RID_DEV double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  v = swap_add<32>(v);
+  v = swap_add<16>(v);
+  v += dpp_f64<0x128>(v);  // row_ror:8
+  v += dpp_f64<0x124>(v);  // row_ror:4
+  v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
   return v;
 }
 
