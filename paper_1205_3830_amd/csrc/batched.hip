@@ -168,7 +168,7 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
     for (int64_t s = 0; s < S; ++s)
       for (int64_t x = 0; x < nbx; ++x)
         t_sk[bucket].push_back(make_int4(i, static_cast<int>(x), static_cast<int>(s), 0));
-    const int64_t nq = (bj[i].n + 3) / 4;
+    const int64_t nq = interp_blocks(bj[i].n);
     for (int64_t x = 0; x < nq; ++x) t_in.push_back(make_int4(i, static_cast<int>(x), 0, 0));
     const int64_t nbq = pivqr_blocks(bj[i].n);
     for (int64_t x = 0; x < nbq; ++x)

@@ -95,22 +95,9 @@ __global__ void pivqr_init_kernel(int64_t n, int *pstep, int *status) {
 
 // Step t of the QR for workgroup bx of nb (the column owner of [64 bx, 64 bx + 64)).
 // A wave handles CB of its 16 columns at a time.
-// A raw buffer resource over the given bytes: loads past the end read zeros
-// and stores past it are dropped by the hardware's range check, so a column
-// slice needs no per-row predicates (and an empty one no branch).  Word 3 is
-// the 32-bit data format that every gfx9 target takes.
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-RID_DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, int bytes) {
-  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
-}
-RID_DEV double2 buf_ld(__amdgpu_buffer_rsrc_t r, int off) {
-  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
-}
-RID_DEV void buf_st(__amdgpu_buffer_rsrc_t r, int off, double2 v) {
-  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
-}
-// The same with the non-temporal hint (cache policy bit 1): for a Y far
-// beyond the caches, which every step streams once.
+// Buffer loads and stores as buf_ld / buf_st, with the non-temporal hint
+// (cache policy bit 1): for a Y far beyond the caches, which every step
+// streams once.
 RID_DEV double2 buf_ld_nt(__amdgpu_buffer_rsrc_t r, int off) {
   return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 2));
 }
@@ -118,16 +105,6 @@ RID_DEV void buf_st_nt(__amdgpu_buffer_rsrc_t r, int off, double2 v) {
   __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 2);
 }
 
-// A value that is the same in every lane but that the compiler cannot see
-// as such (read from LDS), made explicitly uniform.
-RID_DEV int64_t uniform_i64(int64_t v) {
-  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32));
-  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<int>(v));
-  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
-}
-RID_DEV double uniform_f64(double v) {
-  return __builtin_bit_cast(double, uniform_i64(__builtin_bit_cast(int64_t, v)));
-}
 
 // Independent FMA chains per lane sum: row h of a lane goes to chain h % NC,
 // and the chains are added pairwise at the end.  With one wave per SIMD (the
@@ -224,8 +201,8 @@ RID_DEV void make_reflector(const double2 *x, int64_t r0, int64_t l, int lane, d
     if (lane + 64 * h >= 1) ss += xv[h].x * xv[h].x + xv[h].y * xv[h].y;
   }
   const double xnorm2 = wave_sum(ss);
-  const double ar = __shfl(xv[0].x, 0, 64);
-  const double ai = __shfl(xv[0].y, 0, 64);
+  const double ar = lane_bcast(xv[0].x, 0);
+  const double ai = lane_bcast(xv[0].y, 0);
   double2 tau;
   double beta;
   double2 scale;
@@ -513,8 +490,8 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
         if (lane + 64 * h >= 1) ss += xv[h].x * xv[h].x + xv[h].y * xv[h].y;
       }
       const double xnorm2 = wave_sum(ss);
-      const double ar = __shfl(xv[0].x, 0, 64);
-      const double ai = __shfl(xv[0].y, 0, 64);
+      const double ar = lane_bcast(xv[0].x, 0);
+      const double ai = lane_bcast(xv[0].y, 0);
       double2 tau;
       double2 scale;
       if (xnorm2 == 0.0 && ai == 0.0) {

@@ -173,6 +173,34 @@ RID_DEV void ld_stream_pair(const float2 *p, double2 &a, double2 &b) {
   b = make_double2(static_cast<double>(v.z), static_cast<double>(v.w));
 }
 
+// A raw buffer resource over the given bytes: loads past the end read zeros
+// and stores past it are dropped by the hardware's range check, so a column
+// slice needs no per-row predicates (and an empty one no branch).  Word 3 is
+// the 32-bit data format that every gfx9 target takes.  Buffer loads count
+// only against the vector-memory counter, so waiting for an LDS access does
+// not also wait for them (as it would for a flat load).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+RID_DEV __amdgpu_buffer_rsrc_t buf_rsrc(const void *p, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), 0, bytes, 0x00020000);
+}
+RID_DEV double2 buf_ld(__amdgpu_buffer_rsrc_t r, int off) {
+  return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+RID_DEV void buf_st(__amdgpu_buffer_rsrc_t r, int off, double2 v) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
+}
+
+// A value that is the same in every lane but that the compiler cannot see
+// as such (read from LDS), made explicitly uniform.
+RID_DEV int64_t uniform_i64(int64_t v) {
+  const uint32_t hi = __builtin_amdgcn_readfirstlane(static_cast<int>(v >> 32));
+  const uint32_t lo = __builtin_amdgcn_readfirstlane(static_cast<int>(v));
+  return static_cast<int64_t>((static_cast<uint64_t>(hi) << 32) | lo);
+}
+RID_DEV double uniform_f64(double v) {
+  return __builtin_bit_cast(double, uniform_i64(__builtin_bit_cast(int64_t, v)));
+}
+
 template <class T>
 RID_DEV T zero_of();
 template <>
@@ -258,6 +286,15 @@ RID_DEV double swap_add(double v) {
   const double x = __longlong_as_double((static_cast<unsigned long long>(b[0]) << 32) | a[0]);
   const double y = __longlong_as_double((static_cast<unsigned long long>(b[1]) << 32) | a[1]);
   return x + y;
+}
+
+// v of lane src (src the same in every lane; that lane active), read into
+// scalar registers: no trip through the LDS unit as a shuffle would take.
+RID_DEV double lane_bcast(double v, int src) {
+  const unsigned long long u = __double_as_longlong(v);
+  const unsigned lo = __builtin_amdgcn_readlane(static_cast<int>(u), src);
+  const unsigned hi = __builtin_amdgcn_readlane(static_cast<int>(u >> 32), src);
+  return __longlong_as_double((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
 // Sum over the 64 lanes of a wave (all active), every lane getting the same
@@ -483,7 +520,8 @@ hipError_t run_batch(rid_handle h, hipStream_t stream, rid_dtype dtype, rid_prec
 size_t batch_ws_need(rid_handle h, rid_dtype dtype, rid_prec prec, const RidBatchJob *bj,
                      int count, int q);
 
-// Grouped interpolation (k <= 256): tab entries (job, column quad).
+// Grouped interpolation (k <= 256): tab entries (job, column group of
+// interp_blocks).
 hipError_t launch_interp_batch(hipStream_t st, int kmax, const InterpJob *djobs,
                                const int4 *dtab, int64_t count, RidProf *prof);
 
@@ -541,6 +579,8 @@ hipError_t launch_svd(hipStream_t st, rid_dtype dtype, int64_t m, int64_t n, int
 
 size_t interp_ws_bytes(int64_t n, int64_t k);
 bool interp_supported(int64_t k);
+// Workgroups of the direct solve (k <= 256) for n columns of P.
+int64_t interp_blocks(int64_t n);
 hipError_t launch_interp(hipStream_t st, int64_t n, int64_t k, const double2 *R, int64_t ldr,
                          const int64_t *J, double2 *P, int64_t ldp, void *ws,
                          RidProf *prof);
