@@ -73,14 +73,16 @@ bool use_graph() {
 }
 
 // The QR of a batch: one launch per pivot step over all jobs, two columns
-// in flight per wave (7.2 ms per 512-job batch; one and four at a time took
-// 7.5 and 7.4 ms).  RID_BATCH_QR=jobs selects one launch with a workgroup
-// per job for all its steps instead (14.0 ms: a big job's steps run one
-// after another on one CU).  The arithmetic is the same: J and R agree bit
-// for bit.
+// in flight per wave (5.1-5.3 ms per 512-job batch; RID_BATCH_QR=1 or 4,
+// one or four at a time, took 5.4 and 5.3 ms).  RID_BATCH_QR=jobs selects
+// one launch with a workgroup per job for all its steps instead (12.9 ms:
+// a big job's steps run one after another on one CU).  The arithmetic is
+// the same: J and R agree bit for bit.
 int qr_mode() {
   const char *e = getenv("RID_BATCH_QR");
-  return (e && e[0] == 'j') ? 0 : 2;
+  if (e && e[0] == 'j') return 0;
+  if (e && (e[0] == '1' || e[0] == '4')) return e[0] - '0';  // columns in flight per wave
+  return 2;
 }
 
 }  // namespace

@@ -87,6 +87,38 @@ RID_DEV Cand cand_merge(Cand a, Cand b) {
   return w;
 }
 
+// The candidate of lane (lane op CTRL) for a DPP pattern CTRL (src, the
+// same in every lane of a wave wherever this is used, stays).
+template <int CTRL>
+RID_DEV Cand cand_dpp(const Cand &c) {
+  return Cand{dpp_f64<CTRL>(c.v1), dpp_i64<CTRL>(c.i1), dpp_f64<CTRL>(c.v2), c.src};
+}
+
+template <int W>
+RID_DEV Cand cand_swap_merge(const Cand &c) {
+  Cand a, b;
+  swap_pair<W>(c.v1, a.v1, b.v1);
+  swap_pair<W>(c.i1, a.i1, b.i1);
+  swap_pair<W>(c.v2, a.v2, b.v2);
+  a.src = b.src = c.src;
+  return cand_merge(a, b);
+}
+
+// The merge of the 64 lanes' candidates, in every lane.  cand_merge is
+// symmetric (the winner and the largest other value do not depend on the
+// order), so the butterfly of wave_sum applies: both copies of the lane-swap
+// levels are merged, and the row rotations and quad patterns read a lane
+// that holds the partner's candidate.  No LDS traffic and no barrier.
+RID_DEV Cand cand_wave_merge(Cand c) {
+  c = cand_swap_merge<32>(c);
+  c = cand_swap_merge<16>(c);
+  c = cand_merge(c, cand_dpp<0x128>(c));  // row_ror:8
+  c = cand_merge(c, cand_dpp<0x124>(c));  // row_ror:4
+  c = cand_merge(c, cand_dpp<0x4E>(c));   // quad_perm [2,3,0,1]
+  c = cand_merge(c, cand_dpp<0xB1>(c));   // quad_perm [1,0,3,2]
+  return c;
+}
+
 __global__ void pivqr_init_kernel(int64_t n, int *pstep, int *status) {
   const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (j < n) pstep[j] = -1;
@@ -242,7 +274,7 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
                              int64_t *perm, double *gaps, double rank_tol, const PivWs &w,
                              int *status, int64_t bx, int64_t nb) {
   __shared__ double2 v_s[64 * RR];
-  __shared__ Cand red[256];
+  __shared__ Cand red[4];
   __shared__ double2 tau_s;
   __shared__ double beta_s;
   __shared__ int status_s;
@@ -271,15 +303,15 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
       if (x.v1 < 0.0) x = cand_empty();
       cd = cand_merge(cd, x);
     }
-    red[tid] = cd;
+    // each wave's merge, then the four in wave order; the same in every
+    // lane: read as uniform, so that what depends on it (the exit on
+    // failure, the pivot index) stays uniform for the compiler
+    cd = cand_wave_merge(cd);
+    if (lane == 0) red[wave] = cd;
     __syncthreads();
-    for (int s = 128; s >= 1; s >>= 1) {
-      if (tid < s) red[tid] = cand_merge(red[tid], red[tid + s]);
-      __syncthreads();
-    }
-    // the same in every lane: read as uniform, so that what depends on it
-    // (the exit on failure, the pivot index) stays uniform for the compiler
-    Cand best = red[0];
+    Cand best = cand_empty();
+#pragma unroll
+    for (int wv = 0; wv < 4; ++wv) best = cand_merge(best, red[wv]);
     best.v1 = uniform_f64(best.v1);
     best.i1 = uniform_i64(best.i1);
     const double nu1 = best.v1;

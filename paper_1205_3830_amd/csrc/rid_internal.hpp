@@ -271,20 +271,41 @@ RID_DEV double dpp_f64(double v) {
   return __longlong_as_double((static_cast<unsigned long long>(hi) << 32) | lo);
 }
 
-// v plus the value of lane ^ 32 (W = 32) or lane ^ 16 (W = 16), with the
-// gfx950 lane-swap instructions.  Swapping a register with its own copy
-// leaves, in each lane, its own value in one of the two and the partner's
-// in the other; their sum is the same bits either way round.
+// A 64-bit value of lane (lane op CTRL), moved as bits.
+template <int CTRL>
+RID_DEV int64_t dpp_i64(int64_t v) {
+  return __builtin_bit_cast(int64_t, dpp_f64<CTRL>(__builtin_bit_cast(double, v)));
+}
+
+// The gfx950 lane-swap instructions (W = 32: lane ^ 32, W = 16: lane ^ 16)
+// applied to a register and its own copy: x and y get, in each lane, its
+// own value in one and the partner lane's in the other.  Which is which
+// depends on the lane, and is the same for every register swapped, so a
+// symmetric combination of x and y (a sum, a maximum) is the butterfly step.
 template <int W>
-RID_DEV double swap_add(double v) {
+RID_DEV void swap_pair(double v, double &x, double &y) {
   const unsigned long long u = __double_as_longlong(v);
   const unsigned lo = static_cast<unsigned>(u), hi = static_cast<unsigned>(u >> 32);
   const auto a = (W == 32) ? __builtin_amdgcn_permlane32_swap(lo, lo, false, false)
                            : __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
   const auto b = (W == 32) ? __builtin_amdgcn_permlane32_swap(hi, hi, false, false)
                            : __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
-  const double x = __longlong_as_double((static_cast<unsigned long long>(b[0]) << 32) | a[0]);
-  const double y = __longlong_as_double((static_cast<unsigned long long>(b[1]) << 32) | a[1]);
+  x = __longlong_as_double((static_cast<unsigned long long>(b[0]) << 32) | a[0]);
+  y = __longlong_as_double((static_cast<unsigned long long>(b[1]) << 32) | a[1]);
+}
+template <int W>
+RID_DEV void swap_pair(int64_t v, int64_t &x, int64_t &y) {
+  double dx, dy;
+  swap_pair<W>(__builtin_bit_cast(double, v), dx, dy);
+  x = __builtin_bit_cast(int64_t, dx);
+  y = __builtin_bit_cast(int64_t, dy);
+}
+
+// v plus the value of lane ^ W (W = 32 or 16); the same bits in both lanes.
+template <int W>
+RID_DEV double swap_add(double v) {
+  double x, y;
+  swap_pair<W>(v, x, y);
   return x + y;
 }
 
