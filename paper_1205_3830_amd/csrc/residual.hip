@@ -45,8 +45,8 @@ constexpr int AHZ_RS = 2048;   // rows per ahz split (z chunk in LDS, 32 KB)
 // columns per ahz wave: a plan choice, 8 (fewer z reads per byte of A) or 4
 // (fewer registers: 5 waves per SIMD instead of 3 for complex64)
 
-constexpr int PX_JC = 256;     // columns per workgroup of the P x partials
-constexpr int RES_KMAX = 1024; // LDS holds u_J for k <= RES_KMAX
+constexpr int PX_SETS = 1024;  // most column sets of the P x partials (one per wave)
+constexpr int RES_KMAX = 1024; // largest k of the residual (as of the interpolation)
 
 struct ResPlan {
   int64_t nb_ax;   // ax row blocks (ax_h rows each)
@@ -59,9 +59,12 @@ struct ResPlan {
   int64_t rpu;     // rows per ahz split
   int64_t nb_ahz;  // ahz column blocks
   int ahz_cpw;     // ahz columns per wave (4 or 8)
-  int64_t nb_px;   // P x partial blocks
-  int64_t nb_k;    // 256-blocks over k
+  int64_t nb_px;   // P x partial sets (column sets of px_cpw columns, one per wave)
+  int64_t px_cpw;  // columns per P x partial set
+  int64_t nb_pxb;  // P x partial workgroups (four sets each)
+  int64_t nb_k;    // workgroups of the P x final step (four rows of P each)
   int64_t nb_n;    // 256-blocks over n
+  int64_t nb_w;    // 64-blocks over n (the w step; its norm partials)
   int64_t nb_m;    // 256-blocks over m
 };
 
@@ -86,9 +89,16 @@ ResPlan plan_res(int64_t m, int64_t n, int64_t k, int64_t target_blocks, int ahz
   p.S_u = (m + p.rpu - 1) / p.rpu;
   if (p.S_u < 1) p.S_u = 1;
   p.nb_ahz = (n + 4 * p.ahz_cpw - 1) / (4 * p.ahz_cpw);
-  p.nb_px = (n + PX_JC - 1) / PX_JC;
-  p.nb_k = (k + 255) / 256;
+  p.nb_px = std::min<int64_t>((n + 15) / 16, PX_SETS);
+  if (p.nb_px < 1) p.nb_px = 1;
+  p.px_cpw = (n + p.nb_px - 1) / p.nb_px;
+  if (p.px_cpw < 1) p.px_cpw = 1;
+  p.nb_px = (n + p.px_cpw - 1) / p.px_cpw;
+  if (p.nb_px < 1) p.nb_px = 1;
+  p.nb_pxb = (p.nb_px + 3) / 4;
+  p.nb_k = (k + 3) / 4;
   p.nb_n = (n + 255) / 256;
+  p.nb_w = (n + 63) / 64;
   p.nb_m = (m + 255) / 256;
   return p;
 }
@@ -133,7 +143,7 @@ void carve_res(C &c, ResJob &r) {
   r.zpart = c.template take<double>(size_t(p.S_z) * size_t(m) * 4);
   r.upart = c.template take<double>(size_t(p.S_u) * size_t(n) * 4);
   r.zn_part = c.template take<double>(p.nb_m);
-  r.wn_part = c.template take<double>(p.nb_n);
+  r.wn_part = c.template take<double>(p.nb_w > 0 ? p.nb_w : 1);
   r.scal = c.template take<double>(4);
 }
 
@@ -153,8 +163,9 @@ RID_DEV double block_sum(double v, double *sh) {
 }
 
 // ------------------------------------------------------------------ bodies
+// The norm partials of x are per 64 columns (one per wave here, one per
+// workgroup of the w step).
 RID_DEV void x0_body(const ResJob &r, int64_t bx) {
-  __shared__ double sh[4];
   const int64_t j = bx * 256 + threadIdx.x;
   double v = 0.0;
   if (j < r.n) {
@@ -162,8 +173,9 @@ RID_DEV void x0_body(const ResJob &r, int64_t bx) {
     r.x[j] = g;
     v = g.x * g.x + g.y * g.y;
   }
-  const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) r.wn_part[bx] = s;
+  v = wave_sum(v);
+  const int64_t g64 = bx * 4 + (threadIdx.x >> 6);
+  if ((threadIdx.x & 63) == 0 && g64 < r.pl.nb_w) r.wn_part[g64] = v;
   if (bx == 0 && threadIdx.x == 0) {
     r.scal[0] = 0.0;
     r.scal[1] = 0.0;
@@ -175,7 +187,7 @@ RID_DEV void wnorm_final_body(const ResJob &r) {
   __shared__ double sh[4];
   if (stopped(r.scal)) return;
   double v = 0.0;
-  for (int64_t i = threadIdx.x; i < r.pl.nb_n; i += 256) v += r.wn_part[i];
+  for (int64_t i = threadIdx.x; i < r.pl.nb_w; i += 256) v += r.wn_part[i];
   const double s = block_sum(v, sh);
   if (threadIdx.x == 0) {
     const double nrm = sqrt(s);
@@ -205,43 +217,59 @@ RID_DEV void xt_init_body(const ResJob &r, int64_t bx) {
 }
 
 // partial (P x)_t over a block of columns, compensated
+// (P x)_t over one column set, for every t: wave w of workgroup bx takes
+// set 4 bx + w (columns px_cpw (4 bx + w) ..), its lanes rows t = lane + 64 h
+// of those columns (coalesced reads of P), compensated sums in column order.
 RID_DEV void px_partial_body(const ResJob &r, int64_t bx) {
   if (stopped(r.scal)) return;
-  const int64_t j0 = bx * PX_JC;
-  const int64_t j1 = min(r.n, j0 + PX_JC);
-  for (int64_t t = threadIdx.x; t < r.k; t += 256) {
+  const int lane = threadIdx.x & 63;
+  const int64_t set = bx * 4 + (threadIdx.x >> 6);
+  if (set >= r.pl.nb_px) return;
+  const int64_t j0 = set * r.pl.px_cpw;
+  const int64_t j1 = min(r.n, j0 + r.pl.px_cpw);
+  for (int64_t tb = 0; tb < r.k; tb += 64) {
+    const int64_t t = tb + lane;
+    const bool ok = t < r.k;
+    const double2 *pc = r.P + (ok ? t : 0);
     double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
     // unrolled so that several loads are in flight; the sums keep their order
 #pragma unroll 8
     for (int64_t j = j0; j < j1; ++j) {
-      const double2 pe = r.P[t + j * r.ldp];
+      const double2 pv = pc[j * r.ldp];
+      const double2 pe = ok ? pv : make_double2(0.0, 0.0);
       const double2 xj = r.x[j];
       dot2_acc(sr, cr, pe.x, xj.x);
       dot2_acc(sr, cr, -pe.y, xj.y);
       dot2_acc(si, ci, pe.x, xj.y);
       dot2_acc(si, ci, pe.y, xj.x);
     }
-    double *o = r.pxpart + (bx * r.k + t) * 4;
-    o[0] = sr;
-    o[1] = cr;
-    o[2] = si;
-    o[3] = ci;
+    if (ok) {
+      double *o = r.pxpart + (set * r.k + t) * 4;
+      o[0] = sr;
+      o[1] = cr;
+      o[2] = si;
+      o[3] = ci;
+    }
   }
 }
 
-// x~_{J[t]} = x_{J[t]} - (P x)_t as a double-double pair
+// x~_{J[t]} = x_{J[t]} - (P x)_t as a double-double pair: wave w of
+// workgroup bx takes t = 4 bx + w, its lanes the partial sets lane,
+// lane + 64, ..., and a compensated wave sum joins them.
 RID_DEV void px_final_body(const ResJob &r, int64_t bx) {
   if (stopped(r.scal)) return;
-  const int64_t t = bx * 256 + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int64_t t = bx * 4 + (threadIdx.x >> 6);
   if (t >= r.k) return;
   double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
-  // unrolled so that several loads are in flight; the sums keep their order
-#pragma unroll 8
-  for (int64_t b = 0; b < r.pl.nb_px; ++b) {
+  for (int64_t b = lane; b < r.pl.nb_px; b += 64) {
     const double *o = r.pxpart + (b * r.k + t) * 4;
     dd_add(sr, cr, o[0], o[1]);
     dd_add(si, ci, o[2], o[3]);
   }
+  wave_sum_dd(sr, cr);
+  wave_sum_dd(si, ci);
+  if (lane != 0) return;
   const int64_t jt = r.J[t];
   if (jt < 0 || jt >= r.n) return;
   const double2 xj = r.x[jt];
@@ -896,45 +924,78 @@ RID_DEV void u_final_body(const ResJob &r, int64_t bx) {
   r.ul[j] = make_double2(lr, li);
 }
 
-// w_j = u_j - sum_t conj(P(t, j)) u_{J[t]}, compensated; x <- w (unscaled)
+// w_j = u_j - sum_t conj(P(t, j)) u_{J[t]}, compensated; x <- w (unscaled).
+// Workgroup bx takes columns 64 bx .. 64 bx + 63, one per lane.  u_J is
+// staged in LDS 256 rows at a time (a small footprint keeps many
+// workgroups resident); wave w takes its quarter of each chunk's rows of P,
+// and the four compensated partials are joined in wave order.  The norm
+// partial of x is per 64 columns.
 RID_DEV void w_body(const ResJob &r, int64_t bx) {
-  __shared__ double2 ujh[RES_KMAX];
-  __shared__ double2 ujl[RES_KMAX];
-  __shared__ double sh[4];
+  constexpr int WC = 256;  // rows of u_J per chunk
+  __shared__ double2 ujh[WC];
+  __shared__ double2 ujl[WC];
+  __shared__ double part[4][64][4];
   if (stopped(r.scal)) return;
   const int64_t n = r.n, k = r.k;
-  for (int64_t t = threadIdx.x; t < k; t += 256) {
-    const int64_t jt = r.J[t];
-    const bool ok = jt >= 0 && jt < n;
-    ujh[t] = ok ? r.uh[jt] : make_double2(0.0, 0.0);
-    ujl[t] = ok ? r.ul[jt] : make_double2(0.0, 0.0);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t j = bx * 64 + lane;
+  double sr = 0.0, cr = 0.0, si = 0.0, ci = 0.0;
+  if (j < n && wave == 0) {
+    const double2 h = r.uh[j], lo = r.ul[j];
+    sr = h.x;
+    cr = lo.x;
+    si = h.y;
+    ci = lo.y;
   }
+  const double2 *pc = r.P + (j < n ? j : 0) * r.ldp;
+  for (int64_t c0 = 0; c0 < k; c0 += WC) {
+    const int64_t kc = min(k - c0, static_cast<int64_t>(WC));
+    if (c0 > 0) __syncthreads();  // every wave done with the previous chunk
+    if (threadIdx.x < kc) {
+      const int64_t jt = r.J[c0 + threadIdx.x];
+      const bool ok = jt >= 0 && jt < n;
+      ujh[threadIdx.x] = ok ? r.uh[jt] : make_double2(0.0, 0.0);
+      ujl[threadIdx.x] = ok ? r.ul[jt] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+    const int64_t kq = (kc + 3) / 4;
+    const int64_t t0 = wave * kq, t1 = min(kc, t0 + kq);
+    if (j < n) {
+#pragma unroll 4
+      for (int64_t t = t0; t < t1; ++t) {
+        const double2 pe = pc[c0 + t];
+        const double2 a = ujh[t], b = ujl[t];
+        // conj(p) u = (pr ur + pi ui) + i (pr ui - pi ur)
+        dot2_acc(sr, cr, -pe.x, a.x);
+        dot2_acc(sr, cr, -pe.y, a.y);
+        cr = fma(-pe.x, b.x, cr);
+        cr = fma(-pe.y, b.y, cr);
+        dot2_acc(si, ci, -pe.x, a.y);
+        dot2_acc(si, ci, pe.y, a.x);
+        ci = fma(-pe.x, b.y, ci);
+        ci = fma(pe.y, b.x, ci);
+      }
+    }
+  }
+  part[wave][lane][0] = sr;
+  part[wave][lane][1] = cr;
+  part[wave][lane][2] = si;
+  part[wave][lane][3] = ci;
   __syncthreads();
-  const int64_t j = bx * 256 + threadIdx.x;
+  if (wave != 0) return;
   double v = 0.0;
   if (j < n) {
-    const double2 h = r.uh[j], lo = r.ul[j];
-    double sr = h.x, cr = lo.x, si = h.y, ci = lo.y;
-    const double2 *pc = r.P + j * r.ldp;
-    for (int64_t t = 0; t < k; ++t) {
-      const double2 pe = pc[t];
-      const double2 a = ujh[t], b = ujl[t];
-      // conj(p) u = (pr ur + pi ui) + i (pr ui - pi ur)
-      dot2_acc(sr, cr, -pe.x, a.x);
-      dot2_acc(sr, cr, -pe.y, a.y);
-      cr = fma(-pe.x, b.x, cr);
-      cr = fma(-pe.y, b.y, cr);
-      dot2_acc(si, ci, -pe.x, a.y);
-      dot2_acc(si, ci, pe.y, a.x);
-      ci = fma(-pe.x, b.y, ci);
-      ci = fma(pe.y, b.x, ci);
+#pragma unroll
+    for (int w = 1; w < 4; ++w) {
+      dd_add(sr, cr, part[w][lane][0], part[w][lane][1]);
+      dd_add(si, ci, part[w][lane][2], part[w][lane][3]);
     }
     const double wr = sr + cr, wi = si + ci;
     r.x[j] = make_double2(wr, wi);
     v = wr * wr + wi * wi;
   }
-  const double s = block_sum(v, sh);
-  if (threadIdx.x == 0) r.wn_part[bx] = s;
+  v = wave_sum(v);
+  if (lane == 0) r.wn_part[bx] = v;
 }
 
 // ------------------------------------------------------------------ launches
@@ -1011,9 +1072,10 @@ void step_grid(int step, const ResJob &r, int64_t &gx, int64_t &gy) {
   const ResPlan &p = r.pl;
   gy = 1;
   switch (step) {
-    case ST_X0: case ST_XSCALE: case ST_XTINIT: case ST_UF: case ST_W: gx = p.nb_n; break;
+    case ST_X0: case ST_XSCALE: case ST_XTINIT: case ST_UF: gx = p.nb_n; break;
+    case ST_W: gx = p.nb_w; break;
     case ST_WNORM: case ST_SIGMA: gx = 1; break;
-    case ST_PXP: gx = r.k > 0 ? p.nb_px : 0; break;
+    case ST_PXP: gx = r.k > 0 ? p.nb_pxb : 0; break;
     case ST_PXF: gx = r.k > 0 ? p.nb_k : 0; break;
     case ST_AX: gx = p.nb_ax; gy = p.nb_axy; break;
     case ST_ZF: gx = p.nb_m; break;

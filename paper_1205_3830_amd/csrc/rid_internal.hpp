@@ -336,17 +336,30 @@ RID_DEV double wave_sum(double v) {
   return v;
 }
 
-// Double-double wave sum; the result is valid in every lane.
+// Double-double wave sum (all 64 lanes active), the butterfly of wave_sum:
+// dd_add gives the same bits whichever pair comes first, so every lane
+// ends with the same (s, c).
+template <int CTRL>
+RID_DEV void dd_add_dpp(double &s, double &c) {
+  const double s2 = dpp_f64<CTRL>(s), c2 = dpp_f64<CTRL>(c);
+  dd_add(s, c, s2, c2);
+}
+template <int W>
+RID_DEV void dd_add_swap(double &s, double &c) {
+  double s1, s2, c1, c2;
+  swap_pair<W>(s, s1, s2);
+  swap_pair<W>(c, c1, c2);
+  dd_add(s1, c1, s2, c2);
+  s = s1;
+  c = c1;
+}
 RID_DEV void wave_sum_dd(double &s, double &c) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) {
-    const double s2 = __shfl_xor(s, off, 64);
-    const double c2 = __shfl_xor(c, off, 64);
-    dd_add(s, c, s2, c2);
-  }
-  // lanes may differ in the last bits after xor-butterflies; take lane 0's
-  s = __shfl(s, 0, 64);
-  c = __shfl(c, 0, 64);
+  dd_add_swap<32>(s, c);
+  dd_add_swap<16>(s, c);
+  dd_add_dpp<0x128>(s, c);  // row_ror:8
+  dd_add_dpp<0x124>(s, c);  // row_ror:4
+  dd_add_dpp<0x4E>(s, c);   // quad_perm [2,3,0,1]
+  dd_add_dpp<0xB1>(s, c);   // quad_perm [1,0,3,2]
 }
 
 // Sums NV double-double values (s[v], c[v]) (NV a power of two, 2..64) over
