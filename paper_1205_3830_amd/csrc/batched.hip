@@ -107,11 +107,7 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
   std::vector<InterpJob> in(count);
   std::vector<int> mt(count);
   int kmax = 1;
-  int64_t lmax = 1;
-  for (int i = 0; i < count; ++i) {
-    kmax = std::max<int>(kmax, static_cast<int>(bj[i].k));
-    lmax = std::max<int64_t>(lmax, bj[i].l);
-  }
+  for (int i = 0; i < count; ++i) kmax = std::max<int>(kmax, static_cast<int>(bj[i].k));
   // persistent region: Y, mark, status; scratch region: G + partials, or the
   // residual workspace (the sketch is done before the residual starts)
   WsCarve pc(nullptr);
@@ -172,9 +168,22 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
         t_sk[bucket].push_back(make_int4(i, static_cast<int>(x), static_cast<int>(s), 0));
     const int64_t nq = interp_blocks(bj[i].n);
     for (int64_t x = 0; x < nq; ++x) t_in.push_back(make_int4(i, static_cast<int>(x), 0, 0));
+  }
+  // the QR table by k, largest first: the launch of step t covers only the
+  // prefix of jobs that still have step t (k >= t), and picks its rows per
+  // lane from their largest l
+  std::vector<int> by_k(count);
+  std::iota(by_k.begin(), by_k.end(), 0);
+  std::stable_sort(by_k.begin(), by_k.end(), [&](int a, int b) { return bj[a].k > bj[b].k; });
+  std::vector<int64_t> qr_live(kmax + 1, 0), qr_lmax(kmax + 1, 1);
+  for (int i : by_k) {
     const int64_t nbq = pivqr_blocks(bj[i].n);
     for (int64_t x = 0; x < nbq; ++x)
       t_qr.push_back(make_int4(i, static_cast<int>(x), static_cast<int>(nbq), 0));
+    for (int64_t t = 0; t <= bj[i].k && t <= kmax; ++t) {
+      qr_live[t] = static_cast<int64_t>(t_qr.size());
+      qr_lmax[t] = std::max<int64_t>(qr_lmax[t], bj[i].l);
+    }
   }
 
   // the per-job QR launch takes the largest jobs first
@@ -283,7 +292,7 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
                             static_cast<int>(nbuck), red_off, static_cast<int64_t>(t_red.size()),
                             prof);
     if (e != hipSuccess) return e;
-    e = qmode ? launch_pivqr_batch(st, lmax, kmax, d_qr, d_tqr,
+    e = qmode ? launch_pivqr_batch(st, qr_lmax.data(), qr_live.data(), kmax, d_qr, d_tqr,
                                    static_cast<int64_t>(t_qr.size()), prof, qmode)
               : launch_pivqr_jobs(st, d_qr, d_qord, count, prof);
     if (e != hipSuccess) return e;

@@ -1439,15 +1439,19 @@ void pivqr_job_carve(char *base, PivJob &jb) {
   jb.nu0 = c.take<double>(1);
 }
 
-hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const PivJob *djobs,
-                              const int4 *dtab, int64_t count, RidProf *prof, int cb) {
+hipError_t launch_pivqr_batch(hipStream_t st, const int64_t *lmax, const int64_t *live,
+                              int64_t kmax, const PivJob *djobs, const int4 *dtab, int64_t count,
+                              RidProf *prof, int cb) {
   if (count == 0) return hipSuccess;
-  const dim3 grid(static_cast<unsigned>(count));
   ProfScope ps(prof, st, RID_KERNEL_PIVQR);
-  hipLaunchKernelGGL(pivqr_init_grouped, grid, dim3(256), 0, st, djobs, dtab);
+  hipLaunchKernelGGL(pivqr_init_grouped, dim3(static_cast<unsigned>(count)), dim3(256), 0, st,
+                     djobs, dtab);
   for (int t = 0; t <= kmax; ++t) {
-    // every job's rows in play, t-1 .. l-1, fit in lmax - (t-1)
-    with_rr(pick_rr(lmax - (t > 0 ? t - 1 : 0)), [&](auto R) {
+    const int64_t nlive = std::min(live[t], count);
+    if (nlive <= 0) continue;
+    const dim3 grid(static_cast<unsigned>(nlive));
+    // the live jobs' rows in play, t-1 .. l-1, fit in lmax[t] - (t-1)
+    with_rr(pick_rr(lmax[t] - (t > 0 ? t - 1 : 0)), [&](auto R) {
       constexpr int RR = decltype(R)::value;
       if constexpr (RR <= 4) {
         if (cb == 4)

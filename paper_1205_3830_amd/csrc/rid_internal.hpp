@@ -598,8 +598,11 @@ void pivqr_job_carve(char *base, PivJob &jb);
 // in the order given (device array of count job indices).
 hipError_t launch_pivqr_jobs(hipStream_t st, const PivJob *djobs, const int *dorder, int count,
                              RidProf *prof);
-hipError_t launch_pivqr_batch(hipStream_t st, int64_t lmax, int64_t kmax, const PivJob *djobs,
-                              const int4 *dtab, int64_t count, RidProf *prof, int cb);
+// One grouped launch per step t = 0 .. kmax: the first live[t] entries of
+// the table (the jobs with k >= t come first), lmax[t] their largest l.
+hipError_t launch_pivqr_batch(hipStream_t st, const int64_t *lmax, const int64_t *live,
+                              int64_t kmax, const PivJob *djobs, const int4 *dtab, int64_t count,
+                              RidProf *prof, int cb);
 
 // SVD of A(:, J) P (k <= 256): workspace size and launch.  Synchronises the
 // stream (to read the sweep count and the breakdown flag); *rank_bad is set
