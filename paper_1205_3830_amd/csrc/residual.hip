@@ -410,12 +410,12 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
         if constexpr (ACC == RES_DOT2) {
 #pragma unroll
           for (int u = 0; u < 8; ++u) {
-            xl[u] = xtl[j + u];
+            xl[u] = ld_uniform(xtl, j + u);
             lo = lo || xl[u].x != 0.0 || xl[u].y != 0.0;
           }
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) acc_hi(a0[u], a1[u], xth[j + u]);
+        for (int u = 0; u < 8; ++u) acc_hi(a0[u], a1[u], ld_uniform(xth, j + u));
         if (lo) {
 #pragma unroll
           for (int u = 0; u < 8; ++u) acc_lo(a0[u], a1[u], xl[u]);
@@ -431,12 +431,12 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
     if constexpr (ACC == RES_DOT2) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        xl[u] = xtl[j + u];
+        xl[u] = ld_uniform(xtl, j + u);
         lo = lo || xl[u].x != 0.0 || xl[u].y != 0.0;
       }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc_hi(a0[u], a1[u], xth[j + u]);
+    for (int u = 0; u < 4; ++u) acc_hi(a0[u], a1[u], ld_uniform(xth, j + u));
     if (lo) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) acc_lo(a0[u], a1[u], xl[u]);
@@ -445,8 +445,8 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
   for (; j < je; ++j) {
     double2 a0, a1;
     RP::load(a0p, a1p, ok0, ok1, j * lda, pair, a0, a1);
-    acc_hi(a0, a1, xth[j]);
-    if constexpr (ACC == RES_DOT2) acc_lo(a0, a1, xtl[j]);
+    acc_hi(a0, a1, ld_uniform(xth, j));
+    if constexpr (ACC == RES_DOT2) acc_lo(a0, a1, ld_uniform(xtl, j));
   }
   if constexpr (ACC == RES_FP32) {
     s0r = f0r;
@@ -491,7 +491,7 @@ RID_DEV void ax_body(const ResJob &r, int64_t bx, int64_t by) {
 // their errors, so they take this body for an even lda only (every column
 // unshifted); the low words of x~ join the error sums as in the general
 // loop.
-template <int ACC>
+template <int ACC, bool SX>
 RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
   using Acc = typename std::conditional<ACC == RES_FP32, float, double>::type;
   // no early test of the stop flag: a stopped job's partials are computed
@@ -504,14 +504,17 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
   const int h = r.pl.ax_h;
   const int half = h >> 1;
   const int tg = t % half;
-  const int64_t split = by * (AX_ROWS / h) + t / half;
+  // the same in every lane of a wave (a group is at least one wave): read
+  // as uniform, so that the column loop's x~ loads are scalar loads
+  const int64_t split = uniform_i64(by * (AX_ROWS / h) + t / half);
   const int64_t i0 = bx * h + 2 * tg;
   const bool ok0 = i0 < m, ok1 = i0 + 1 < m;
   const bool okm = i0 >= 1 && i0 - 1 < m;  // row i0 - 1 of a shifted pair
   const bool odd = (lda & 1) != 0;
   // a wave whose rows (shifted ones included) all lie past m, or whose
   // split lies past the last one, has no loads
-  const bool live = bx * h + 128 * (tg >> 6) - 1 < m && split < r.pl.S_z;
+  const bool live = __builtin_amdgcn_readfirstlane(
+                        (bx * h + 128 * (tg >> 6) - 1 < m && split < r.pl.S_z) ? 1 : 0) != 0;
   // pair starts: unshifted (i0, or row 0 past m); shifted (i0 - 1, or row
   // -1 past m: the previous column's last stored entry, as j >= 1 there)
   const int64_t pu = ok0 ? i0 : 0;
@@ -519,6 +522,15 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
   const int64_t jb = split * r.pl.cpz;
   const int64_t je = live ? min(r.n, jb + r.pl.cpz) : jb;
   const double2 *__restrict__ xth = r.xth;
+  // x~ of a column, the same in every lane: a scalar load (SX, the batch's
+  // passes: one scalar load per two columns instead of a vector load each)
+  // or a plain load (one ID: the scalar form costs it a wave per SIMD)
+  auto xload = [](const double2 *p, int64_t i) -> double2 {
+    if constexpr (SX)
+      return ld_uniform(p, i);
+    else
+      return p[i];
+  };
   Acc s0r = 0, s0i = 0, s1r = 0, s1i = 0;  // rows i0, i0 + 1 (unshifted columns)
   Acc smr = 0, smi = 0, snr = 0, sni = 0;  // rows i0 - 1, i0 (shifted columns)
   const double2 zero2 = make_double2(0.0, 0.0);
@@ -573,11 +585,11 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
       bool any = false;
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
-        xl[u] = xtl[j + u];
+        xl[u] = xload(xtl, j + u);
         any = any || xl[u].x != 0.0 || xl[u].y != 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) hi(a0[u], a1[u], xth[j + u]);
+      for (int u = 0; u < 8; ++u) hi(a0[u], a1[u], xload(xth, j + u));
       if (any) {
 #pragma unroll
         for (int u = 0; u < 8; ++u) lo(a0[u], a1[u], xl[u]);
@@ -586,8 +598,8 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
     for (; j < je; ++j) {
       double2 a0, a1;
       ld_stream_pair(A + j * lda + pu, a0, a1);
-      hi(a0, a1, xth[j]);
-      lo(a0, a1, xtl[j]);
+      hi(a0, a1, xload(xth, j));
+      lo(a0, a1, xload(xtl, j));
     }
     if (split >= r.pl.S_z) return;
     double *zp = r.zpart + split * m * 4;
@@ -620,7 +632,7 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
     if ((j & 1) && j < je) {
       double2 b0, b1;
       ld_stream_pair(A + j * lda + ps, b0, b1);
-      shifted(b0, b1, xth[j]);
+      shifted(b0, b1, xload(xth, j));
       ++j;
     }
     for (; j + 8 <= je; j += 8) {
@@ -630,9 +642,9 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) {
         if (u & 1)
-          shifted(a0[u], a1[u], xth[j + u]);
+          shifted(a0[u], a1[u], xload(xth, j + u));
         else
-          unshifted(a0[u], a1[u], xth[j + u]);
+          unshifted(a0[u], a1[u], xload(xth, j + u));
       }
     }
     for (; j < je; ++j) {
@@ -640,9 +652,9 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
       const bool sh = (j & 1) != 0;
       ld_stream_pair(A + j * lda + (sh ? ps : pu), a0, a1);
       if (sh)
-        shifted(a0, a1, xth[j]);
+        shifted(a0, a1, xload(xth, j));
       else
-        unshifted(a0, a1, xth[j]);
+        unshifted(a0, a1, xload(xth, j));
     }
   } else {
     for (; j + 8 <= je; j += 8) {
@@ -650,12 +662,12 @@ RID_DEV void ax_c64_paired(const ResJob &r, int64_t bx, int64_t by) {
 #pragma unroll
       for (int u = 0; u < 8; ++u) ld_stream_pair(A + (j + u) * lda + pu, a0[u], a1[u]);
 #pragma unroll
-      for (int u = 0; u < 8; ++u) unshifted(a0[u], a1[u], xth[j + u]);
+      for (int u = 0; u < 8; ++u) unshifted(a0[u], a1[u], xload(xth, j + u));
     }
     for (; j < je; ++j) {
       double2 a0, a1;
       ld_stream_pair(A + j * lda + pu, a0, a1);
-      unshifted(a0, a1, xth[j]);
+      unshifted(a0, a1, xload(xth, j));
     }
   }
   // words 0 and 2 of rows i0, i0 + 1; words 1 and 3 of rows i0 - 1, i0
@@ -1007,7 +1019,7 @@ enum Step : int {
   ST_W, ST_AHZ4, ST_COUNT
 };
 
-template <class TA, int STEP, bool WIDE, int ACC>
+template <class TA, int STEP, bool WIDE, int ACC, bool GROUPED = false>
 RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
   if constexpr (STEP == ST_X0) x0_body(r, bx);
   if constexpr (STEP == ST_WNORM) wnorm_final_body(r);
@@ -1022,7 +1034,7 @@ RID_DEV void run_step(const ResJob &r, int64_t bx, int64_t by, int t) {
     if constexpr (sizeof(TA) == 8 && (ACC != RES_DOT2 || !WIDE)) {
       const bool even = (r.lda & 1) == 0;
       if (r.al16 && r.m >= 2 && (even || (ACC != RES_DOT2 && r.m % r.pl.ax_h != 0))) {
-        ax_c64_paired<ACC>(r, bx, by);
+        ax_c64_paired<ACC, GROUPED>(r, bx, by);
         return;
       }
     }
@@ -1048,7 +1060,7 @@ __global__ __launch_bounds__(256) void step_grouped(const ResJob *__restrict__ j
   // the whole-slab fast path of the ax pass only with plain sums, whose
   // registers leave room for it (with compensated sums it costs a batch
   // more occupancy than its jobs gain)
-  run_step<TA, STEP, ACC != RES_DOT2, ACC>(jobs[e.x], e.y, e.z, t);
+  run_step<TA, STEP, ACC != RES_DOT2, ACC, true>(jobs[e.x], e.y, e.z, t);
 }
 
 // The passes over A take the accumulation `acc` (RES_*); every other step

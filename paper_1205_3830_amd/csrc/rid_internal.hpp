@@ -201,6 +201,16 @@ RID_DEV double uniform_f64(double v) {
   return __builtin_bit_cast(double, uniform_i64(__builtin_bit_cast(int64_t, v)));
 }
 
+// p[i] where the index is the same in every lane and no kernel writes p
+// while this one runs: read through the constant address space, so that the
+// load is one scalar load (the scalar cache starts each kernel invalidated)
+// instead of a vector load that every lane repeats.
+RID_DEV double2 ld_uniform(const double2 *p, int64_t i) {
+  const __attribute__((address_space(4))) double *q =
+      (const __attribute__((address_space(4))) double *)p;
+  return make_double2(q[2 * i], q[2 * i + 1]);
+}
+
 template <class T>
 RID_DEV T zero_of();
 template <>
