@@ -381,25 +381,34 @@ RID_DEV void wave_sum_dd(double &s, double &c) {
 // and 17 compensated adds, against 192 and 96 for 16 separate wave sums.  On
 // return (s[0], c[0]) of every lane is the total of its value v (dd_add is
 // symmetric, so all lanes of a group hold the same bits).
+// One level of wave_reduce_dd (HALF values kept of 2 HALF), then the next;
+// a compile-time recursion, so that every index into s and c is a constant
+// (an index the compiler cannot resolve becomes a chain of compares and
+// selects over the whole array).
+template <int NV, int HALF>
+RID_DEV void wave_reduce_dd_level(double (&s)[NV], double (&c)[NV], int lane) {
+  if constexpr (HALF >= 1) {
+    constexpr int off = HALF * (64 / NV);
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int j = 0; j < HALF; ++j) {
+      double ks = up ? s[HALF + j] : s[j], kc = up ? c[HALF + j] : c[j];
+      const double gs = __shfl_xor(up ? s[j] : s[HALF + j], off, 64);
+      const double gc = __shfl_xor(up ? c[j] : c[HALF + j], off, 64);
+      dd_add(ks, kc, gs, gc);
+      s[j] = ks;
+      c[j] = kc;
+    }
+    wave_reduce_dd_level<NV, HALF / 2>(s, c, lane);
+  }
+}
+
 template <int NV>
 RID_DEV void wave_reduce_dd(double (&s)[NV], double (&c)[NV]) {
   static_assert(NV >= 2 && NV <= 64 && (NV & (NV - 1)) == 0, "NV: power of two in 2..64");
   const int lane = threadIdx.x & 63;
   constexpr int GROUP = 64 / NV;  // lanes that end up holding the same value
-#pragma unroll
-  for (int half = NV / 2; half >= 1; half >>= 1) {
-    const int off = half * GROUP;
-    const bool up = (lane & off) != 0;
-#pragma unroll
-    for (int j = 0; j < half; ++j) {
-      double ks = up ? s[half + j] : s[j], kc = up ? c[half + j] : c[j];
-      const double gs = __shfl_xor(up ? s[j] : s[half + j], off, 64);
-      const double gc = __shfl_xor(up ? c[j] : c[half + j], off, 64);
-      dd_add(ks, kc, gs, gc);
-      s[j] = ks;
-      c[j] = kc;
-    }
-  }
+  wave_reduce_dd_level<NV, NV / 2>(s, c, lane);
 #pragma unroll
   for (int off = GROUP / 2; off >= 1; off >>= 1) {
     const double gs = __shfl_xor(s[0], off, 64);
