@@ -302,10 +302,15 @@ def test_pivqr_exact_tie_goes_to_lowest_index(h):
 
 
 # ------------------------------------------------------------------ a5: residual
+# (700, 800, 300): u_J staged in two chunks of the w step, five row chunks
+# of P in the P x sets; (300, 17000, 12): more columns than the P x step has
+# sets (1024 sets of 17 columns, the last one short)
 @pytest.mark.parametrize("m,n,k,l,noise,q", [(1000, 500, 20, 30, 1e-10, 10),
                                              (777, 333, 9, 17, 1e-7, 6),
                                              (300, 1100, 40, 48, 1e-9, 4),
-                                             (64, 50, 50, 50, 0.0, 3)])
+                                             (64, 50, 50, 50, 0.0, 3),
+                                             (700, 800, 300, 310, 1e-9, 3),
+                                             (300, 17000, 12, 20, 1e-9, 3)])
 def test_residual_call_for_call(h, m, n, k, l, noise, q):
     A = _lowrank(m, n, k, noise, seed=m)
     r = oracle.decompose(A, k, l, seed=3, q=q)
