@@ -153,6 +153,9 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
     const int nr = static_cast<int>(std::min<int64_t>((totY + 255) / 256, 64));
     for (int b = 0; b < nr; ++b) t_red.push_back(make_int4(i, b, nr, 0));
     mt[i] = sketch_pick_mt(bj[i].l);
+    // FP32 products: the kernel covers (mt + 1) / 2 row tiles of Y, so tile
+    // counts 2c - 1 and 2c share one launch
+    if (prec == RID_FP32) mt[i] = (mt[i] + 1) / 2 * 2;
     int bucket = -1;
     for (size_t u = 0; u < mts.size(); ++u)
       if (mts[u] == mt[i]) bucket = static_cast<int>(u);
