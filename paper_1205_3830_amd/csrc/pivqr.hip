@@ -119,6 +119,20 @@ RID_DEV Cand cand_wave_merge(Cand c) {
   return c;
 }
 
+// The merge of a 256-thread workgroup's candidates, the same in every
+// thread: each wave's merge, then the four in wave order.  red holds at least
+// four candidates in LDS; the caller writes none of red[0..3] again before a
+// barrier that every thread reaches after this call.
+RID_DEV Cand cand_block_merge(Cand cd, Cand *red) {
+  cd = cand_wave_merge(cd);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = cd;
+  __syncthreads();
+  Cand best = cand_empty();
+#pragma unroll
+  for (int wv = 0; wv < 4; ++wv) best = cand_merge(best, red[wv]);
+  return best;
+}
+
 __global__ void pivqr_init_kernel(int64_t n, int *pstep, int *status) {
   const int64_t j = blockIdx.x * int64_t(blockDim.x) + threadIdx.x;
   if (j < n) pstep[j] = -1;
@@ -303,15 +317,9 @@ RID_DEV void pivqr_step_body(int t, int64_t l, int64_t n, int64_t k, double2 *Y,
       if (x.v1 < 0.0) x = cand_empty();
       cd = cand_merge(cd, x);
     }
-    // each wave's merge, then the four in wave order; the same in every
-    // lane: read as uniform, so that what depends on it (the exit on
-    // failure, the pivot index) stays uniform for the compiler
-    cd = cand_wave_merge(cd);
-    if (lane == 0) red[wave] = cd;
-    __syncthreads();
-    Cand best = cand_empty();
-#pragma unroll
-    for (int wv = 0; wv < 4; ++wv) best = cand_merge(best, red[wv]);
+    // the same in every lane: read as uniform, so that what depends on it
+    // (the exit on failure, the pivot index) stays uniform for the compiler
+    Cand best = cand_block_merge(cd, red);
     best.v1 = uniform_f64(best.v1);
     best.i1 = uniform_i64(best.i1);
     const double nu1 = best.v1;
@@ -450,7 +458,7 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
                                                           int64_t nbk, int64_t gprev) {
   __shared__ double2 vl[QP_NB][64 * RR];
   __shared__ double2 taus[QP_NB];
-  __shared__ Cand red[256];
+  __shared__ Cand red[4];
   __shared__ double beta_s;
   __shared__ int status_s;
   if (threadIdx.x == 0) status_s = *status;
@@ -484,15 +492,9 @@ __global__ __launch_bounds__(256) void pivqr_panel_kernel(int t, int a, int wr, 
       if (x.v1 < 0.0) x = cand_empty();
       cd = cand_merge(cd, x);
     }
-    red[tid] = cd;
-    __syncthreads();
-    for (int st = 128; st >= 1; st >>= 1) {
-      if (tid < st) red[tid] = cand_merge(red[tid], red[tid + st]);
-      __syncthreads();
-    }
     // the same in every lane: read as uniform, so that what depends on it
     // (the exit on failure, the pivot index) stays uniform for the compiler
-    Cand best = red[0];
+    Cand best = cand_block_merge(cd, red);
     best.v1 = uniform_f64(best.v1);
     best.i1 = uniform_i64(best.i1);
     const double nu1 = best.v1;
@@ -843,7 +845,7 @@ __global__ __launch_bounds__(256) void cgs2_pick_kernel(int t, int64_t l, int64_
   constexpr int QU = 4;                    // directions per wave in flight
   __shared__ double2 vs[64 * RR];          // the pivot's residual column, then v
   __shared__ double2 c_s[1024];            // c_i = q_i^H v
-  __shared__ Cand red[256];
+  __shared__ Cand red[4];
   __shared__ double part[256];
   __shared__ int status_s;
   if (threadIdx.x == 0) status_s = *status;
@@ -859,13 +861,7 @@ __global__ __launch_bounds__(256) void cgs2_pick_kernel(int t, int64_t l, int64_
     if (x.v1 < 0.0) x = cand_empty();
     cd = cand_merge(cd, x);
   }
-  red[tid] = cd;
-  __syncthreads();
-  for (int st = 128; st >= 1; st >>= 1) {
-    if (tid < st) red[tid] = cand_merge(red[tid], red[tid + st]);
-    __syncthreads();
-  }
-  const Cand best = red[0];
+  const Cand best = cand_block_merge(cd, red);
   const double nu1 = best.v1;
   const double nu0 = (t == 1) ? nu1 : *w.nu0;
   const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
@@ -969,7 +965,7 @@ template <int RR>
 __global__ __launch_bounds__(256) void cgs2_head_kernel(int t, int64_t l, int64_t *perm,
                                                         double *gaps, double rank_tol, PivWs w,
                                                         CgsSplit cs, int *status, int64_t nb) {
-  __shared__ Cand red[256];
+  __shared__ Cand red[4];
   __shared__ int status_s;
   if (threadIdx.x == 0) status_s = *status;
   __syncthreads();
@@ -982,13 +978,7 @@ __global__ __launch_bounds__(256) void cgs2_head_kernel(int t, int64_t l, int64_
     if (x.v1 < 0.0) x = cand_empty();
     cd = cand_merge(cd, x);
   }
-  red[tid] = cd;
-  __syncthreads();
-  for (int st = 128; st >= 1; st >>= 1) {
-    if (tid < st) red[tid] = cand_merge(red[tid], red[tid + st]);
-    __syncthreads();
-  }
-  const Cand best = red[0];
+  const Cand best = cand_block_merge(cd, red);
   const double nu1 = best.v1;
   const double nu0 = (t == 1) ? nu1 : *w.nu0;
   const bool fail = !(nu1 > 0.0) || nu1 <= rank_tol * nu0;
