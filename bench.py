@@ -105,7 +105,7 @@ def batched_result(args, torch, rid, synth) -> dict:
     dt = torch.complex64 if args.dtype == "c64" else torch.complex128
     esize = 8 if args.dtype == "c64" else 16
     prec = PRECS[args.prec](rid)
-    tol = 1e-12 if prec == rid.RID_FP64 else 1e-5
+    tol = RANK_TOL[args.prec]
     print("generating %d matrices" % len(shapes), file=sys.stderr, flush=True)
     As = [synth.lowrank_device(m, n, k, 1e-7, seed=i, dtype=dt).t()
           for i, (m, n, k, l) in enumerate(shapes)]
@@ -819,19 +819,25 @@ def forms_result(args, torch, rid, synth, fp64_line) -> dict:
     ba = copy.copy(args)
     ba.jobs, ba.dtype, ba.steps, ba.no_tune, ba.no_single = 512, "c64", 5, False, False
     batch_rows = {}
-    for p in ("fp64", "fp32"):
+    single_ids = 0.0
+    for p in ("fp64", "fp32", "bf16x2", "bf16x3"):
         ba.prec = p
+        # the one-at-a-time FP64 comparison is the same for every row
+        ba.no_single = p not in ("fp64", "fp32")
         print("forms: batched %s" % p, file=sys.stderr, flush=True)
         rec = batched_result(ba, torch, rid, synth)
         print("forms: batched %s: %.2f ms per batch" % (p, rec["ms_per_step"]), file=sys.stderr,
               flush=True)
         single = rec["single_fp64_one_at_a_time"] or {}
+        if single:
+            single_ids = single["ids_per_s"]
         batch_rows[p] = {"ms": round(rec["ms_per_step"], 3), "ids_per_s": round(rec["ids_per_s"], 1),
                          "A_GB_per_s": round(rec["value"], 1),
                          "ax_hbm_frac": frac(rec, "residual_ax"),
                          "ahz_hbm_frac": frac(rec, "residual_ahz"),
-                         "single_fp64_ids_per_s": round(single.get("ids_per_s", 0.0), 1),
-                         "speedup_vs_single": round(rec["speedup_vs_single"] or 0.0, 2)}
+                         "single_fp64_ids_per_s": round(single_ids, 1),
+                         "speedup_vs_single": round(rec["ids_per_s"] / single_ids, 2)
+                         if single_ids else None}
     forms["batched_512_c64"] = batch_rows
 
     sa = copy.copy(args)

@@ -88,7 +88,9 @@ int qr_mode() {
 }  // namespace
 
 // The grouped sketch is built for FP64 and FP32 products.
-bool batch_prec_supported(rid_prec prec) { return prec == RID_FP64 || prec == RID_FP32; }
+bool batch_prec_supported(rid_prec prec) {
+  return prec == RID_FP64 || prec == RID_FP32 || prec == RID_BF16X2 || prec == RID_BF16X3;
+}
 
 bool batch_job_supported(const RidBatchJob &j) {
   return j.l <= 256 && j.k <= 256 && sketch_pick_mt(j.l) > 0;
@@ -119,13 +121,23 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
   const size_t offStatus = pc.take_off<int>(count);
   const size_t persist = (pc.off + 255) & ~size_t(255);
   WsCarve sc(nullptr);
-  std::vector<size_t> offG(count), offPart(count);
+  std::vector<size_t> offG(count), offPart(count), offPl(count);
   const int64_t pchunk = h->batch_sketch_rows;
+  const bool bf16 = prec == RID_BF16X2 || prec == RID_BF16X3;
+  const int nterms = prec == RID_BF16X2 ? 2 : 3;
   for (int i = 0; i < count; ++i) {
+    mt[i] = sketch_pick_mt(bj[i].l);
+    // the reduced-precision kernels cover (mt + 1) / 2 row tiles of Y, so
+    // tile counts 2c - 1 and 2c share one launch
+    if (prec != RID_FP64) mt[i] = (mt[i] + 1) / 2 * 2;
     const int64_t S = (bj[i].m + pchunk - 1) / pchunk;
     offG[i] = sc.take_off<double2>(size_t(bj[i].l) * size_t(bj[i].m));
-    const size_t el = prec == RID_FP32 ? sizeof(float) : sizeof(double);
+    const size_t el = prec == RID_FP64 ? sizeof(double) : sizeof(float);
     offPart[i] = sc.take_off<char>(size_t(S) * size_t(2 * bj[i].l) * size_t(bj[i].n) * el);
+    // bf16 planes: 16 rows per row tile of the bucket, K padded to 16
+    if (bf16)
+      offPl[i] = sc.take_off<uint16_t>(size_t(nterms) * size_t(8 * mt[i]) *
+                                       size_t(2 * ((bj[i].m + 15) / 16 * 16)));
   }
   // the QR workspace reuses the scratch region too (G is dead by then)
   WsCarve qc(nullptr);
@@ -152,10 +164,6 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
     const int64_t totY = 2 * bj[i].l * bj[i].n;
     const int nr = static_cast<int>(std::min<int64_t>((totY + 255) / 256, 64));
     for (int b = 0; b < nr; ++b) t_red.push_back(make_int4(i, b, nr, 0));
-    mt[i] = sketch_pick_mt(bj[i].l);
-    // FP32 products: the kernel covers (mt + 1) / 2 row tiles of Y, so tile
-    // counts 2c - 1 and 2c share one launch
-    if (prec == RID_FP32) mt[i] = (mt[i] + 1) / 2 * 2;
     int bucket = -1;
     for (size_t u = 0; u < mts.size(); ++u)
       if (mts[u] == mt[i]) bucket = static_cast<int>(u);
@@ -164,7 +172,8 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
       t_sk.emplace_back();
       bucket = static_cast<int>(mts.size()) - 1;
     }
-    const int64_t nbx = (bj[i].n + 63) / 64;
+    const int64_t cols = sketch_batch_cols(prec);
+    const int64_t nbx = (bj[i].n + cols - 1) / cols;
     const int64_t S = (bj[i].m + pchunk - 1) / pchunk;
     for (int64_t s = 0; s < S; ++s)
       for (int64_t x = 0; x < nbx; ++x)
@@ -238,7 +247,14 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
     int *mark = reinterpret_cast<int *>(pbase + offMark[i]);
     double2 *G = reinterpret_cast<double2 *>(sbase + offG[i]);
     sk[i] = SketchJob{bj[i].m, bj[i].n, bj[i].l, bj[i].lda, bj[i].m, pchunk, bj[i].A, G,
-                      sbase + offPart[i], Y, (bj[i].m + pchunk - 1) / pchunk, 0};
+                      sbase + offPart[i], Y, (bj[i].m + pchunk - 1) / pchunk, 0,
+                      nullptr, 0, 0, 0};
+    if (bf16) {
+      sk[i].planes = sbase + offPl[i];
+      sk[i].prow = 8 * mt[i];
+      sk[i].ldk = 2 * ((bj[i].m + 15) / 16 * 16);
+      sk[i].pstride = sk[i].prow * sk[i].ldk;
+    }
     op[i] = OpJob{bj[i].l, bj[i].m, bj[i].m, bj[i].seed, G, h->sketch_kind};
     qr[i] = PivJob{bj[i].l, bj[i].n, bj[i].k, bj[i].l, Y, bj[i].J, mark, dstatus + i, rank_tol,
                    nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -291,9 +307,10 @@ static hipError_t run_batch_impl(rid_handle h, hipStream_t stream, rid_dtype dty
     // sits before the sketch tables: a negative offset from d_tsk)
     const int64_t red_off = (static_cast<int64_t>(o_tred) - static_cast<int64_t>(o_tsk0)) /
                             static_cast<int64_t>(sizeof(int4));
+    // the bf16 planes are split over the operator's table (job, block, blocks)
     e = launch_sketch_batch(st, dtype, prec, d_sk, d_tsk, mts.data(), skoff.data(), skcnt.data(),
                             static_cast<int>(nbuck), red_off, static_cast<int64_t>(t_red.size()),
-                            prof);
+                            d_top, static_cast<int64_t>(t_op.size()), prof);
     if (e != hipSuccess) return e;
     e = qmode ? launch_pivqr_batch(st, qr_lmax.data(), qr_live.data(), kmax, d_qr, d_tqr,
                                    static_cast<int64_t>(t_qr.size()), prof, qmode)

@@ -452,6 +452,10 @@ struct SketchJob {
   double2 *Y;
   int64_t S;
   int64_t red_blocks;  // blocks of the reduce for this job
+  // bfloat16-split products only: the split planes of [Gr Gi] (bf16, plane
+  // s at s * pstride, entry (i, kappa) at i * ldk + kappa, prow x ldk each)
+  void *planes;
+  int64_t ldk, pstride, prow;
 };
 
 // One interpolation of a batch: R (k x n, ldr), J (k), P (k x n, ldp), and
@@ -538,10 +542,24 @@ hipError_t launch_sketch(hipStream_t st, rid_dtype dtype, rid_prec prec, int64_t
 
 // Grouped sketch over a batch: for each MT bucket the (job, bx, split)
 // table slice, then the grouped reduce over (job, block, blocks-of-job).
+// The bfloat16-split products first split each job's G into its planes, one
+// workgroup per (job, block, blocks-of-job) entry of dsplit (split_cnt
+// entries), and take 128 columns per bx instead of 64.
 hipError_t launch_sketch_batch(hipStream_t st, rid_dtype dtype, rid_prec prec,
                                const SketchJob *djobs, const int4 *dtab, const int *mts,
                                const int64_t *off, const int64_t *cnt, int nbuckets,
-                               int64_t red_off, int64_t red_cnt, RidProf *prof);
+                               int64_t red_off, int64_t red_cnt, const int4 *dsplit,
+                               int64_t split_cnt, RidProf *prof);
+hipError_t launch_sketch_batch_bf16(hipStream_t st, rid_dtype dtype, int terms,
+                                    const SketchJob *djobs, const int4 *dtab, const int *mts,
+                                    const int64_t *off, const int64_t *cnt, int nbuckets,
+                                    int64_t red_off, int64_t red_cnt, const int4 *dsplit,
+                                    int64_t split_cnt, RidProf *prof);
+// Columns of A per sketch workgroup of a batch job (64, or 128 for the
+// bfloat16-split products).
+inline int64_t sketch_batch_cols(rid_prec prec) {
+  return prec == RID_BF16X2 || prec == RID_BF16X3 ? 128 : 64;
+}
 int sketch_pick_mt(int64_t l);  // tiles per block for one batch job (0: unsupported)
 
 bool batch_job_supported(const RidBatchJob &j);

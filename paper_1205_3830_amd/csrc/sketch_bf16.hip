@@ -57,15 +57,13 @@ RID_DEV void split_terms(double v, __bf16 (&t)[NT]) {
 // bf16 term s of [Gr Gi](i, kappa) -- Re G(i, kappa/2) for even,
 // Im G(i, kappa/2) for odd kappa -- for i < rows_pad, kappa < ldk (zero
 // outside l x 2m).  One thread per complex entry (i, p).
+// Entries first, first + stride, ... of the rows_pad x mpad grid.
 template <int NT>
-__global__ __launch_bounds__(256) void bf16_split_kernel(int64_t l, int64_t m, int64_t rows_pad,
-                                                         int64_t mpad,
-                                                         const double2 *__restrict__ G,
-                                                         int64_t ldg, __bf16 *__restrict__ Gs,
-                                                         int64_t ldk, int64_t pstride) {
+RID_DEV void split_planes(int64_t l, int64_t m, int64_t rows_pad, int64_t mpad,
+                          const double2 *__restrict__ G, int64_t ldg, __bf16 *__restrict__ Gs,
+                          int64_t ldk, int64_t pstride, int64_t first, int64_t stride) {
   const int64_t total = rows_pad * mpad;
-  for (int64_t e = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; e < total;
-       e += int64_t(gridDim.x) * blockDim.x) {
+  for (int64_t e = first; e < total; e += stride) {
     const int64_t i = e / mpad;
     const int64_t p = e - i * mpad;
     const double2 g = (i < l && p < m) ? G[i * ldg + p] : make_double2(0.0, 0.0);
@@ -81,13 +79,43 @@ __global__ __launch_bounds__(256) void bf16_split_kernel(int64_t l, int64_t m, i
   }
 }
 
+template <int NT>
+__global__ __launch_bounds__(256) void bf16_split_kernel(int64_t l, int64_t m, int64_t rows_pad,
+                                                         int64_t mpad,
+                                                         const double2 *__restrict__ G,
+                                                         int64_t ldg, __bf16 *__restrict__ Gs,
+                                                         int64_t ldk, int64_t pstride) {
+  split_planes<NT>(l, m, rows_pad, mpad, G, ldg, Gs, ldk, pstride,
+                   blockIdx.x * int64_t(blockDim.x) + threadIdx.x,
+                   int64_t(gridDim.x) * blockDim.x);
+}
+
+// A batch: workgroup b takes entry (job, block, blocks-of-job) of tab.
+template <int NT>
+__global__ __launch_bounds__(256) void bf16_split_grouped(const SketchJob *__restrict__ jobs,
+                                                          const int4 *__restrict__ tab) {
+  const int4 e = tab[blockIdx.x];
+  const SketchJob &j = jobs[e.x];
+  split_planes<NT>(j.l, j.m, j.prow, j.ldk / 2, j.G, j.ldg, static_cast<__bf16 *>(j.planes),
+                   j.ldk, j.pstride, int64_t(e.y) * 256 + threadIdx.x, int64_t(e.z) * 256);
+}
+
 // The lane's four entries of A in their stored type (converted later, by
 // to_floats: converting right after the load would make the wave wait for
 // the load there, serialising the prefetch with the step's products).
-template <class TA>
+// WHOLE: a lane whose four entries are all in range loads them without
+// per-entry guards (wide loads, no branch per entry).  Measured at 131072 x
+// 16384, l = 108: the two-term sketch 7.9 -> 6.4 ms with it, the three-term
+// one 10.7 -> 12.3 ms, so only the two-term kernel takes it.
+template <class TA, bool WHOLE>
 RID_DEV void load_a(const TA *Acol, int64_t pb, int64_t pend, bool ok, TA (&v)[4]) {
+  if (WHOLE && ok && pb + 4 <= pend) {
 #pragma unroll
-  for (int u = 0; u < 4; ++u) v[u] = (ok && pb + u < pend) ? Acol[pb + u] : zero_of<TA>();
+    for (int u = 0; u < 4; ++u) v[u] = Acol[pb + u];
+  } else {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = (ok && pb + u < pend) ? Acol[pb + u] : zero_of<TA>();
+  }
 }
 
 template <class TA>
@@ -190,7 +218,7 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
   store_slab(0);
 #pragma unroll
   for (int g = 0; g < 2; ++g) {
-    load_a(Acol[g], pbeg + 4 * q, pend, ok[g], an[g]);
+    load_a<TA, NT == 2>(Acol[g], pbeg + 4 * q, pend, ok[g], an[g]);
     to_floats(an[g], av[g]);
   }
   // nothing may be pending into av when the loop starts (it would make every
@@ -203,7 +231,7 @@ RID_DEV void sketch_bf16_body(int64_t m, int64_t n, int64_t l, const TA *__restr
     if (more) {
       load_slab(p0 + 16);
 #pragma unroll
-      for (int g = 0; g < 2; ++g) load_a(Acol[g], p0 + 16 + 4 * q, pend, ok[g], an[g]);
+      for (int g = 0; g < 2; ++g) load_a<TA, NT == 2>(Acol[g], p0 + 16 + 4 * q, pend, ok[g], an[g]);
     }
     // B operand: k-index 2p (e = 0) carries [Re a, Im a] for parts c = 0, 1;
     // k-index 2p+1 carries [-Im a, Re a]; then its NT bf16 terms
@@ -287,6 +315,35 @@ __global__ __launch_bounds__(512) void sketch_bf16_kernel(
     int64_t ldo, int64_t split_stride, int64_t pchunk) {
   sketch_bf16_body<RT, TA, NT>(m, n, l, A, lda, Gs, ldk, pstride, out, ldo, split_stride,
                                pchunk, blockIdx.x, blockIdx.y, blockIdx.z);
+}
+
+// A batch: workgroup b takes entry (job, bx, split) of tab; the job's planes
+// have 16 RT rows.
+template <int RT, class TA, int NT>
+__global__ __launch_bounds__(512) void sketch_bf16_kernel_grouped(
+    const SketchJob *__restrict__ jobs, const int4 *__restrict__ tab) {
+  const int4 e = tab[blockIdx.x];
+  const SketchJob &j = jobs[e.x];
+  sketch_bf16_body<RT, TA, NT>(j.m, j.n, j.l, static_cast<const TA *>(j.A), j.lda,
+                               static_cast<const __bf16 *>(j.planes), j.ldk, j.pstride,
+                               static_cast<float *>(j.part), 2 * j.l, 2 * j.l * j.n, j.pchunk,
+                               e.y, e.z, 0);
+}
+
+// A batch: Y = the sum over the job's splits (in order, in double) of its
+// partials; workgroup b takes entry (job, block, blocks-of-job) of tab.
+__global__ __launch_bounds__(256) void bf16_reduce_grouped(const SketchJob *__restrict__ jobs,
+                                                           const int4 *__restrict__ tab) {
+  const int4 en = tab[blockIdx.x];
+  const SketchJob &jb = jobs[en.x];
+  const int64_t total = 2 * jb.l * jb.n;
+  const float *part = static_cast<const float *>(jb.part);
+  double *Y = reinterpret_cast<double *>(jb.Y);
+  for (int64_t e = int64_t(en.y) * 256 + threadIdx.x; e < total; e += int64_t(en.z) * 256) {
+    double s = 0.0;
+    for (int64_t sp = 0; sp < jb.S; ++sp) s += static_cast<double>(part[sp * total + e]);
+    Y[e] = s;
+  }
 }
 
 // Y(mu, j) = sum over splits (in order, in double) of part[s](mu, j).
@@ -409,6 +466,66 @@ hipError_t launch_sketch_bf16(hipStream_t st, int terms, int64_t m, int64_t n, i
     return launch_bf16_terms<TA, 2>(st, m, n, l, A, lda, G, ldg, Y, ldy, ws, prof);
   if (terms == 3)
     return launch_bf16_terms<TA, 3>(st, m, n, l, A, lda, G, ldg, Y, ldy, ws, prof);
+  return hipErrorInvalidValue;
+}
+
+namespace {
+
+template <int NT>
+hipError_t launch_batch_terms(hipStream_t st, rid_dtype dtype, const SketchJob *djobs,
+                              const int4 *dtab, const int *mts, const int64_t *off,
+                              const int64_t *cnt, int nbuckets, int64_t red_off, int64_t red_cnt,
+                              const int4 *dsplit, int64_t split_cnt, RidProf *prof) {
+  if (split_cnt > 0)
+    hipLaunchKernelGGL((bf16_split_grouped<NT>), dim3(static_cast<unsigned>(split_cnt)),
+                       dim3(256), 0, st, djobs, dsplit);
+  ProfScope ps(prof, st, RID_KERNEL_SKETCH);
+  for (int b = 0; b < nbuckets; ++b) {
+    if (cnt[b] == 0) continue;
+    const dim3 grid(static_cast<unsigned>(cnt[b]));
+    const int4 *tb = dtab + off[b];
+    // mts[b] counts 16-row tiles of 2l real rows (the bucket key shared by
+    // the batch kernels); (mts[b] + 1) / 2 row tiles of Y cover every job of
+    // the bucket, and its planes have that many
+    switch ((mts[b] + 1) / 2) {
+#define RID_BF_CASE(X)                                                                      \
+  case X:                                                                                   \
+    if (dtype == RID_C64)                                                                   \
+      hipLaunchKernelGGL((sketch_bf16_kernel_grouped<X, float2, NT>), grid, dim3(512), 0, st, \
+                         djobs, tb);                                                        \
+    else                                                                                    \
+      hipLaunchKernelGGL((sketch_bf16_kernel_grouped<X, double2, NT>), grid, dim3(512), 0,  \
+                         st, djobs, tb);                                                    \
+    break;
+      RID_BF_CASE(1) RID_BF_CASE(2) RID_BF_CASE(3) RID_BF_CASE(4) RID_BF_CASE(5)
+      RID_BF_CASE(6) RID_BF_CASE(7) RID_BF_CASE(8) RID_BF_CASE(9) RID_BF_CASE(10)
+      RID_BF_CASE(11) RID_BF_CASE(12) RID_BF_CASE(13) RID_BF_CASE(14)
+#undef RID_BF_CASE
+      default:
+        return hipErrorInvalidValue;
+    }
+  }
+  ps.stop();
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || red_cnt == 0) return e;
+  hipLaunchKernelGGL(bf16_reduce_grouped, dim3(static_cast<unsigned>(red_cnt)), dim3(256), 0, st,
+                     djobs, dtab + red_off);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_sketch_batch_bf16(hipStream_t st, rid_dtype dtype, int terms,
+                                    const SketchJob *djobs, const int4 *dtab, const int *mts,
+                                    const int64_t *off, const int64_t *cnt, int nbuckets,
+                                    int64_t red_off, int64_t red_cnt, const int4 *dsplit,
+                                    int64_t split_cnt, RidProf *prof) {
+  if (terms == 2)
+    return launch_batch_terms<2>(st, dtype, djobs, dtab, mts, off, cnt, nbuckets, red_off,
+                                 red_cnt, dsplit, split_cnt, prof);
+  if (terms == 3)
+    return launch_batch_terms<3>(st, dtype, djobs, dtab, mts, off, cnt, nbuckets, red_off,
+                                 red_cnt, dsplit, split_cnt, prof);
   return hipErrorInvalidValue;
 }
 

@@ -332,7 +332,11 @@ hipError_t launch_sketch_batch_f64(hipStream_t st, rid_dtype dtype, const Sketch
 hipError_t launch_sketch_batch(hipStream_t st, rid_dtype dtype, rid_prec prec,
                                const SketchJob *djobs, const int4 *dtab, const int *mts,
                                const int64_t *off, const int64_t *cnt, int nbuckets,
-                               int64_t red_off, int64_t red_cnt, RidProf *prof) {
+                               int64_t red_off, int64_t red_cnt, const int4 *dsplit,
+                               int64_t split_cnt, RidProf *prof) {
+  if (prec == RID_BF16X2 || prec == RID_BF16X3)
+    return launch_sketch_batch_bf16(st, dtype, prec == RID_BF16X2 ? 2 : 3, djobs, dtab, mts, off,
+                                    cnt, nbuckets, red_off, red_cnt, dsplit, split_cnt, prof);
   if (prec == RID_FP32)
     return launch_sketch_batch_f32(st, dtype, djobs, dtab, mts, off, cnt, nbuckets, red_off,
                                    red_cnt, prof);

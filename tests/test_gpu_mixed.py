@@ -247,12 +247,41 @@ def test_decompose_complex64_fp64_matches_double_oracle(h):
     check_decompose(A.astype(np.complex128), ref["Y"], J, P, s, 0, 8, ref=ref)
 
 
+# uneven jobs over several row-tile buckets (l = 14 .. 200: 1 .. 13 row tiles
+# of Y), ragged 128-column blocks and ragged K splits (m not a multiple of
+# the 1024-row split or of 16)
+BF16_BATCH = [(1500, 300, 20, 28), (700, 130, 6, 14), (2100, 257, 40, 48), (300, 129, 60, 72),
+              (1030, 520, 100, 108), (900, 300, 190, 200)]
+
+
+@pytest.mark.parametrize("dt", [np.complex64, np.complex128])
 @pytest.mark.parametrize("prec", ["RID_BF16X2", "RID_BF16X3"])
-def test_bf16_batches_are_reported_unsupported(h, prec):
-    A = dev(lowrank64(100, 40, 4, 1e-3, seed=1))
-    with pytest.raises(rid.RidError) as ei:
-        rid.rid_decompose_batched(h, [A], [4], [8], [0], q=2, prec=getattr(rid, prec))
-    assert ei.value.status == rid.RID_ERR_UNSUPPORTED
+def test_bf16_batches_match_the_oracle(h, prec, dt):
+    # each job's J at every step, P entry by entry on the GPU's pivots and
+    # sigma, to the form's bars; and each job bitwise as when batched alone
+    # (a job's plan depends on the job only)
+    tau, ptol, rank_tol = FORM_BARS[prec]
+    p = getattr(rid, prec)
+    As = [lowrank64(m, n, k, 1e-3, seed=11 + i).astype(dt) for i, (m, n, k, l) in
+          enumerate(BF16_BATCH)]
+    Ad = [dev(A) for A in As]
+    ks, ls = [s[2] for s in BF16_BATCH], [s[3] for s in BF16_BATCH]
+    seeds = [3 + i for i in range(len(BF16_BATCH))]
+    Js, Ps, sig, status, used = rid.rid_decompose_batched(h, Ad, ks, ls, seeds, q=6, prec=p,
+                                                          rank_tol=rank_tol)
+    assert status == [0] * len(BF16_BATCH)
+    for i, (m, n, k, l) in enumerate(BF16_BATCH):
+        A128 = As[i].astype(np.complex128)
+        ref = oracle.decompose(A128, k, l, seed=seeds[i], q=6)
+        assert used[i] == ref["seed_used"]
+        Jb, Pb, sb = host(Js[i]), host(Ps[i]), float(host(sig[i])[0])
+        check_decompose(A128, ref["Y"], Jb, Pb, sb, used[i], 6, tau=tau, ptol=ptol, ref=ref,
+                        sigma_factor=2.0)
+    for i in (1, 5):
+        J1, P1, s1, _, _ = rid.rid_decompose_batched(h, [Ad[i]], [ks[i]], [ls[i]], [seeds[i]],
+                                                     q=6, prec=p, rank_tol=rank_tol)
+        assert torch.equal(J1[0], Js[i]) and torch.equal(P1[0], Ps[i])
+        assert torch.equal(s1[0], sig[i])
 
 
 def test_precision_codes_follow_the_abi():
