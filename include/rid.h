@@ -77,8 +77,7 @@ typedef enum { RID_C128 = 0, RID_C64 = 1 } rid_dtype;
  *   RID_BF16X3 each operand split into three bfloat16 terms, the six
  *              leading bf16 products per real product, single accumulation
  *              (FP32-level error).
- * The two bf16 forms are built for single IDs: batches take RID_FP64 or
- * RID_FP32 and return RID_ERR_UNSUPPORTED for them.                     */
+ * Single IDs and batches take all four.                                  */
 typedef enum { RID_FP64 = 0, RID_FP32 = 1, RID_BF16X2 = 2, RID_BF16X3 = 3 } rid_prec;
 
 /* ---------------------------------------------------------------- handle */
